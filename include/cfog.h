@@ -1,0 +1,163 @@
+/*
+ * cfog.h - C-ABI of libcfog: CFOG extraction and SSD template matching by
+ * 3-D FFT on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Ye, Bruzzone, Shan, Bovolo, Zhu, "Fast and Robust Matching for
+ * Multimodal Remote Sensing Image Registration".
+ *   - cfog_extract: the pixel-wise CFOG feature representation (Section III-F:
+ *     oriented gradient channels of Eq. 2 smoothed by a 2-D Gaussian in X/Y
+ *     and a [1,2,1] kernel along the orientation axis), plus an FP64
+ *     summed-area table of the per-pixel energy sum_k D_k^2 (the energy terms
+ *     of Eq. 5).
+ *   - match_batch: for every control point, the SSD similarity of Eq. 3 over a
+ *     search window, evaluated as Eq. 5 with the correlation term by FFT
+ *     (Eqs. 8-9), and the matching function of Eq. 4 (argmin).
+ *
+ * Conventions (apply to every entry point):
+ *   - All image, volume, table, control-point and result buffers are DEVICE
+ *     pointers owned by the caller; the library never frees them.  Job arrays
+ *     (cfog_job) are HOST arrays.  `stream` is a hipStream_t passed as void*
+ *     (NULL = the null stream).
+ *   - Calls are stream-ordered and asynchronous: a return of CFOG_OK means the
+ *     work was validated and enqueued.  Faults during execution surface at the
+ *     caller's next synchronisation of that stream; cfog_ctx_last_error()
+ *     reports the last HIP error the library saw.
+ *   - Errors are negative return codes (never abort, never C++ exceptions).
+ *   - A cfog_ctx is not thread-safe: use one per host thread.
+ *   - Axes: x = column, y = row.  Layouts are row-major.
+ */
+#ifndef CFOG_H_
+#define CFOG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define CFOG_OK 0
+#define CFOG_EINVAL (-1)       /* invalid argument (null pointer, bad size, ...) */
+#define CFOG_EUNSUPPORTED (-2) /* valid but not supported (e.g. window too large) */
+#define CFOG_ENOMEM (-3)       /* workspace too small / allocation failed */
+#define CFOG_EHIP (-4)         /* HIP runtime error at launch */
+
+/* per-control-point status in cfog_result.status */
+#define CFOG_CP_OK 0
+#define CFOG_CP_OUT_OF_BOUNDS 1 /* template leaves A or search window leaves B */
+#define CFOG_CP_NONFINITE 2     /* a similarity value was NaN or infinite */
+
+/* match_batch flags: exactly one path */
+#define CFOG_PATH_PLAIN_FFT 0x1   /* one FFT launch per job, one workgroup per CP */
+#define CFOG_PATH_BATCHED_FFT 0x2 /* all jobs' CPs fused into persistent launches per FFT size */
+#define CFOG_PATH_MFMA_BF16 0x4   /* direct correlation as BF16 MFMA GEMMs (FP32 accumulate) */
+
+typedef struct cfog_ctx cfog_ctx;
+
+/* Create a context bound to HIP device `device` (it becomes current).
+ * Returns CFOG_OK and *out, or CFOG_EINVAL / CFOG_EHIP. */
+int cfog_ctx_create(int device, cfog_ctx** out);
+
+/* Destroy a context; NULL is accepted.  Frees only what the context owns. */
+int cfog_ctx_destroy(cfog_ctx* ctx);
+
+/* Last HIP error code (hipError_t as int) recorded by the context, 0 if none;
+ * reading it clears it. */
+int cfog_ctx_last_error(cfog_ctx* ctx);
+
+/* Static description of a status code (never NULL). */
+const char* cfog_status_str(int status);
+
+/*
+ * cfog_extract - CFOG volume of one image (Section III-F, Eq. 2).
+ *
+ *   d_img       [H][row_stride] fp32 image (row_stride >= W, in elements).
+ *   m           number of orientation channels, 1..16 (paper default 9);
+ *               theta_k = k*pi/m, k = 0..m-1.
+ *   sigma       Gaussian std in pixels (paper default 0.8), > 0.
+ *   gauss_radius taps each side, 0..8; -1 selects int(4*sigma + 0.5).
+ *   d_vol       output [m][H][W] fp32, planar (plane stride H*W).
+ *   d_sat       nullable output [(H+1)][(W+1)] fp64 summed-area table of
+ *               Q = sum_k D_k^2 computed from the fp32 volume values:
+ *               SAT(y, x) = sum_{y'<y, x'<x} Q(y', x'); row 0 and column 0 are 0.
+ *   Borders are replicated (clamp-to-edge) for the gradient and the Gaussian;
+ *   gx, gy are central differences by [-1, 0, 1] without a 1/2 factor.
+ *   Returns CFOG_EINVAL for null pointers, H or W < 1, m out of range, bad
+ *   sigma/radius; CFOG_EUNSUPPORTED if the tile does not fit on chip.
+ */
+int cfog_extract(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride,
+                 int32_t m, float sigma, int32_t gauss_radius, float* d_vol, double* d_sat, void* stream);
+
+/* One control point: template centre (x, y) in A; search centre (bx, by) in B
+ * (a georeferenced prediction; bx = x, by = y when A and B are co-registered). */
+typedef struct {
+  int32_t x, y, bx, by;
+} cfog_cp;
+
+/* One result (24 bytes).  (dx, dy): A's template at (x, y) best matches B's
+ * window centred at (bx + dx, by + dy) (this is -v of Eq. 3).  ssd_best is the
+ * minimum SSD (Eq. 3), ssd_second the smallest SSD over all other offsets
+ * (+inf when r = 0).
+ * Ties go to the smallest row-major index (dy first, then dx).  For a status
+ * other than CFOG_CP_OK: dx = dy = 0 and both SSDs are NaN. */
+typedef struct {
+  int32_t dx, dy;
+  float ssd_best, ssd_second;
+  int32_t status, pad;
+} cfog_result;
+
+/* One matching job: a pair of CFOG volumes (from cfog_extract, with SATs) and
+ * a list of control points sharing template side N and search radius r.
+ *   Template of CP p: rows [y - N/2, y - N/2 + N), cols [x - N/2, x - N/2 + N) of A.
+ *   Offsets d = (dx, dy) in [-r, r]^2, i.e. (2r+1)^2 candidates.
+ *   cps      device array of n_cps cfog_cp (16-byte aligned).
+ *   out      device array of n_cps cfog_result.
+ *   surfaces nullable device array [n_cps][2r+1][2r+1] fp32 of SSD(d),
+ *            index [dy + r][dx + r]; NaN for points that are not CFOG_CP_OK. */
+typedef struct {
+  const float* volA;
+  const double* satA;
+  int32_t hA, wA;
+  const float* volB;
+  const double* satB;
+  int32_t hB, wB;
+  const cfog_cp* cps;
+  int32_t n_cps;
+  int32_t N, r;
+  int32_t pad_;
+  cfog_result* out;
+  float* surfaces;
+} cfog_job;
+
+/* Device workspace (bytes) match_batch needs for these jobs and flags; 0 for
+ * the plain path.  Returns (size_t)-1 for invalid jobs. */
+size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m,
+                                  int32_t flags);
+
+/*
+ * match_batch - SSD template matching of every control point of every job
+ * (Eqs. 3-6, 8-9; Eq. 4 argmin).  Volumes have m channels (1..16).
+ *   jobs        host array of n_jobs jobs (n_jobs >= 0).
+ *   flags       one CFOG_PATH_* value.
+ *   d_ws        device workspace of ws_bytes >= match_batch_workspace_size(); may be
+ *               NULL when that size is 0.  It must stay untouched until the work
+ *               completes on `stream`.
+ *   Returns CFOG_EINVAL for invalid jobs, CFOG_EUNSUPPORTED when 2r+1 or
+ *   N + 2r exceeds what the chosen path supports, CFOG_ENOMEM when the
+ *   workspace is too small.  Per-point failures are reported in out[].status.
+ */
+int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags, void* d_ws,
+                size_t ws_bytes, void* stream);
+
+/* Largest N + 2r the FFT paths support. */
+int32_t cfog_max_window(void);
+
+/* FFT side P the FFT paths use for template side N and radius r (P >= N + 2r),
+ * or 0 if unsupported. */
+int32_t cfog_fft_size(int32_t N, int32_t r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFOG_H_ */

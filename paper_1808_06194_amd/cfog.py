@@ -1,0 +1,228 @@
+"""Python binding of libcfog (ctypes).  Argument marshalling only: every step
+of extraction and matching runs in the library's HIP kernels.  PyTorch is used
+for device memory and streams.
+
+    import torch
+    from paper_1808_06194_amd import cfog
+    vol, sat = cfog.cfog_extract(img)                      # img: cuda fp32 (H, W)
+    res = cfog.match_batch([cfog.Job(volA, satA, volB, satB, cps, N=48, r=10)])
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcfog.so")
+
+CFOG_OK = 0
+CFOG_EINVAL = -1
+CFOG_EUNSUPPORTED = -2
+CFOG_ENOMEM = -3
+CFOG_EHIP = -4
+
+CP_OK, CP_OUT_OF_BOUNDS, CP_NONFINITE = 0, 1, 2
+
+PATH_PLAIN_FFT = 0x1
+PATH_BATCHED_FFT = 0x2
+PATH_MFMA_BF16 = 0x4
+
+# Exported symbols, as declared in include/cfog.h.
+EXPORTS = (
+    "cfog_ctx_create", "cfog_ctx_destroy", "cfog_ctx_last_error", "cfog_status_str",
+    "cfog_extract", "match_batch_workspace_size", "match_batch", "cfog_max_window", "cfog_fft_size",
+)
+
+
+class CfogError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {status_str(code)} ({code})")
+        self.code = code
+
+
+class cfog_job(ctypes.Structure):
+    _fields_ = [
+        ("volA", ctypes.c_void_p), ("satA", ctypes.c_void_p), ("hA", ctypes.c_int32), ("wA", ctypes.c_int32),
+        ("volB", ctypes.c_void_p), ("satB", ctypes.c_void_p), ("hB", ctypes.c_int32), ("wB", ctypes.c_int32),
+        ("cps", ctypes.c_void_p), ("n_cps", ctypes.c_int32), ("N", ctypes.c_int32), ("r", ctypes.c_int32),
+        ("pad_", ctypes.c_int32), ("out", ctypes.c_void_p), ("surfaces", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libcfog.so (built in-tree by paper_1808_06194_amd.build).  Raises
+    if it is missing: there is no fallback implementation."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing; build it with `python -m paper_1808_06194_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.cfog_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    lib.cfog_ctx_destroy.argtypes = [vp]
+    lib.cfog_ctx_last_error.argtypes = [vp]
+    lib.cfog_status_str.argtypes = [ctypes.c_int]
+    lib.cfog_status_str.restype = ctypes.c_char_p
+    lib.cfog_extract.argtypes = [vp, vp, i32, i32, i64, i32, ctypes.c_float, i32, vp, vp, vp]
+    lib.match_batch_workspace_size.argtypes = [vp, ctypes.POINTER(cfog_job), i32, i32, i32]
+    lib.match_batch_workspace_size.restype = sz
+    lib.match_batch.argtypes = [vp, ctypes.POINTER(cfog_job), i32, i32, i32, vp, sz, vp]
+    lib.cfog_max_window.restype = i32
+    lib.cfog_fft_size.argtypes = [i32, i32]
+    lib.cfog_fft_size.restype = i32
+    _lib = lib
+    return lib
+
+
+def status_str(code: int) -> str:
+    return load().cfog_status_str(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != CFOG_OK:
+        raise CfogError(code, what)
+
+
+class Context:
+    """A libcfog context bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.cfog_ctx_create(int(device), ctypes.byref(h)), "cfog_ctx_create")
+        self.handle = h
+        self.device = device
+        self._ws = None
+
+    def close(self):
+        if self.handle:
+            load().cfog_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> int:
+        return load().cfog_ctx_last_error(self.handle)
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        """Context-cached device workspace of at least nbytes."""
+        if nbytes <= 0:
+            return None
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+
+_ctx: dict = {}
+
+
+def context(device: Optional[int] = None) -> Context:
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _ctx:
+        _ctx[dev] = Context(dev)
+    return _ctx[dev]
+
+
+def _stream_ptr(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def cfog_extract(img: torch.Tensor, m: int = 9, sigma: float = 0.8, radius: int = -1, with_sat: bool = True,
+                 vol: Optional[torch.Tensor] = None, sat: Optional[torch.Tensor] = None, stream=None):
+    """CFOG volume (m, H, W) fp32 and FP64 SAT (H+1, W+1) of a 2-D cuda fp32 image."""
+    if img.dim() != 2 or img.dtype != torch.float32 or not img.is_cuda or img.stride(1) != 1:
+        raise ValueError("img must be a 2-D row-contiguous cuda float32 tensor")
+    H, W = img.shape
+    if vol is None:
+        vol = torch.empty((m, H, W), dtype=torch.float32, device=img.device)
+    if with_sat and sat is None:
+        sat = torch.empty((H + 1, W + 1), dtype=torch.float64, device=img.device)
+    ctx = context(img.device.index)
+    rc = load().cfog_extract(ctx.handle, img.data_ptr(), H, W, img.stride(0), m, float(sigma), int(radius),
+                             vol.data_ptr(), _ptr(sat) if with_sat else None, _stream_ptr(stream))
+    _check(rc, "cfog_extract")
+    return vol, (sat if with_sat else None)
+
+
+@dataclasses.dataclass
+class Job:
+    """One matching job: volumes + SATs of A and B, control points (n, 4) int32
+    cuda tensor of (x, y, bx, by), template side N, search radius r."""
+    volA: torch.Tensor
+    satA: torch.Tensor
+    volB: torch.Tensor
+    satB: torch.Tensor
+    cps: torch.Tensor
+    N: int
+    r: int
+    out: Optional[torch.Tensor] = None        # (n, 6) int32 view of cfog_result
+    surfaces: Optional[torch.Tensor] = None   # (n, 2r+1, 2r+1) fp32
+
+    def to_c(self) -> cfog_job:
+        n = int(self.cps.shape[0])
+        if self.out is None:
+            self.out = torch.empty((n, 6), dtype=torch.int32, device=self.cps.device)
+        return cfog_job(
+            self.volA.data_ptr(), self.satA.data_ptr(), self.volA.shape[1], self.volA.shape[2],
+            self.volB.data_ptr(), self.satB.data_ptr(), self.volB.shape[1], self.volB.shape[2],
+            self.cps.data_ptr() if n else None, n, int(self.N), int(self.r), 0,
+            self.out.data_ptr(), _ptr(self.surfaces))
+
+
+def results(out: torch.Tensor) -> dict:
+    """Split an (n, 6) int32 result tensor into named fields (on its device)."""
+    return dict(dx=out[:, 0], dy=out[:, 1], best=out[:, 2].view(torch.float32),
+                second=out[:, 3].view(torch.float32), status=out[:, 4])
+
+
+def make_jobs_array(jobs: List[Job]):
+    arr = (cfog_job * max(1, len(jobs)))()
+    for i, j in enumerate(jobs):
+        arr[i] = j.to_c()
+    return arr
+
+
+def match_batch(jobs: List[Job], m: int = 9, flags: int = PATH_PLAIN_FFT, stream=None,
+                workspace: Optional[torch.Tensor] = None) -> List[torch.Tensor]:
+    """Match every control point of every job; returns the (n, 6) int32 result
+    tensors (see `results`).  Asynchronous on `stream`."""
+    if not jobs:
+        return []
+    dev = jobs[0].cps.device.index
+    ctx = context(dev)
+    arr = make_jobs_array(jobs)
+    lib = load()
+    need = lib.match_batch_workspace_size(ctx.handle, arr, len(jobs), m, flags)
+    if need == ctypes.c_size_t(-1).value:
+        raise CfogError(CFOG_EINVAL, "match_batch_workspace_size")
+    ws = workspace if workspace is not None else ctx.workspace(need)
+    rc = lib.match_batch(ctx.handle, arr, len(jobs), m, flags, _ptr(ws) if need else None,
+                         ws.numel() if (need and ws is not None) else 0, _stream_ptr(stream))
+    _check(rc, "match_batch")
+    return [j.out for j in jobs]
+
+
+def max_window() -> int:
+    return int(load().cfog_max_window())
+
+
+def fft_size(N: int, r: int) -> int:
+    """FFT side P used for template side N and radius r (0 if unsupported)."""
+    return int(load().cfog_fft_size(int(N), int(r)))
