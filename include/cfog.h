@@ -81,13 +81,23 @@ const char* cfog_status_str(int status);
  *   d_sat       nullable output [(H+1)][(W+1)] fp64 summed-area table of
  *               Q = sum_k D_k^2 computed from the fp32 volume values:
  *               SAT(y, x) = sum_{y'<y, x'<x} Q(y', x'); row 0 and column 0 are 0.
+ *   d_ws        device workspace of ws_bytes >= cfog_extract_workspace_size(H, W)
+ *               when d_sat is not NULL; it must stay untouched until the call's
+ *               work completes on `stream`.  NULL selects a workspace owned by
+ *               the context (calls on several streams must then not overlap).
  *   Borders are replicated (clamp-to-edge) for the gradient and the Gaussian;
  *   gx, gy are central differences by [-1, 0, 1] without a 1/2 factor.
  *   Returns CFOG_EINVAL for null pointers, H or W < 1, m out of range, bad
- *   sigma/radius; CFOG_EUNSUPPORTED if the tile does not fit on chip.
+ *   sigma/radius; CFOG_EUNSUPPORTED if the tile does not fit on chip;
+ *   CFOG_ENOMEM if ws_bytes is too small or the context workspace cannot grow.
  */
 int cfog_extract(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride,
-                 int32_t m, float sigma, int32_t gauss_radius, float* d_vol, double* d_sat, void* stream);
+                 int32_t m, float sigma, int32_t gauss_radius, float* d_vol, double* d_sat,
+                 void* d_ws, size_t ws_bytes, void* stream);
+
+/* Device workspace (bytes) cfog_extract needs to build the SAT of an H x W
+ * image: 8 * (H * ceil(W/64) + ceil(H/16) * W). */
+size_t cfog_extract_workspace_size(int32_t H, int32_t W);
 
 /* One control point: template centre (x, y) in A; search centre (bx, by) in B
  * (a georeferenced prediction; bx = x, by = y when A and B are co-registered). */

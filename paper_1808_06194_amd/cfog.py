@@ -34,7 +34,8 @@ PATH_MFMA_BF16 = 0x4
 # Exported symbols, as declared in include/cfog.h.
 EXPORTS = (
     "cfog_ctx_create", "cfog_ctx_destroy", "cfog_ctx_last_error", "cfog_status_str",
-    "cfog_extract", "match_batch_workspace_size", "match_batch", "cfog_max_window", "cfog_fft_size",
+    "cfog_extract", "cfog_extract_workspace_size", "match_batch_workspace_size", "match_batch",
+    "cfog_max_window", "cfog_fft_size",
 )
 
 
@@ -71,7 +72,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cfog_ctx_last_error.argtypes = [vp]
     lib.cfog_status_str.argtypes = [ctypes.c_int]
     lib.cfog_status_str.restype = ctypes.c_char_p
-    lib.cfog_extract.argtypes = [vp, vp, i32, i32, i64, i32, ctypes.c_float, i32, vp, vp, vp]
+    lib.cfog_extract.argtypes = [vp, vp, i32, i32, i64, i32, ctypes.c_float, i32, vp, vp, vp, sz, vp]
+    lib.cfog_extract_workspace_size.argtypes = [i32, i32]
+    lib.cfog_extract_workspace_size.restype = sz
     lib.match_batch_workspace_size.argtypes = [vp, ctypes.POINTER(cfog_job), i32, i32, i32]
     lib.match_batch_workspace_size.restype = sz
     lib.match_batch.argtypes = [vp, ctypes.POINTER(cfog_job), i32, i32, i32, vp, sz, vp]
@@ -144,9 +147,16 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def extract_workspace_size(H: int, W: int) -> int:
+    return int(load().cfog_extract_workspace_size(int(H), int(W)))
+
+
 def cfog_extract(img: torch.Tensor, m: int = 9, sigma: float = 0.8, radius: int = -1, with_sat: bool = True,
-                 vol: Optional[torch.Tensor] = None, sat: Optional[torch.Tensor] = None, stream=None):
-    """CFOG volume (m, H, W) fp32 and FP64 SAT (H+1, W+1) of a 2-D cuda fp32 image."""
+                 vol: Optional[torch.Tensor] = None, sat: Optional[torch.Tensor] = None, stream=None,
+                 workspace: Optional[torch.Tensor] = None):
+    """CFOG volume (m, H, W) fp32 and FP64 SAT (H+1, W+1) of a 2-D cuda fp32 image.
+    `workspace` (uint8 cuda tensor of >= extract_workspace_size(H, W) bytes) is
+    needed only when extractions on several streams overlap."""
     if img.dim() != 2 or img.dtype != torch.float32 or not img.is_cuda or img.stride(1) != 1:
         raise ValueError("img must be a 2-D row-contiguous cuda float32 tensor")
     H, W = img.shape
@@ -156,7 +166,8 @@ def cfog_extract(img: torch.Tensor, m: int = 9, sigma: float = 0.8, radius: int 
         sat = torch.empty((H + 1, W + 1), dtype=torch.float64, device=img.device)
     ctx = context(img.device.index)
     rc = load().cfog_extract(ctx.handle, img.data_ptr(), H, W, img.stride(0), m, float(sigma), int(radius),
-                             vol.data_ptr(), _ptr(sat) if with_sat else None, _stream_ptr(stream))
+                             vol.data_ptr(), _ptr(sat) if with_sat else None, _ptr(workspace),
+                             workspace.numel() if workspace is not None else 0, _stream_ptr(stream))
     _check(rc, "cfog_extract")
     return vol, (sat if with_sat else None)
 

@@ -13,6 +13,11 @@ struct cfog_ctx {
   int device = 0;
   int last_error = 0;
   int num_cus = 0;
+  void* ext_ws = nullptr;  // context-owned extraction workspace
+  size_t ext_ws_bytes = 0;
+  void* stage = nullptr;   // pinned host staging for task tables
+  size_t stage_bytes = 0;
+  hipEvent_t stage_done = nullptr;  // recorded after the last copy out of `stage`
 };
 
 namespace {
@@ -51,11 +56,61 @@ cfog::MatchJob to_device_job(const cfog_job& j, int m) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Batched path workspace: [MatchJob x n_jobs][int2 x total CPs]
-size_t batched_ws_bytes(const cfog_job* jobs, int n_jobs) {
-  size_t n = 0;
-  for (int i = 0; i < n_jobs; ++i) n += (size_t)std::max(0, jobs[i].n_cps);
-  return align_up(sizeof(cfog::MatchJob) * (size_t)n_jobs, 256) + sizeof(int2) * n;
+// Workspace of match_batch: [template-spectrum buffers of the large-P plans]
+// [batched path: MatchJob x n_jobs | int2 x total CPs]
+struct WsLayout {
+  size_t tg = 0;       // bytes of the template-spectrum region
+  size_t jobs_off = 0, tasks_off = 0, total = 0;
+};
+
+WsLayout ws_layout(cfog_ctx* ctx, const cfog_job* jobs, int n_jobs, int flags,
+                   const std::vector<const cfog::FftPlan*>& plans) {
+  WsLayout L;
+  size_t ncp = 0;
+  for (int i = 0; i < n_jobs; ++i) {
+    ncp += (size_t)std::max(0, jobs[i].n_cps);
+    const cfog::FftPlan* p = plans[i];
+    if (p && p->tg_bytes && jobs[i].n_cps > 0) {
+      // plain path: one launch per job; batched path: one per plan over all jobs
+      const int blocks = flags == CFOG_PATH_PLAIN_FFT ? std::min(jobs[i].n_cps, cfog::plan_slots(p, ctx->num_cus))
+                                                      : cfog::plan_slots(p, ctx->num_cus);
+      L.tg = std::max(L.tg, (size_t)blocks * p->tg_bytes);
+    }
+  }
+  L.tg = align_up(L.tg, 256);
+  L.total = L.tg;
+  if (flags == CFOG_PATH_BATCHED_FFT && ncp > 0) {
+    L.jobs_off = L.total;
+    L.tasks_off = align_up(L.jobs_off + sizeof(cfog::MatchJob) * (size_t)n_jobs, 256);
+    L.total = L.tasks_off + sizeof(int2) * ncp;
+  }
+  return L;
+}
+
+int ensure_stage(cfog_ctx* ctx, size_t bytes) {
+  if (!ctx->stage_done && hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming) != hipSuccess)
+    return record(ctx, hipGetLastError());
+  // wait until the previous copy out of the staging buffer has completed
+  if (hipEventSynchronize(ctx->stage_done) != hipSuccess) return record(ctx, hipGetLastError());
+  if (ctx->stage_bytes >= bytes) return CFOG_OK;
+  if (ctx->stage) (void)hipHostFree(ctx->stage);
+  ctx->stage = nullptr;
+  ctx->stage_bytes = 0;
+  const size_t nb = std::max<size_t>(bytes, 1 << 20);
+  if (hipHostMalloc(&ctx->stage, nb, hipHostMallocDefault) != hipSuccess) return CFOG_ENOMEM;
+  ctx->stage_bytes = nb;
+  return CFOG_OK;
+}
+
+int resolve_plans(const cfog_job* jobs, int n_jobs, int m, std::vector<const cfog::FftPlan*>& plans) {
+  plans.assign(n_jobs, nullptr);
+  for (int i = 0; i < n_jobs; ++i) {
+    int rc = validate_job(jobs[i], m);
+    if (rc != CFOG_OK) return rc;
+    plans[i] = cfog::choose_fft_plan(jobs[i].N, jobs[i].r);
+    if (!plans[i]) return CFOG_EUNSUPPORTED;
+  }
+  return CFOG_OK;
 }
 
 }  // namespace
@@ -77,6 +132,13 @@ int cfog_ctx_create(int device, cfog_ctx** out) {
 }
 
 int cfog_ctx_destroy(cfog_ctx* ctx) {
+  if (!ctx) return CFOG_OK;
+  if (ctx->ext_ws) (void)hipFree(ctx->ext_ws);
+  if (ctx->stage_done) {
+    (void)hipEventSynchronize(ctx->stage_done);
+    (void)hipEventDestroy(ctx->stage_done);
+  }
+  if (ctx->stage) (void)hipHostFree(ctx->stage);
   delete ctx;
   return CFOG_OK;
 }
@@ -111,8 +173,14 @@ int32_t cfog_fft_size(int32_t N, int32_t r) {
   return p ? p->P : 0;
 }
 
+size_t cfog_extract_workspace_size(int32_t H, int32_t W) {
+  if (H < 1 || W < 1) return 0;
+  return cfog::extract_workspace_bytes(H, W);
+}
+
 int cfog_extract(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride, int32_t m,
-                 float sigma, int32_t gauss_radius, float* d_vol, double* d_sat, void* stream) {
+                 float sigma, int32_t gauss_radius, float* d_vol, double* d_sat, void* d_ws, size_t ws_bytes,
+                 void* stream) {
   if (!ctx || !d_img || !d_vol) return CFOG_EINVAL;
   if (H < 1 || W < 1 || row_stride < W || m < 1 || m > cfog::kMaxOrient) return CFOG_EINVAL;
   if (!(sigma > 0.f) || !isfinite(sigma)) return CFOG_EINVAL;
@@ -120,7 +188,27 @@ int cfog_extract(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_
   if (R > cfog::kMaxGaussRadius) return CFOG_EUNSUPPORTED;
   if (!aligned(d_sat, 8)) return CFOG_EINVAL;
   if (cfog::extract_lds_bytes(m, R) > cfog::kMaxLds) return CFOG_EUNSUPPORTED;
-  int rc = cfog::launch_extract(d_img, row_stride, H, W, m, sigma, R, d_vol, d_sat, (hipStream_t)stream);
+  const size_t need = d_sat ? cfog::extract_workspace_bytes(H, W) : 0;
+  if (need && d_ws && ws_bytes < need) return CFOG_ENOMEM;
+  if (!aligned(d_ws, 8)) return CFOG_EINVAL;
+  if (need && !d_ws) {
+    if (ctx->ext_ws_bytes < need) {
+      if (ctx->ext_ws) {
+        // the old workspace may still be in use by queued work on any stream
+        if (hipDeviceSynchronize() != hipSuccess) return record(ctx, hipGetLastError());
+        (void)hipFree(ctx->ext_ws);
+        ctx->ext_ws = nullptr;
+        ctx->ext_ws_bytes = 0;
+      }
+      if (hipMalloc(&ctx->ext_ws, need) != hipSuccess) {
+        ctx->ext_ws = nullptr;
+        return CFOG_ENOMEM;
+      }
+      ctx->ext_ws_bytes = need;
+    }
+    d_ws = ctx->ext_ws;
+  }
+  int rc = cfog::launch_extract(d_img, row_stride, H, W, m, sigma, R, d_vol, d_sat, d_ws, (hipStream_t)stream);
   if (rc == -1) return CFOG_EUNSUPPORTED;
   if (rc != 0) return record(ctx, hipGetLastError());
   return CFOG_OK;
@@ -129,10 +217,9 @@ int cfog_extract(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_
 size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m,
                                   int32_t flags) {
   if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return (size_t)-1;
-  for (int i = 0; i < n_jobs; ++i)
-    if (validate_job(jobs[i], m) != CFOG_OK) return (size_t)-1;
-  if (flags == CFOG_PATH_BATCHED_FFT) return batched_ws_bytes(jobs, n_jobs);
-  return 0;
+  std::vector<const cfog::FftPlan*> plans;
+  if (resolve_plans(jobs, n_jobs, m, plans) == CFOG_EINVAL) return (size_t)-1;
+  return ws_layout(ctx, jobs, n_jobs, flags, plans).total;
 }
 
 int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags, void* d_ws,
@@ -140,59 +227,62 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
   if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return CFOG_EINVAL;
   if (flags != CFOG_PATH_PLAIN_FFT && flags != CFOG_PATH_BATCHED_FFT && flags != CFOG_PATH_MFMA_BF16)
     return CFOG_EINVAL;
-  std::vector<const cfog::FftPlan*> plans(n_jobs);
-  for (int i = 0; i < n_jobs; ++i) {
-    int rc = validate_job(jobs[i], m);
-    if (rc != CFOG_OK) return rc;
-    plans[i] = cfog::choose_fft_plan(jobs[i].N, jobs[i].r);
-    if (!plans[i]) return CFOG_EUNSUPPORTED;
-  }
-  hipStream_t st = (hipStream_t)stream;
+  std::vector<const cfog::FftPlan*> plans;
+  int rc = resolve_plans(jobs, n_jobs, m, plans);
+  if (rc != CFOG_OK) return rc;
   if (flags == CFOG_PATH_MFMA_BF16) return CFOG_EUNSUPPORTED;
+  const WsLayout W = ws_layout(ctx, jobs, n_jobs, flags, plans);
+  if (W.total > 0 && (!d_ws || ws_bytes < W.total)) return CFOG_ENOMEM;
+  if (!aligned(d_ws, 256)) return CFOG_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)d_ws;
+  void* tg_ws = W.tg ? ws : nullptr;
   if (flags == CFOG_PATH_PLAIN_FFT) {
     for (int i = 0; i < n_jobs; ++i) {
       if (jobs[i].n_cps == 0) continue;
-      if (cfog::launch_match_fft_plain(plans[i], to_device_job(jobs[i], m), st) != 0)
+      const cfog::FftPlan* p = plans[i];
+      const int blocks = p->tg_bytes ? std::min(jobs[i].n_cps, cfog::plan_slots(p, ctx->num_cus)) : jobs[i].n_cps;
+      if (cfog::launch_match_fft(p, to_device_job(jobs[i], m), nullptr, nullptr, jobs[i].n_cps, blocks, tg_ws, st) !=
+          0)
         return record(ctx, hipGetLastError());
     }
     return CFOG_OK;
   }
   // batched: one persistent launch per FFT plan over a (job, cp) task table
-  const size_t need = batched_ws_bytes(jobs, n_jobs);
-  if (need > 0 && (!d_ws || ws_bytes < need)) return CFOG_ENOMEM;
-  if (!aligned(d_ws, 256)) return CFOG_EINVAL;
-  std::vector<cfog::MatchJob> hj(n_jobs);
-  for (int i = 0; i < n_jobs; ++i) hj[i] = to_device_job(jobs[i], m);
   int nplans = 0;
   const cfog::FftPlan* all = cfog::fft_plans(&nplans);
-  std::vector<int2> tasks;
+  size_t ncp = 0;
+  for (int i = 0; i < n_jobs; ++i) ncp += jobs[i].n_cps;
+  if (ncp == 0) return CFOG_OK;
+  const size_t table_bytes = W.total - W.jobs_off;
+  rc = ensure_stage(ctx, table_bytes);
+  if (rc != CFOG_OK) return rc;
+  char* stage = (char*)ctx->stage;
+  cfog::MatchJob* hj = (cfog::MatchJob*)stage;
+  int2* ht = (int2*)(stage + (W.tasks_off - W.jobs_off));
+  for (int i = 0; i < n_jobs; ++i) hj[i] = to_device_job(jobs[i], m);
   std::vector<int> bucket_begin(nplans + 1, 0);
+  size_t nt = 0;
   for (int p = 0; p < nplans; ++p) {
-    bucket_begin[p] = (int)tasks.size();
+    bucket_begin[p] = (int)nt;
     for (int i = 0; i < n_jobs; ++i)
       if (plans[i] == &all[p])
-        for (int c = 0; c < jobs[i].n_cps; ++c) tasks.push_back(make_int2(i, c));
+        for (int c = 0; c < jobs[i].n_cps; ++c) ht[nt++] = make_int2(i, c);
   }
-  bucket_begin[nplans] = (int)tasks.size();
-  if (tasks.empty()) return CFOG_OK;
-  char* ws = (char*)d_ws;
-  cfog::MatchJob* d_jobs = (cfog::MatchJob*)ws;
-  int2* d_tasks = (int2*)(ws + align_up(sizeof(cfog::MatchJob) * (size_t)n_jobs, 256));
-  if (hipMemcpyAsync(d_jobs, hj.data(), sizeof(cfog::MatchJob) * n_jobs, hipMemcpyHostToDevice, st) != hipSuccess)
+  bucket_begin[nplans] = (int)nt;
+  if (hipMemcpyAsync(ws + W.jobs_off, stage, table_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
     return record(ctx, hipGetLastError());
-  if (hipMemcpyAsync(d_tasks, tasks.data(), sizeof(int2) * tasks.size(), hipMemcpyHostToDevice, st) != hipSuccess)
-    return record(ctx, hipGetLastError());
+  if (hipEventRecord(ctx->stage_done, st) != hipSuccess) return record(ctx, hipGetLastError());
+  const cfog::MatchJob* d_jobs = (const cfog::MatchJob*)(ws + W.jobs_off);
+  const int2* d_tasks = (const int2*)(ws + W.tasks_off);
   for (int p = 0; p < nplans; ++p) {
-    int n = bucket_begin[p + 1] - bucket_begin[p];
+    const int n = bucket_begin[p + 1] - bucket_begin[p];
     if (n == 0) continue;
-    int per_cu = std::max<int>(1, (int)(cfog::kMaxLds / all[p].lds));
-    per_cu = std::min(per_cu, std::max(1, 2048 / all[p].NT));
-    int blocks = std::min(n, ctx->num_cus * per_cu);
-    if (cfog::launch_match_fft_tasks(&all[p], d_jobs, d_tasks + bucket_begin[p], n, blocks, st) != 0)
+    const int blocks = std::min(n, cfog::plan_slots(&all[p], ctx->num_cus));
+    if (cfog::launch_match_fft(&all[p], cfog::MatchJob{}, d_jobs, d_tasks + bucket_begin[p], n, blocks, tg_ws, st) !=
+        0)
       return record(ctx, hipGetLastError());
   }
-  // the host task table must outlive the asynchronous copy
-  if (hipStreamSynchronize(st) != hipSuccess) return record(ctx, hipGetLastError());
   return CFOG_OK;
 }
 

@@ -1,21 +1,36 @@
-// CFOG extraction (Section III-F of Ye et al.) and FP64 summed-area tables of
-// the per-pixel energy Q = sum_k D_k^2 (the energy terms of Eq. 5).
+// CFOG extraction (Section III-F of Ye et al.) and the FP64 summed-area table
+// of the per-pixel energy Q = sum_k D_k^2 (the energy terms of Eq. 5).
 //
 // Layout: image [H][row_stride] fp32; volume D [m][H][W] fp32 (planar, one
 // contiguous H*W plane per orientation); SAT [(H+1)][(W+1)] fp64 with a zero
-// first row and column, SAT(y, x) = sum_{y'<y, x'<x} Q.
+// first row and column, SAT(y+1, x+1) = sum_{y'<=y, x'<=x} Q(y', x').
 //
-// One workgroup produces a TX x TY output tile for all m channels:
-//   A. stage the image tile plus a (R+1)-pixel halo in LDS (clamp-to-edge);
-//   B. per pixel of the tile + R halo: gx, gy by [-1,0,1] (Eq. 2's filters),
-//      g_k = |cos(theta_k) gx + sin(theta_k) gy| for theta_k = k pi / m, and the
-//      circular [1,2,1]/4 orientation smoothing, all in registers; result -> LDS;
-//   C. per channel: horizontal then vertical Gaussian pass (radius R, clamp-to-
-//      edge; the halo values of B were computed at clamped positions), output
-//      written straight to HBM; Q accumulated in FP64 from the FP32 outputs.
-// The Gaussian and the [1,2,1] kernel are linear and act on different axes, so
-// applying the orientation smoothing before the spatial one gives the same
-// volume as the order the paper describes (up to FP32 rounding).
+// Kernel 1 (cfog_extract_kernel<R>) produces a 64 x 16 output tile for all m
+// channels:
+//   A. stage the image tile plus an (R+1)-pixel halo in LDS (clamp-to-edge);
+//   B. gx, gy by [-1,0,1] (the filters given after Eq. 2) at every pixel of
+//      the tile + R halo, at the clamped pixel (which is what clamp-to-edge
+//      Gaussian borders read); (gx, gy) -> LDS;
+//   C. per channel k: g_k = |cos(theta_k) gx + sin(theta_k) gy| (Eq. 2,
+//      theta_k = k pi / m) into LDS, the horizontal Gaussian pass (consecutive
+//      lanes on consecutive columns, conflict-free), then the vertical pass
+//      (radius R, 4 outputs per thread from a sliding window down a column);
+//      the circular [1,2,1]/4 orientation smoothing is
+//      applied to the spatially smoothed channels with rolling registers, and
+//      each finished channel goes straight to HBM; Q accumulated in FP64 from
+//      the FP32 outputs;
+//   D. the tile-local 2-D inclusive prefix L of Q (row scan across the 64 lanes
+//      of a wave, column scan down the tile), written into the SAT buffer,
+//      plus the tile's right column and bottom row into a small workspace.
+// LDS holds only the image tile, (gx, gy), one channel and two row-pass
+// buffers (~39 KB at R = 3), so four workgroups share a CU.
+
+// Global SAT from tile-local prefixes: for a tile (i, j) with origin (y0, x0),
+//   SAT(y, x) = L(y, x) + sum_{j'<j} Rc_{i,j'}(y) + sum_{i'<i} Bt_{i',j}(x)
+//             + sum_{i'<i, j'<j} total(i', j')
+// where Rc is a tile's right column of L and Bt its bottom row.  Kernel 2
+// turns Rc into exclusive prefixes along each image row and Bt into exclusive
+// prefixes along each image column; kernel 3 adds the three terms in place.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include "kernels.hpp"
@@ -25,109 +40,23 @@ namespace cfog {
 constexpr int EX_TX = 64;
 constexpr int EX_TY = 16;
 constexpr int EX_NT = 256;
+constexpr int EX_RUN = 4;  // outputs per thread in the sliding Gaussian passes
 
 struct ExtractArgs {
   const float* img;
   int64_t stride;
-  int H, W, m, R;
+  int H, W, m;
   float* vol;
   double* sat;  // nullable
-  float cs[kMaxOrient];
-  float sn[kMaxOrient];
-  float w[kMaxGaussRadius + 1];  // w[|j|], j in [-R, R]
+  double* rc;   // [H][ntx] right columns of the tile-local prefixes
+  double* bt;   // [nty][W] bottom rows
+  int ntx, nty;
+  float cs[kMaxOrient];           // cos(theta_k)
+  float sn[kMaxOrient];           // sin(theta_k)
+  float w[kMaxGaussRadius + 1];   // w[|j|], j in [-R, R]
 };
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-__global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
-  extern __shared__ float lds[];
-  const int R = a.R, m = a.m;
-  const int IW = EX_TX + 2 * R + 2, IH = EX_TY + 2 * R + 2;  // image tile
-  const int GW = EX_TX + 2 * R, GH = EX_TY + 2 * R;          // channel tile
-  float* img = lds;                                          // IH * IW
-  float* G = img + IH * IW;                                  // m * GH * GW
-  float* Hb = G + m * GH * GW;                               // 2 * GH * EX_TX
-  const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * EX_TX, y0 = blockIdx.y * EX_TY;
-  const int H = a.H, W = a.W;
-
-  // A. image tile, rows y0-R-1 .. y0+TY+R, clamped
-  for (int i = tid; i < IH * IW; i += EX_NT) {
-    int r = i / IW, c = i - r * IW;
-    int gy = clampi(y0 - R - 1 + r, 0, H - 1), gx = clampi(x0 - R - 1 + c, 0, W - 1);
-    img[i] = a.img[(int64_t)gy * a.stride + gx];
-  }
-  __syncthreads();
-
-  // B. oriented channels + Z smoothing at clamped positions of the halo tile
-  const int oy = y0 - R - 1, ox = x0 - R - 1;  // global coords of img[0][0]
-  for (int i = tid; i < GH * GW; i += EX_NT) {
-    int r = i / GW, c = i - r * GW;
-    int Yc = clampi(y0 - R + r, 0, H - 1), Xc = clampi(x0 - R + c, 0, W - 1);
-    int yl = Yc - oy, xl = Xc - ox;
-    int xp = clampi(Xc + 1, 0, W - 1) - ox, xm = clampi(Xc - 1, 0, W - 1) - ox;
-    int yp = clampi(Yc + 1, 0, H - 1) - oy, ym = clampi(Yc - 1, 0, H - 1) - oy;
-    float gx = img[yl * IW + xp] - img[yl * IW + xm];
-    float gy = img[yp * IW + xl] - img[ym * IW + xl];
-    float g0 = fabsf(fmaf(a.cs[0], gx, a.sn[0] * gy));
-    float prev = fabsf(fmaf(a.cs[m - 1], gx, a.sn[m - 1] * gy));
-    float cur = g0;
-    for (int k = 0; k < m; ++k) {
-      float nxt = (k + 1 < m) ? fabsf(fmaf(a.cs[k + 1], gx, a.sn[k + 1] * gy)) : g0;
-      G[(k * GH + r) * GW + c] = fmaf(0.25f, prev + nxt, 0.5f * cur);
-      prev = cur;
-      cur = nxt;
-    }
-  }
-  __syncthreads();
-
-  // C. separable Gaussian per channel; each thread owns 4 output pixels
-  constexpr int PPT = EX_TX * EX_TY / EX_NT;
-  double q[PPT];
-#pragma unroll
-  for (int p = 0; p < PPT; ++p) q[p] = 0.0;
-  const size_t plane = (size_t)H * W;
-  for (int k = 0; k < m; ++k) {
-    float* hb = Hb + (k & 1) * GH * EX_TX;
-    const float* gk = G + k * GH * GW;
-    for (int i = tid; i < GH * EX_TX; i += EX_NT) {
-      int r = i / EX_TX, c = i - r * EX_TX;
-      const float* row = gk + r * GW + c + R;
-      float s = a.w[0] * row[0];
-      for (int j = 1; j <= R; ++j) s = fmaf(a.w[j], row[-j] + row[j], s);
-      hb[i] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      int i = tid + p * EX_NT;
-      int r = i / EX_TX, c = i - r * EX_TX;
-      const float* col = hb + (r + R) * EX_TX + c;
-      float s = a.w[0] * col[0];
-      for (int j = 1; j <= R; ++j) s = fmaf(a.w[j], col[-j * EX_TX] + col[j * EX_TX], s);
-      int gyy = y0 + r, gxx = x0 + c;
-      if (gyy < H && gxx < W) {
-        a.vol[k * plane + (size_t)gyy * W + gxx] = s;
-        q[p] = fma((double)s, (double)s, q[p]);
-      }
-    }
-    // the next channel writes the other half of Hb; the one after this
-    // overwrites this half only after the next barrier
-  }
-  if (a.sat) {
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-      int i = tid + p * EX_NT;
-      int r = i / EX_TX, c = i - r * EX_TX;
-      int gyy = y0 + r, gxx = x0 + c;
-      if (gyy < H && gxx < W) a.sat[(size_t)(gyy + 1) * (W + 1) + gxx + 1] = q[p];
-    }
-  }
-}
-
-// ---------------------------------------------------------------- FP64 SAT
-// Pass 1: zero row 0 and column 0, inclusive scan of every row in place.
-constexpr int SAT_NT = 256;
 
 __device__ __forceinline__ double wave_incl_scan(double v) {
   const int lane = threadIdx.x & 63;
@@ -139,112 +68,317 @@ __device__ __forceinline__ double wave_incl_scan(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(SAT_NT) void sat_rows_kernel(double* sat, int H, int W) {
-  __shared__ double wsum[SAT_NT / 64];
-  const int row = blockIdx.x;  // 0..H
-  double* p = sat + (size_t)row * (W + 1);
-  if (row == 0) {
-    for (int x = threadIdx.x; x <= W; x += SAT_NT) p[x] = 0.0;
-    return;
+template <int R>
+__global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
+  extern __shared__ float lds[];
+  constexpr int IW = EX_TX + 2 * R + 2, IH = EX_TY + 2 * R + 2;  // image tile
+  constexpr int GW = EX_TX + 2 * R, GH = EX_TY + 2 * R;          // gradient tile
+  const int m = a.m;
+  float* img = lds;                                              // IH * IW
+  float2* gxy = reinterpret_cast<float2*>(img + ((IH * IW + 1) & ~1));  // GH * GW
+  float* G = reinterpret_cast<float*>(gxy + GH * GW);            // GH * GW (+1 pad)
+  float* Hb = G + ((GH * GW + 1) & ~1);                           // 2 * GH * EX_TX
+  double* qx = reinterpret_cast<double*>(Hb + 2 * GH * EX_TX);   // 4 x 64 wave carries
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * EX_TX, y0 = blockIdx.y * EX_TY;
+  const int H = a.H, W = a.W;
+  float w[R + 1];
+#pragma unroll
+  for (int j = 0; j <= R; ++j) w[j] = a.w[j];
+
+  // A. image tile, rows y0-R-1 .. y0+TY+R, clamped; all loads issued before
+  // the LDS stores so their latencies overlap
+  {
+    constexpr int NIT = (IH * IW + EX_NT - 1) / EX_NT;
+    float v[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int i = tid + it * EX_NT;
+      if (i < IH * IW) {
+        const int r = i / IW, c = i - r * IW;
+        const int gy = clampi(y0 - R - 1 + r, 0, H - 1), gx = clampi(x0 - R - 1 + c, 0, W - 1);
+        v[it] = __builtin_nontemporal_load(a.img + (int64_t)gy * a.stride + gx);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int i = tid + it * EX_NT;
+      if (i < IH * IW) img[i] = v[it];
+    }
   }
-  if (threadIdx.x == 0) p[0] = 0.0;
-  double carry = 0.0;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int base = 1; base <= W; base += SAT_NT) {
-    int x = base + threadIdx.x;
-    double v = (x <= W) ? p[x] : 0.0;
-    v = wave_incl_scan(v);
-    if (lane == 63) wsum[wv] = v;
+  __syncthreads();
+
+  // B. gradients at clamped positions of the halo tile
+  const int oy = y0 - R - 1, ox = x0 - R - 1;  // global coords of img[0][0]
+  for (int i = tid; i < GH * GW; i += EX_NT) {
+    int r = i / GW, c = i - r * GW;
+    int Yc = clampi(y0 - R + r, 0, H - 1), Xc = clampi(x0 - R + c, 0, W - 1);
+    int yl = Yc - oy, xl = Xc - ox;
+    int xp = clampi(Xc + 1, 0, W - 1) - ox, xm = clampi(Xc - 1, 0, W - 1) - ox;
+    int yp = clampi(Yc + 1, 0, H - 1) - oy, ym = clampi(Yc - 1, 0, H - 1) - oy;
+    gxy[i] = make_float2(img[yl * IW + xp] - img[yl * IW + xm], img[yp * IW + xl] - img[ym * IW + xl]);
+  }
+  __syncthreads();
+
+  // C. per channel: oriented gradient, horizontal then vertical Gaussian; the
+  // vertical pass leaves the spatially smoothed channel Gs_k for the rows
+  // [4 (tid/64), +4) of column tid % 64 in registers.
+  const int oc = tid & 63, orow = (tid >> 6) * EX_RUN;
+  const int gxx = x0 + oc;
+  double q[EX_RUN];
+  float g0[EX_RUN], g1[EX_RUN], pm2[EX_RUN], pm1[EX_RUN];
+#pragma unroll
+  for (int p = 0; p < EX_RUN; ++p) { q[p] = 0.0; g0[p] = g1[p] = pm2[p] = pm1[p] = 0.f; }
+  const size_t plane = (size_t)H * W;
+  auto emit = [&](int k, const float (&d)[EX_RUN]) {
+#pragma unroll
+    for (int o = 0; o < EX_RUN; ++o) {
+      const int gyy = y0 + orow + o;
+      if (gyy < H && gxx < W) {
+        a.vol[k * plane + (size_t)gyy * W + gxx] = d[o];
+        q[o] = fma((double)d[o], (double)d[o], q[o]);
+      }
+    }
+  };
+  for (int k = 0; k < m; ++k) {
+    const float ck = a.cs[k], sk = a.sn[k];
+    float* hb = Hb + (k & 1) * GH * EX_TX;
+    // oriented gradient of channel k at every pixel of the halo tile
+    for (int i = tid; i < GH * GW; i += EX_NT) {
+      const float2 g = gxy[i];
+      G[i] = fabsf(fmaf(ck, g.x, sk * g.y));
+    }
     __syncthreads();
-    double off = carry;
-    for (int i = 0; i < wv; ++i) off += wsum[i];
-    double tot = 0.0;
-    for (int i = 0; i < SAT_NT / 64; ++i) tot += wsum[i];
-    if (x <= W) p[x] = v + off;
-    carry += tot;
+    // horizontal pass: consecutive lanes on consecutive columns
+    for (int i = tid; i < GH * EX_TX; i += EX_NT) {
+      const int r = i / EX_TX, c = i - r * EX_TX;
+      const float* row = G + r * GW + c + R;
+      float s = w[0] * row[0];
+#pragma unroll
+      for (int j = 1; j <= R; ++j) s = fmaf(w[j], row[-j] + row[j], s);
+      hb[i] = s;
+    }
     __syncthreads();
+    float cur[EX_RUN];
+    {
+      const float* col = hb + orow * EX_TX + oc;  // col[t*TX] = row orow - R + t
+      float v[EX_RUN + 2 * R];
+#pragma unroll
+      for (int t = 0; t < EX_RUN + 2 * R; ++t) v[t] = col[t * EX_TX];
+#pragma unroll
+      for (int o = 0; o < EX_RUN; ++o) {
+        float s = w[0] * v[o + R];
+#pragma unroll
+        for (int j = 1; j <= R; ++j) s = fmaf(w[j], v[o + R - j] + v[o + R + j], s);
+        cur[o] = s;
+      }
+    }
+    // circular [1,2,1]/4 along orientation: D_{k-1} = Gs_{k-2}/4 + Gs_{k-1}/2 + Gs_k/4
+    if (k == 0) {
+#pragma unroll
+      for (int o = 0; o < EX_RUN; ++o) g0[o] = cur[o];
+    } else if (k == 1) {
+#pragma unroll
+      for (int o = 0; o < EX_RUN; ++o) g1[o] = cur[o];
+    } else {
+      float d[EX_RUN];
+#pragma unroll
+      for (int o = 0; o < EX_RUN; ++o) d[o] = fmaf(0.25f, pm2[o] + cur[o], 0.5f * pm1[o]);
+      emit(k - 1, d);
+    }
+#pragma unroll
+    for (int o = 0; o < EX_RUN; ++o) { pm2[o] = pm1[o]; pm1[o] = cur[o]; }
+    // the next channel writes the other half of Hb; this half is overwritten
+    // two channels later, after the next barrier
+  }
+  {
+    float d[EX_RUN];
+    if (m == 1) {
+      emit(0, g0);
+    } else {
+      // D_{m-1} = Gs_{m-2}/4 + Gs_{m-1}/2 + Gs_0/4 ;  D_0 = Gs_{m-1}/4 + Gs_0/2 + Gs_1/4
+#pragma unroll
+      for (int o = 0; o < EX_RUN; ++o) d[o] = fmaf(0.25f, pm2[o] + g0[o], 0.5f * pm1[o]);
+      emit(m - 1, d);
+#pragma unroll
+      for (int o = 0; o < EX_RUN; ++o) d[o] = fmaf(0.25f, pm1[o] + g1[o], 0.5f * g0[o]);
+      emit(0, d);
+    }
+  }
+  if (!a.sat) return;
+
+  // D. tile-local 2-D prefix of Q
+#pragma unroll
+  for (int o = 0; o < EX_RUN; ++o) q[o] = wave_incl_scan(q[o]);  // along x (lanes = columns)
+#pragma unroll
+  for (int o = 1; o < EX_RUN; ++o) q[o] += q[o - 1];              // along y within the thread
+  const int wv = tid >> 6;
+  qx[wv * 64 + oc] = q[EX_RUN - 1];
+  __syncthreads();
+  double up = 0.0;
+  for (int i = 0; i < wv; ++i) up += qx[i * 64 + oc];
+  const int W1 = W + 1;
+#pragma unroll
+  for (int o = 0; o < EX_RUN; ++o) {
+    q[o] += up;
+    const int gyy = y0 + orow + o;
+    if (gyy < H && gxx < W) a.sat[(size_t)(gyy + 1) * W1 + gxx + 1] = q[o];
+    if (oc == 63 && gyy < H) a.rc[(size_t)gyy * a.ntx + blockIdx.x] = q[o];
+  }
+  if (wv == EX_NT / 64 - 1 && gxx < W) a.bt[(size_t)blockIdx.y * W + gxx] = q[EX_RUN - 1];
+}
+
+// Kernel 2: exclusive prefixes of the right columns along each image row (one
+// wave per row, lanes across tiles) and of the bottom rows along each image
+// column (one thread per column, 8 rows of loads in flight).
+constexpr int SAT_NT = 256;
+
+__device__ __forceinline__ double wave_excl_scan(double v, double& total) {
+  const double inc = wave_incl_scan(v);
+  total = __shfl(inc, 63, 64);
+  return inc - v;
+}
+
+__global__ __launch_bounds__(SAT_NT) void sat_carry_kernel(double* rc, double* bt, int H, int W, int ntx, int nty,
+                                                           int row_blocks) {
+  if ((int)blockIdx.x < row_blocks) {
+    const int y = blockIdx.x * (SAT_NT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (y >= H) return;
+    double* p = rc + (size_t)y * ntx;
+    double carry = 0.0;
+    for (int base = 0; base < ntx; base += 64) {
+      const int j = base + lane;
+      const double v = j < ntx ? p[j] : 0.0;
+      double tot;
+      const double ex = wave_excl_scan(v, tot);
+      if (j < ntx) p[j] = ex + carry;
+      carry += tot;
+    }
+  } else {
+    const int x = (blockIdx.x - row_blocks) * SAT_NT + threadIdx.x;
+    if (x >= W) return;
+    double run = 0.0;
+    constexpr int CH = 8;
+    for (int i0 = 0; i0 < nty; i0 += CH) {
+      double v[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) v[u] = (i0 + u < nty) ? bt[(size_t)(i0 + u) * W + x] : 0.0;
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        if (i0 + u < nty) bt[(size_t)(i0 + u) * W + x] = run;
+        run += v[u];
+      }
+    }
   }
 }
 
-// Pass 2: column scan over row blocks.  Block b covers rows [1 + b*SB, ...).
-constexpr int SAT_SB = 64;
-
-__global__ __launch_bounds__(SAT_NT) void sat_cols_local_kernel(double* sat, int H, int W) {
-  const int x = blockIdx.x * SAT_NT + threadIdx.x;
-  if (x > W) return;
-  const int r0 = 1 + blockIdx.y * SAT_SB, r1 = min(H + 1, r0 + SAT_SB);
-  double s = 0.0;
-  for (int y = r0; y < r1; ++y) {
-    double* q = sat + (size_t)y * (W + 1) + x;
-    s += *q;
-    *q = s;
+// Kernel 3: SAT = L + row carry + column carry + corner, in place; zero row 0
+// and column 0.  One thread per pixel column of a 64 x 16 tile, 4 rows each.
+__global__ __launch_bounds__(EX_NT) void sat_fix_kernel(double* sat, const double* rc, const double* bt, int H,
+                                                        int W, int ntx) {
+  __shared__ double corner_part[EX_NT / 64];
+  const int tid = threadIdx.x, oc = tid & 63, wv = tid >> 6;
+  const int tx = blockIdx.x, ty = blockIdx.y;
+  const int x0 = tx * EX_TX, y0 = ty * EX_TY;
+  // corner = sum_{j' < tx} (column prefix of bottom rows at the last column of tile j')
+  double cpart = 0.0;
+  for (int j = tid; j < tx; j += EX_NT) {
+    const int xl = min(W, (j + 1) * EX_TX) - 1;
+    cpart += bt[(size_t)ty * W + xl];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cpart += __shfl_xor(cpart, o, 64);
+  if ((tid & 63) == 0) corner_part[wv] = cpart;
+  __syncthreads();
+  const double corner = corner_part[0] + corner_part[1] + corner_part[2] + corner_part[3];
+  const int W1 = W + 1;
+  const int gxx = x0 + oc;
+  if (gxx < W) {
+    const double colc = bt[(size_t)ty * W + gxx];
+#pragma unroll
+    for (int o = 0; o < EX_RUN; ++o) {
+      const int gyy = y0 + wv * EX_RUN + o;
+      if (gyy < H) {
+        double* p = sat + (size_t)(gyy + 1) * W1 + gxx + 1;
+        *p = *p + rc[(size_t)gyy * ntx + tx] + colc + corner;
+      }
+    }
+  }
+  if (ty == 0) {
+    for (int x = x0 + tid; x < min(W + 1, x0 + EX_TX + 1); x += EX_NT) sat[x] = 0.0;
+  }
+  if (tx == 0) {
+    for (int y = y0 + tid; y < min(H + 1, y0 + EX_TY + 1); y += EX_NT) sat[(size_t)y * W1] = 0.0;
   }
 }
 
-// Pass 3: carry block totals down each column (last row of every block ends
-// up holding the global prefix), one thread per column.
-__global__ __launch_bounds__(SAT_NT) void sat_cols_carry_kernel(double* sat, int H, int W, int nblk) {
-  const int x = blockIdx.x * SAT_NT + threadIdx.x;
-  if (x > W) return;
-  double run = 0.0;
-  for (int b = 0; b < nblk; ++b) {
-    int last = min(H, b * SAT_SB + SAT_SB);  // last row index of block b
-    double* q = sat + (size_t)last * (W + 1) + x;
-    run += *q;
-    *q = run;
+static size_t lds_bytes(int m, int R) {
+  (void)m;
+  const int IW = EX_TX + 2 * R + 2, IH = EX_TY + 2 * R + 2;
+  const int GW = EX_TX + 2 * R, GH = EX_TY + 2 * R;
+  return sizeof(float) * (((size_t)IH * IW + 1) & ~(size_t)1) + sizeof(float2) * (size_t)GH * GW +
+         sizeof(float) * (((size_t)GH * GW + 1) & ~(size_t)1) + sizeof(float) * 2 * (size_t)GH * EX_TX +
+         sizeof(double) * 4 * 64;
+}
+
+size_t extract_lds_bytes(int m, int R) { return lds_bytes(m, R); }
+
+size_t extract_workspace_bytes(int H, int W) {
+  const size_t ntx = (W + EX_TX - 1) / EX_TX, nty = (H + EX_TY - 1) / EX_TY;
+  return sizeof(double) * ((size_t)H * ntx + nty * (size_t)W);
+}
+
+template <int R>
+static int launch_r(const ExtractArgs& a, hipStream_t st) {
+  static bool attr = false;
+  const size_t lds = lds_bytes(a.m, R);
+  if (!attr) {
+    if (hipFuncSetAttribute((const void*)cfog_extract_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kMaxLds) != hipSuccess)
+      return -2;
+    attr = true;
   }
+  dim3 grid(a.ntx, a.nty);
+  hipLaunchKernelGGL(cfog_extract_kernel<R>, grid, dim3(EX_NT), lds, st, a);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// Pass 4: add the previous block's global prefix to the other rows of a block.
-__global__ __launch_bounds__(SAT_NT) void sat_cols_fix_kernel(double* sat, int H, int W) {
-  const int x = blockIdx.x * SAT_NT + threadIdx.x;
-  const int b = blockIdx.y + 1;
-  if (x > W) return;
-  const int prev_last = b * SAT_SB;  // last row of block b-1
-  const double off = sat[(size_t)prev_last * (W + 1) + x];
-  const int r0 = 1 + b * SAT_SB, r1 = min(H, r0 + SAT_SB - 1);  // excludes own last row
-  for (int y = r0; y < r1; ++y) sat[(size_t)y * (W + 1) + x] += off;
-}
-
-int launch_extract(const float* img, int64_t stride, int H, int W, int m, float sigma, int R,
-                   float* vol, double* sat, hipStream_t st) {
+int launch_extract(const float* img, int64_t stride, int H, int W, int m, float sigma, int R, float* vol,
+                   double* sat, void* ws, hipStream_t st) {
   ExtractArgs a{};
-  a.img = img; a.stride = stride; a.H = H; a.W = W; a.m = m; a.R = R; a.vol = vol; a.sat = sat;
+  a.img = img; a.stride = stride; a.H = H; a.W = W; a.m = m; a.vol = vol; a.sat = sat;
+  a.ntx = (W + EX_TX - 1) / EX_TX;
+  a.nty = (H + EX_TY - 1) / EX_TY;
+  a.rc = (double*)ws;
+  a.bt = a.rc + (size_t)H * a.ntx;
   for (int k = 0; k < m; ++k) {
     double th = k * 3.14159265358979323846 / m;
     a.cs[k] = (float)cos(th);
     a.sn[k] = (float)sin(th);
   }
-  double ws[kMaxGaussRadius + 1], tot = 0.0;
-  for (int j = 0; j <= R; ++j) { ws[j] = exp(-(double)j * j / (2.0 * sigma * sigma)); tot += (j ? 2 : 1) * ws[j]; }
-  for (int j = 0; j <= R; ++j) a.w[j] = (float)(ws[j] / tot);
-  const int IW = EX_TX + 2 * R + 2, IH = EX_TY + 2 * R + 2;
-  const int GW = EX_TX + 2 * R, GH = EX_TY + 2 * R;
-  size_t lds = sizeof(float) * ((size_t)IH * IW + (size_t)m * GH * GW + 2 * (size_t)GH * EX_TX);
-  if (lds > kMaxLds) return -1;
-  dim3 grid((W + EX_TX - 1) / EX_TX, (H + EX_TY - 1) / EX_TY);
-  hipLaunchKernelGGL(cfog_extract_kernel, grid, dim3(EX_NT), lds, st, a);
-  if (hipGetLastError() != hipSuccess) return -2;
-  if (sat) {
-    hipLaunchKernelGGL(sat_rows_kernel, dim3(H + 1), dim3(SAT_NT), 0, st, sat, H, W);
-    const int nblk = (H + SAT_SB - 1) / SAT_SB;
-    dim3 g2((W + 1 + SAT_NT - 1) / SAT_NT, nblk);
-    hipLaunchKernelGGL(sat_cols_local_kernel, g2, dim3(SAT_NT), 0, st, sat, H, W);
-    hipLaunchKernelGGL(sat_cols_carry_kernel, dim3((W + 1 + SAT_NT - 1) / SAT_NT), dim3(SAT_NT), 0, st,
-                       sat, H, W, nblk);
-    if (nblk > 1) {
-      dim3 g3((W + 1 + SAT_NT - 1) / SAT_NT, nblk - 1);
-      hipLaunchKernelGGL(sat_cols_fix_kernel, g3, dim3(SAT_NT), 0, st, sat, H, W);
-    }
-    if (hipGetLastError() != hipSuccess) return -2;
+  double ws_[kMaxGaussRadius + 1], tot = 0.0;
+  for (int j = 0; j <= R; ++j) { ws_[j] = exp(-(double)j * j / (2.0 * sigma * sigma)); tot += (j ? 2 : 1) * ws_[j]; }
+  for (int j = 0; j <= R; ++j) a.w[j] = (float)(ws_[j] / tot);
+  if (lds_bytes(m, R) > kMaxLds) return -1;
+  int rc = -1;
+  switch (R) {
+    case 0: rc = launch_r<0>(a, st); break;
+    case 1: rc = launch_r<1>(a, st); break;
+    case 2: rc = launch_r<2>(a, st); break;
+    case 3: rc = launch_r<3>(a, st); break;
+    case 4: rc = launch_r<4>(a, st); break;
+    case 5: rc = launch_r<5>(a, st); break;
+    case 6: rc = launch_r<6>(a, st); break;
+    case 7: rc = launch_r<7>(a, st); break;
+    case 8: rc = launch_r<8>(a, st); break;
+    default: return -1;
   }
-  return 0;
-}
-
-size_t extract_lds_bytes(int m, int R) {
-  const int IW = EX_TX + 2 * R + 2, IH = EX_TY + 2 * R + 2;
-  const int GW = EX_TX + 2 * R, GH = EX_TY + 2 * R;
-  return sizeof(float) * ((size_t)IH * IW + (size_t)m * GH * GW + 2 * (size_t)GH * EX_TX);
+  if (rc != 0 || !sat) return rc;
+  const int row_blocks = (H + SAT_NT / 64 - 1) / (SAT_NT / 64);
+  hipLaunchKernelGGL(sat_carry_kernel, dim3(row_blocks + (W + SAT_NT - 1) / SAT_NT), dim3(SAT_NT), 0, st, a.rc,
+                     a.bt, H, W, a.ntx, a.nty, row_blocks);
+  hipLaunchKernelGGL(sat_fix_kernel, dim3(a.ntx, a.nty), dim3(EX_NT), 0, st, sat, a.rc, a.bt, H, W, a.ntx);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 }  // namespace cfog

@@ -30,20 +30,24 @@ struct MatchJob {
 enum : int { kCpOk = 0, kCpOutOfBounds = 1, kCpNonFinite = 2 };
 
 int launch_extract(const float* img, int64_t stride, int H, int W, int m, float sigma, int R,
-                   float* vol, double* sat, hipStream_t st);
+                   float* vol, double* sat, void* ws, hipStream_t st);
 size_t extract_lds_bytes(int m, int R);
+size_t extract_workspace_bytes(int H, int W);
 
-// FFT matcher plans: FFT side P = R1 * R2, NT threads per workgroup.
-struct FftPlan { int P, R1, R2, NT; size_t lds; };
+// FFT matcher plans: FFT side P = R1 * R2, NT threads per workgroup; plans
+// with tg_bytes > 0 park the template spectrum of the current channel in a
+// per-workgroup global workspace of that size.
+struct FftPlan { int P, R1, R2, NT; size_t lds; size_t tg_bytes; };
 const FftPlan* fft_plans(int* count);
 // Smallest supported plan with P >= Ws whose LDS scratch also fits the
 // inverse row pass for K = 2r + 1; nullptr if none.
 const FftPlan* choose_fft_plan(int N, int r);
-// Launch the plain FFT matcher: one workgroup per control point of one job.
-int launch_match_fft_plain(const FftPlan* plan, const MatchJob& job, hipStream_t st);
-// Launch the FFT matcher over a device task table (job index, cp index) for
-// jobs that share one plan; grid-stride persistent workgroups.
-int launch_match_fft_tasks(const FftPlan* plan, const MatchJob* d_jobs, const int2* d_tasks, int n_tasks,
-                           int n_blocks, hipStream_t st);
+// Workgroups of this plan that fit the device at once.
+int plan_slots(const FftPlan* p, int num_cus);
+// Launch the FFT matcher.  d_jobs == nullptr: n_tasks control points of job0
+// (plain path).  Otherwise n_tasks (job, cp) pairs from d_tasks over d_jobs.
+// tg_ws: n_blocks * tg_bytes bytes when tg_bytes > 0.
+int launch_match_fft(const FftPlan* plan, const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks,
+                     int n_tasks, int n_blocks, void* tg_ws, hipStream_t st);
 
 }  // namespace cfog

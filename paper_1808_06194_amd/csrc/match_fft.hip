@@ -1,6 +1,6 @@
 // SSD template matching of control points in the frequency domain
 // (Section III-G of Ye et al.: Eqs. 3-6 and 8-9), one workgroup per control
-// point, everything on chip.
+// point at a time, everything on chip.
 //
 // For control point (x, y) in A with search centre (bx, by) in B, template side
 // N, radius r, h = N/2, K = 2r+1, Ws = N + 2r:
@@ -15,38 +15,53 @@
 // zero orientation shift, where the orientation DFT / inverse DFT pair reduces
 // (Parseval) to a plain sum over channels of 2-D spectral products.  So each
 // channel goes through real 2-D FFTs of size P x P (P >= Ws):
-//   x-pass: rows of T_c (or S_c), two real rows packed per complex FFT;
-//   y-pass: complex column FFTs of the half-spectrum kx in [0, P/2], with the
-//           two packed rows separated on load via Z(k) / conj Z(-k);
-//   ACC(ky, kx) += conj(T^_c) * S^_c  (registers; T^_c is parked in registers
-//           between the T and S passes of the channel);
+//   x-pass: rows of T_c (or S_c), two real rows packed per complex FFT, the
+//           two half-spectra separated via Z(k) and conj Z(-k);
+//   y-pass: complex column FFTs of the half-spectrum kx in [0, P/2];
+//   ACC(ky, kx) += conj(T^_c) * S^_c  in registers (T^_c is parked in
+//           registers, or for the largest P in a global workspace, between the
+//           T and S passes of the channel);
 // then one inverse: column IFFTs (kept rows u_y < K) and a C2R row IFFT with
 // two output rows packed per complex FFT (kept columns u_x < K), the SSD
 // assembly in FP64, and a lexicographic argmin + second-best over (SSD, index).
 //
-// 1-D FFTs of length P = R1 * R2 are two radix stages in LDS:
-//   stage 1: t[b R1 + k1] = sum_a x[b + R2 a] W_R1^{a k1}         (b < R2)
-//   stage 2: X[k1 + R1 k2] = sum_b W_P^{k1 b} t[b R1 + k1] W_R2^{b k2}
-// with the small DFTs as unrolled register codelets (dft.hpp).
+// Execution: every 1-D FFT of length P = R1 * R2 is owned by a group of
+// G = max(R1, R2) lanes of one wave:
+//   stage 1 (lane j < R2):  t[j R1 + k1] = sum_a x[j + R2 a] W_R1^{a k1}
+//   stage 2 (lane k1 < R1): X[k1 + R1 k2] = sum_j W_P^{k1 j} t[j R1 + k1] W_R2^{j k2}
+// with the small DFTs as unrolled register codelets (dft.hpp) and the
+// exchange between stages through the FFT's own LDS rows or column.  Only the
+// x -> y transposes need workgroup barriers (4 per channel).
 #include <hip/hip_runtime.h>
-#include <float.h>
 #include <limits.h>
+#include <algorithm>
 #include "dft.hpp"
 #include "kernels.hpp"
 
 namespace cfog {
 
-template <int P_, int R1_, int R2_, int NT_>
+// Orders the LDS accesses of one wave (the hardware keeps a wave's LDS
+// operations in order; this stops the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int P_, int R1_, int R2_, int NT_, bool TG_>
 struct FftCfg {
   static constexpr int P = P_, R1 = R1_, R2 = R2_, NT = NT_;
+  static constexpr bool TG = TG_;  // T^ parked in a global workspace
   static_assert(P == R1 * R2, "P must equal R1 * R2");
+  static_assert(NT % 64 == 0 && NT <= 1024, "bad workgroup size");
   static constexpr int PH = P / 2 + 1;
-  static constexpr int NB_Y1 = PH * R2;  // column-FFT stage-1 butterflies (radix R1)
-  static constexpr int NB_Y2 = PH * R1;  // column-FFT stage-2 butterflies (radix R2)
-  static constexpr int KS1 = (NB_Y1 + NT - 1) / NT;
-  static constexpr int KF = (NB_Y2 + NT - 1) / NT;
+  static constexpr int G = R1 > R2 ? R1 : R2;  // lanes per FFT group
+  static constexpr int GPW = 64 / G;           // groups per wave
   static constexpr int NW = NT / 64;
+  static constexpr int NG = NW * GPW;          // groups per workgroup
+  static constexpr int KF = (PH + NG - 1) / NG;  // column rounds per group
   static constexpr size_t LDS = sizeof(float2) * ((size_t)P * PH + P) + NW * 16;
+  static constexpr size_t TG_BYTES = TG ? sizeof(float2) * (size_t)P * PH : 0;
 };
 
 struct ArgminState {
@@ -84,108 +99,121 @@ __device__ __forceinline__ double box_sum(const double* sat, int ld, int y0, int
   return (b[n] - a[n]) - (b[0] - a[0]);
 }
 
-// x-pass: forward FFT of nrows x ncols real rows (src, leading dim ld),
-// zero-padded to P, two rows per complex FFT.  Row pair q's spectrum Z_q(k),
-// k in [0, P), is left at X[2q*PH + k].
+// Lane identity within the FFT group layout.
 template <class C>
-__device__ __forceinline__ void xpass_fwd(const float* __restrict__ src, int64_t ld, int nrows, int ncols,
-                                          float2* X, const float2* tw) {
-  constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH, NT = C::NT;
-  const int nrp = (nrows + 1) >> 1;
-  for (int b = threadIdx.x; b < nrp * R2; b += NT) {
-    const int q = b / R2, j = b - q * R2;
-    const float* r0 = src + (int64_t)(2 * q) * ld;
-    const bool has1 = (2 * q + 1) < nrows;
-    float2 v[R1];
-#pragma unroll
-    for (int a = 0; a < R1; ++a) {
-      const int xx = j + R2 * a;
-      float re = 0.f, im = 0.f;
-      if (xx < ncols) {
-        re = r0[xx];
-        if (has1) im = r0[ld + xx];
-      }
-      v[a] = make_float2(re, im);
-    }
-    dft<R1, -1>(v);
-    float2* dst = X + 2 * q * PH + j * R1;
-#pragma unroll
-    for (int k = 0; k < R1; ++k) dst[k] = v[k];
+struct Lane {
+  int g;   // group index in the workgroup (>= NG for idle lanes)
+  int li;  // lane index in the group
+  __device__ __forceinline__ Lane() {
+    const int lane = threadIdx.x & 63, gi = lane / C::G;
+    li = lane - gi * C::G;
+    g = gi < C::GPW ? (int)(threadIdx.x >> 6) * C::GPW + gi : INT_MAX / 2;
   }
-  __syncthreads();
-  for (int b = threadIdx.x; b < nrp * R1; b += NT) {
-    const int q = b / R1, k1 = b - q * R1;
-    float2* base = X + 2 * q * PH + k1;
-    float2 v[R2];
-    v[0] = base[0];
-#pragma unroll
-    for (int bb = 1; bb < R2; ++bb) v[bb] = cmul(base[R1 * bb], tw[k1 * bb]);
-    dft<R2, -1>(v);
-#pragma unroll
-    for (int k = 0; k < R2; ++k) base[R1 * k] = v[k];
-  }
-  __syncthreads();
-}
+};
 
-// y-pass: forward column FFTs of the half-spectrum (kx in [0, P/2]) of the rows
-// left by xpass_fwd; rows >= nrows are zero.  Output ownership: butterfly
-// b = threadIdx.x + k*NT owns ky = k1 + R1*k2 of column kx = b % PH,
-// k1 = b / PH; each value is handed to sink(k, k2, value).
-template <class C, class Sink>
-__device__ __forceinline__ void ypass_fwd(int nrows, float2* X, const float2* tw, Sink&& sink) {
-  constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH, NT = C::NT;
-  float2 v[C::KS1][R1];
-#pragma unroll
-  for (int k = 0; k < C::KS1; ++k) {
-    const int b = threadIdx.x + k * NT;
-    if (b < C::NB_Y1) {
-      const int kx = b % PH, j = b / PH;
-      const int km = (kx == 0) ? 0 : P - kx;
+// x-pass: forward FFT of nrows x ncols real rows (src, leading dim ld),
+// zero-padded to P, two rows per complex FFT; leaves the half-spectra of the
+// rows in X as [row][kx], kx in [0, P/2], row stride PH.
+template <class C>
+__device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const float* __restrict__ src, int64_t ld, int nrows,
+                                          int ncols, float2* X, const float2* tw) {
+  constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH;
+  const int nrp = (nrows + 1) >> 1;
+  for (int q = L.g; q < nrp; q += C::NG) {
+    float2* base = X + 2 * q * PH;
+    if (L.li < R2) {
+      const int j = L.li;
+      const float* r0 = src + (int64_t)(2 * q) * ld;
+      const bool has1 = (2 * q + 1) < nrows;
+      float2 v[R1];
 #pragma unroll
       for (int a = 0; a < R1; ++a) {
-        const int y = j + R2 * a;
-        float2 val = make_float2(0.f, 0.f);
-        if (y < nrows) {
-          const float2* zq = X + (y & ~1) * PH;
-          const float2 z1 = zq[kx], z2 = zq[km];
-          // A(k) = (Z(k) + conj Z(-k)) / 2 ;  B(k) = (Z(k) - conj Z(-k)) / 2i
-          val = (y & 1) ? make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x))
-                        : make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
+        const int xx = j + R2 * a;
+        float re = 0.f, im = 0.f;
+        if (xx < ncols) {
+          re = r0[xx];
+          if (has1) im = r0[ld + xx];
         }
-        v[k][a] = val;
+        v[a] = make_float2(re, im);
       }
-      dft<R1, -1>(v[k]);
+      dft<R1, -1>(v);
+#pragma unroll
+      for (int k = 0; k < R1; ++k) base[j * R1 + k] = v[k];
     }
+    wave_sync();
+    // stage 2 on every lane of the group (idle lanes duplicate lane R1-1 so the
+    // cross-lane fetch below runs with the whole wave active)
+    const int k1 = L.li < R1 ? L.li : R1 - 1;
+    float2 v[R2];
+    v[0] = base[k1];
+#pragma unroll
+    for (int b = 1; b < R2; ++b) v[b] = cmul(base[k1 + R1 * b], tw[b * R1 + k1]);
+    dft<R2, -1>(v);
+    // separate the packed rows: A(k) = (Z(k) + conj Z(-k)) / 2, B(k) = (Z(k) - conj Z(-k)) / 2i.
+    // Z(-k) for k = k1 + R1 k2 is Z((R1-k1) + R1 (R2-1-k2)), i.e. register R2-1-k2 of
+    // lane R1-k1 of the group (k1 > 0), or this lane's register (R2-k2) mod R2 (k1 = 0).
+    const int lane = threadIdx.x & 63;
+    const int msrc = lane - L.li + (k1 == 0 ? 0 : R1 - k1);
+    const bool odd_pad = (2 * q + 1) >= nrows;  // second row of the pair is padding
+    static_for<0, R2>([&](auto k2I) {
+      constexpr int k2 = decltype(k2I)::value;
+      const float2 far = make_float2(__shfl(v[R2 - 1 - k2].x, msrc, 64), __shfl(v[R2 - 1 - k2].y, msrc, 64));
+      const float2 zm = (k1 == 0) ? v[(R2 - k2) % R2] : far;
+      const int k = k1 + R1 * k2;
+      if (L.li < R1 && k <= P / 2) {
+        const float2 z = v[k2];
+        base[k] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+        base[PH + k] = odd_pad ? make_float2(0.f, 0.f) : make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x));
+      }
+    });
+    wave_sync();
   }
-  __syncthreads();
+  // rows [2 nrp, P) of the half-spectrum are zero padding (an odd last row is
+  // zeroed by its pair above): the y-pass reads all P rows unconditionally
+  for (int i = threadIdx.x; i < (P - 2 * nrp) * PH; i += C::NT) X[2 * nrp * PH + i] = make_float2(0.f, 0.f);
+}
+
+// y-pass: forward column FFTs of the half-spectrum (rows >= nrows were zeroed
+// by the x-pass).
+// Column kx = g + rnd * NG; lane k1 < R1 of its group ends up with
+// ky = k1 + R1 k2 and hands each value to sink(rnd, k2, kx, value).
+template <class C, class Sink>
+__device__ __forceinline__ void ypass_fwd(const Lane<C>& L, float2* X, const float2* tw, Sink&& sink) {
+  constexpr int R1 = C::R1, R2 = C::R2, PH = C::PH;
+  static_for<0, C::KF>([&](auto rndI) {
+    constexpr int rnd = decltype(rndI)::value;
+    const int kx = L.g + rnd * C::NG;
+    if (kx < PH) {
+      float2* col = X + kx;
+      if (L.li < R2) {
+        const int j = L.li;
+        float2 v[R1];
 #pragma unroll
-  for (int k = 0; k < C::KS1; ++k) {
-    const int b = threadIdx.x + k * NT;
-    if (b < C::NB_Y1) {
-      const int kx = b % PH, j = b / PH;
+        for (int a = 0; a < R1; ++a) v[a] = col[(j + R2 * a) * PH];
+        dft<R1, -1>(v);
 #pragma unroll
-      for (int k1 = 0; k1 < R1; ++k1) X[(j * R1 + k1) * PH + kx] = v[k][k1];
+        for (int k = 0; k < R1; ++k) col[(j * R1 + k) * PH] = v[k];
+      }
+      wave_sync();
+      if (L.li < R1) {
+        const int k1 = L.li;
+        float2 w[R2];
+        w[0] = col[k1 * PH];
+#pragma unroll
+        for (int b = 1; b < R2; ++b) w[b] = cmul(col[(k1 + R1 * b) * PH], tw[b * R1 + k1]);
+        dft<R2, -1>(w);
+        static_for<0, R2>([&](auto k2I) {
+          constexpr int k2 = decltype(k2I)::value;
+          sink(rndI, k2I, kx, w[k2]);
+        });
+      }
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < C::KF; ++k) {
-    const int b = threadIdx.x + k * NT;
-    if (b < C::NB_Y2) {
-      const int kx = b % PH, k1 = b / PH;
-      float2 w[R2];
-      w[0] = X[k1 * PH + kx];
-#pragma unroll
-      for (int bb = 1; bb < R2; ++bb) w[bb] = cmul(X[(k1 + R1 * bb) * PH + kx], tw[k1 * bb]);
-      dft<R2, -1>(w);
-#pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) sink(k, k2, w[k2]);
-    }
-  }
+  });
 }
 
 template <class C>
-__device__ void match_one(const MatchJob& jd, int cpi, float2* X, float2* tw, ArgminState* red) {
+__device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, int cpi, float2* X, const float2* tw,
+                          ArgminState* red, float2* __restrict__ tg) {
   constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH, NT = C::NT, KF = C::KF;
   const int4 cp = jd.cps[cpi];
   const int N = jd.N, r = jd.r, K = 2 * r + 1, h = N / 2, Ws = N + 2 * r;
@@ -211,131 +239,129 @@ __device__ void match_one(const MatchJob& jd, int cpi, float2* X, float2* tw, Ar
 
   const size_t planeA = (size_t)jd.hA * jd.wA, planeB = (size_t)jd.hB * jd.wB;
   for (int c = 0; c < jd.m; ++c) {
-    float2 th[KF][R2];
+    float2 th[C::TG ? 1 : KF][R2];
+    __syncthreads();  // previous readers of X are done
+    xpass_fwd<C>(L, jd.volA + c * planeA + (size_t)ty0 * jd.wA + tx0, jd.wA, N, N, X, tw);
     __syncthreads();
-    xpass_fwd<C>(jd.volA + c * planeA + (size_t)ty0 * jd.wA + tx0, jd.wA, N, N, X, tw);
-    ypass_fwd<C>(N, X, tw, [&](int k, int k2, float2 v) { th[k][k2] = v; });
+    ypass_fwd<C>(L, X, tw, [&](auto rndI, auto k2I, int kx, float2 v) {
+      constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
+      if constexpr (C::TG) tg[(size_t)kx * P + L.li + R1 * k2] = v;
+      else th[rnd][k2] = v;
+    });
     __syncthreads();
-    xpass_fwd<C>(jd.volB + c * planeB + (size_t)sy0 * jd.wB + sx0, jd.wB, Ws, Ws, X, tw);
-    ypass_fwd<C>(Ws, X, tw, [&](int k, int k2, float2 v) { acc[k][k2] = cmac_conj(acc[k][k2], th[k][k2], v); });
+    xpass_fwd<C>(L, jd.volB + c * planeB + (size_t)sy0 * jd.wB + sx0, jd.wB, Ws, Ws, X, tw);
+    __syncthreads();
+    ypass_fwd<C>(L, X, tw, [&](auto rndI, auto k2I, int kx, float2 v) {
+      constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
+      float2 t;
+      if constexpr (C::TG) t = tg[(size_t)kx * P + L.li + R1 * k2];
+      else t = th[rnd][k2];
+      acc[rnd][k2] = cmac_conj(acc[rnd][k2], t, v);
+    });
   }
 
-  // ---- inverse: columns (ky -> u_y), keep rows u_y < K
-  __syncthreads();
+  // ---- inverse along y: each group transforms its own columns in place and
+  // keeps the rows u_y < K (no workgroup barrier: a column is group-private).
 #pragma unroll
-  for (int k = 0; k < KF; ++k) {
-    const int b = threadIdx.x + k * NT;
-    if (b < C::NB_Y2) {
-      const int kx = b % PH, k1 = b / PH;
+  for (int rnd = 0; rnd < KF; ++rnd) {
+    const int kx = L.g + rnd * C::NG;
+    if (kx < PH) {
+      float2* col = X + kx;
+      if (L.li < R1) {
 #pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) X[(k1 + R1 * k2) * PH + kx] = acc[k][k2];
+        for (int k2 = 0; k2 < R2; ++k2) col[(L.li + R1 * k2) * PH] = acc[rnd][k2];
+      }
+      wave_sync();
+      if (L.li < R2) {
+        const int j = L.li;
+        float2 v[R1];
+#pragma unroll
+        for (int a = 0; a < R1; ++a) v[a] = col[(j + R2 * a) * PH];
+        dft<R1, +1>(v);
+#pragma unroll
+        for (int k = 0; k < R1; ++k) col[(j * R1 + k) * PH] = v[k];
+      }
+      wave_sync();
+      if (L.li < R1) {
+        const int k1 = L.li;
+        float2 w[R2];
+        w[0] = col[k1 * PH];
+#pragma unroll
+        for (int b = 1; b < R2; ++b) {
+          const float2 t = tw[b * R1 + k1];
+          w[b] = cmul(col[(k1 + R1 * b) * PH], make_float2(t.x, -t.y));
+        }
+        dft<R2, +1>(w);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) {
+          const int uy = k1 + R1 * k2;
+          if (uy < K) col[uy * PH] = w[k2];
+        }
+      }
     }
   }
   __syncthreads();
-  {
-    float2 v[C::KS1][R1];
+
+  // ---- inverse along x: C2R, two output rows per complex FFT, kept u_x < K;
+  // the correlation C(u_y, u_x) goes to LDS behind the row-FFT scratch.
+  const int npair = (K + 1) >> 1;
+  float2* SC = X + K * PH;
+  float* Cs = reinterpret_cast<float*>(SC + npair * P);
+  const float inv = 1.0f / ((float)P * (float)P);
+  for (int p = L.g; p < npair; p += C::NG) {
+    float2* sc = SC + p * P;
+    if (L.li < R2) {
+      const int j = L.li;
+      const float2* v1r = X + (2 * p) * PH;
+      const bool has2 = 2 * p + 1 < K;
+      float2 v[R1];
 #pragma unroll
-    for (int k = 0; k < C::KS1; ++k) {
-      const int b = threadIdx.x + k * NT;
-      if (b < C::NB_Y1) {
-        const int kx = b % PH, j = b / PH;
-#pragma unroll
-        for (int a = 0; a < R1; ++a) v[k][a] = X[(j + R2 * a) * PH + kx];
-        dft<R1, +1>(v[k]);
+      for (int a = 0; a < R1; ++a) {
+        const int kx = j + R2 * a;
+        const bool lo = kx <= P / 2;
+        const int kk = lo ? kx : P - kx;
+        const float2 v1 = v1r[kk];
+        const float2 v2 = has2 ? v1r[PH + kk] : make_float2(0.f, 0.f);
+        v[a] = lo ? make_float2(v1.x - v2.y, v1.y + v2.x) : make_float2(v1.x + v2.y, v2.x - v1.y);
       }
+      dft<R1, +1>(v);
+#pragma unroll
+      for (int k = 0; k < R1; ++k) sc[j * R1 + k] = v[k];
     }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < C::KS1; ++k) {
-      const int b = threadIdx.x + k * NT;
-      if (b < C::NB_Y1) {
-        const int kx = b % PH, j = b / PH;
-#pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) X[(j * R1 + k1) * PH + kx] = v[k][k1];
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int k = 0; k < KF; ++k) {
-    const int b = threadIdx.x + k * NT;
-    if (b < C::NB_Y2) {
-      const int kx = b % PH, k1 = b / PH;
+    wave_sync();
+    if (L.li < R1) {
+      const int k1 = L.li;
       float2 w[R2];
-      w[0] = X[k1 * PH + kx];
+      w[0] = sc[k1];
 #pragma unroll
-      for (int bb = 1; bb < R2; ++bb) {
-        const float2 t = tw[k1 * bb];
-        w[bb] = cmul(X[(k1 + R1 * bb) * PH + kx], make_float2(t.x, -t.y));
+      for (int b = 1; b < R2; ++b) {
+        const float2 t = tw[b * R1 + k1];
+        w[b] = cmul(sc[k1 + R1 * b], make_float2(t.x, -t.y));
       }
       dft<R2, +1>(w);
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) {
-        const int uy = k1 + R1 * k2;
-        if (uy < K) X[uy * PH + kx] = w[k2];
-      }
-    }
-  }
-  __syncthreads();
-
-  // ---- inverse: rows (kx -> u_x), two real output rows per complex FFT
-  const int npair = (K + 1) >> 1;
-  float2* SC = X + K * PH;
-  for (int b = threadIdx.x; b < npair * R2; b += NT) {
-    const int p = b / R2, j = b - p * R2;
-    const float2* v1r = X + (2 * p) * PH;
-    const bool has2 = 2 * p + 1 < K;
-    float2 v[R1];
-#pragma unroll
-    for (int a = 0; a < R1; ++a) {
-      const int kx = j + R2 * a;
-      const bool lo = kx <= P / 2;
-      const int kk = lo ? kx : P - kx;
-      const float2 v1 = v1r[kk];
-      const float2 v2 = has2 ? v1r[PH + kk] : make_float2(0.f, 0.f);
-      v[a] = lo ? make_float2(v1.x - v2.y, v1.y + v2.x) : make_float2(v1.x + v2.y, v2.x - v1.y);
-    }
-    dft<R1, +1>(v);
-    float2* dst = SC + p * P + j * R1;
-#pragma unroll
-    for (int k = 0; k < R1; ++k) dst[k] = v[k];
-  }
-  __syncthreads();
-
-  ArgminState st{INFINITY, INT_MAX, INFINITY, 0};
-  const double E1 = box_sum(jd.satA, jd.wA + 1, ty0, tx0, N);
-  const int ldB = jd.wB + 1;
-  const double inv = 1.0 / ((double)P * (double)P);
-  float* surf = jd.surfaces ? jd.surfaces + (size_t)cpi * K * K : nullptr;
-  for (int b = threadIdx.x; b < npair * R1; b += NT) {
-    const int p = b / R1, k1 = b - p * R1;
-    const float2* base = SC + p * P + k1;
-    float2 w[R2];
-    w[0] = base[0];
-#pragma unroll
-    for (int bb = 1; bb < R2; ++bb) {
-      const float2 t = tw[k1 * bb];
-      w[bb] = cmul(base[R1 * bb], make_float2(t.x, -t.y));
-    }
-    dft<R2, +1>(w);
-#pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2) {
-      const int ux = k1 + R1 * k2;
-      if (ux < K) {
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int uy = 2 * p + e;
-          if (uy < K) {
-            const double cval = (double)(e ? w[k2].y : w[k2].x) * inv;
-            const double E2 = box_sum(jd.satB, ldB, sy0 + uy, sx0 + ux, N);
-            const float s = (float)(E1 + E2 - 2.0 * cval);
-            const int idx = uy * K + ux;
-            am_push(st, s, idx);
-            if (surf) surf[idx] = s;
-          }
+        const int ux = k1 + R1 * k2;
+        if (ux < K) {
+          Cs[(2 * p) * K + ux] = w[k2].x * inv;
+          if (2 * p + 1 < K) Cs[(2 * p + 1) * K + ux] = w[k2].y * inv;
         }
       }
     }
+  }
+  __syncthreads();
+
+  // ---- SSD (Eq. 5) with FP64 energies, surface output, running argmin
+  ArgminState st{INFINITY, INT_MAX, INFINITY, 0};
+  const double E1 = box_sum(jd.satA, jd.wA + 1, ty0, tx0, N);
+  const int ldB = jd.wB + 1;
+  float* surf = jd.surfaces ? jd.surfaces + (size_t)cpi * K * K : nullptr;
+  for (int idx = threadIdx.x; idx < K * K; idx += NT) {
+    const int uy = idx / K, ux = idx - uy * K;
+    const double E2 = box_sum(jd.satB, ldB, sy0 + uy, sx0 + ux, N);
+    const float s = (float)(E1 + E2 - 2.0 * (double)Cs[idx]);
+    am_push(st, s, idx);
+    if (surf) surf[idx] = s;
   }
   // wave reduction then across waves
 #pragma unroll
@@ -361,62 +387,70 @@ __device__ void match_one(const MatchJob& jd, int cpi, float2* X, float2* tw, Ar
   }
 }
 
+// One kernel for both paths: with jobs == nullptr every task t is control
+// point t of job0 (plain path); otherwise task t = tasks[t] = (job, cp) over the
+// device job table (batched path).  Workgroups loop over tasks with a grid
+// stride; tg_ws holds one T^ buffer per workgroup for the TG plans.
 template <class C>
-__device__ __forceinline__ void init_twiddles(float2* tw) {
-  for (int k = threadIdx.x; k < C::P; k += C::NT) {
+__global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const MatchJob* __restrict__ jobs,
+                                                          const int2* __restrict__ tasks, int n_tasks,
+                                                          float2* __restrict__ tg_ws) {
+  extern __shared__ float2 smem[];
+  float2* X = smem;
+  float2* tw = X + C::P * C::PH;
+  ArgminState* red = reinterpret_cast<ArgminState*>(tw + C::P);
+  // stage-2 twiddles W_P^{k1 b} stored lane-major: tw[b * R1 + k1]
+  for (int i = threadIdx.x; i < C::P; i += C::NT) {
+    const int b = i / C::R1, k1 = i - b * C::R1;
     double s, c;
-    sincospi(2.0 * k / C::P, &s, &c);
-    tw[k] = make_float2((float)c, (float)-s);
+    sincospi(2.0 * (double)((k1 * b) % C::P) / C::P, &s, &c);
+    tw[i] = make_float2((float)c, (float)-s);
   }
-}
-
-template <class C>
-__global__ __launch_bounds__(C::NT) void match_fft_plain_kernel(MatchJob jd) {
-  extern __shared__ float2 smem[];
-  float2* X = smem;
-  float2* tw = X + C::P * C::PH;
-  ArgminState* red = reinterpret_cast<ArgminState*>(tw + C::P);
-  init_twiddles<C>(tw);
-  __syncthreads();
-  match_one<C>(jd, blockIdx.x, X, tw, red);
-}
-
-template <class C>
-__global__ __launch_bounds__(C::NT) void match_fft_tasks_kernel(const MatchJob* __restrict__ jobs,
-                                                                const int2* __restrict__ tasks, int n_tasks) {
-  extern __shared__ float2 smem[];
-  float2* X = smem;
-  float2* tw = X + C::P * C::PH;
-  ArgminState* red = reinterpret_cast<ArgminState*>(tw + C::P);
-  init_twiddles<C>(tw);
-  __syncthreads();
+  const Lane<C> L;
+  float2* tg = C::TG ? tg_ws + (size_t)blockIdx.x * C::P * C::PH : nullptr;
   for (int t = blockIdx.x; t < n_tasks; t += gridDim.x) {
-    const int2 tk = tasks[t];
-    const MatchJob jd = jobs[tk.x];
-    match_one<C>(jd, tk.y, X, tw, red);
-    __syncthreads();
+    __syncthreads();  // twiddles ready / previous task's reduction done
+    MatchJob jd = job0;
+    int cpi = t;
+    if (jobs) {
+      const int2 tk = tasks[t];
+      jd = jobs[tk.x];
+      cpi = tk.y;
+    }
+    match_one<C>(L, jd, cpi, X, tw, red, tg);
   }
 }
 
 // ------------------------------------------------------------------ plans
-#define CFOG_PLANS(X)  \
-  X(16, 4, 4, 64)      \
-  X(24, 4, 6, 128)     \
-  X(32, 4, 8, 128)     \
-  X(40, 5, 8, 256)     \
-  X(48, 6, 8, 256)     \
-  X(64, 8, 8, 256)     \
-  X(72, 8, 9, 256)     \
-  X(80, 8, 10, 512)    \
-  X(96, 8, 12, 512)    \
-  X(100, 10, 10, 512)  \
-  X(120, 10, 12, 1024) \
-  X(128, 8, 16, 1024)  \
-  X(144, 12, 12, 1024) \
-  X(160, 10, 16, 1024)
+//  P, R1, R2, NT, TG  (R1 >= R2 keeps the per-lane outputs of stage 2 small;
+//  NT chosen so that the groups cover the P/2+1 columns in one round where the
+//  registers allow)
+#define CFOG_PLANS(X)            \
+  X(16, 4, 4, 64, false)         \
+  X(24, 6, 4, 128, false)        \
+  X(32, 8, 4, 192, false)        \
+  X(40, 8, 5, 192, false)        \
+  X(48, 8, 6, 256, false)        \
+  X(60, 10, 6, 384, false)       \
+  X(64, 8, 8, 320, false)        \
+  X(72, 9, 8, 384, false)        \
+  X(80, 10, 8, 448, false)       \
+  X(90, 10, 9, 512, false)       \
+  X(96, 12, 8, 512, false)       \
+  X(100, 10, 10, 512, false)     \
+  X(108, 12, 9, 512, false)      \
+  X(120, 12, 10, 512, false)     \
+  X(128, 16, 8, 384, false)      \
+  X(144, 12, 12, 512, false)     \
+  X(160, 16, 10, 256, true)      \
+  X(180, 15, 12, 256, true)      \
+  X(192, 16, 12, 256, true)
+
+#define CFOG_CFG(P_, R1_, R2_, NT_, TG_) FftCfg<P_, R1_, R2_, NT_, TG_>
 
 static const FftPlan kPlans[] = {
-#define CFOG_PLAN_ENTRY(P, R1, R2, NT) {P, R1, R2, NT, FftCfg<P, R1, R2, NT>::LDS},
+#define CFOG_PLAN_ENTRY(P_, R1_, R2_, NT_, TG_) \
+  {P_, R1_, R2_, NT_, CFOG_CFG(P_, R1_, R2_, NT_, TG_)::LDS, CFOG_CFG(P_, R1_, R2_, NT_, TG_)::TG_BYTES},
     CFOG_PLANS(CFOG_PLAN_ENTRY)
 #undef CFOG_PLAN_ENTRY
 };
@@ -431,52 +465,41 @@ const FftPlan* choose_fft_plan(int N, int r) {
   for (const FftPlan& p : kPlans) {
     if (p.P < Ws) continue;
     const int PH = p.P / 2 + 1;
-    if ((long)((K + 1) / 2) * p.P > (long)(p.P - K) * PH) continue;  // inverse row scratch
+    // inverse row scratch and the K x K correlation behind it must fit in LDS
+    if (2L * ((long)(K + 1) / 2 * p.P) + (long)K * K > 2L * (long)(p.P - K) * PH) continue;
     return &p;
   }
   return nullptr;
 }
 
+int plan_slots(const FftPlan* p, int num_cus) {
+  const int by_lds = (int)(kMaxLds / p->lds);
+  const int by_waves = 32 / (p->NT / 64);
+  return num_cus * std::max(1, std::min(by_lds, by_waves));
+}
+
 template <class C>
-static int launch_plain_t(const MatchJob& job, hipStream_t st) {
+static int launch_t(const MatchJob& job0, const MatchJob* jobs, const int2* tasks, int n_tasks, int n_blocks,
+                    void* tg_ws, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)match_fft_plain_kernel<C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    if (hipFuncSetAttribute((const void*)match_fft_kernel<C>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)C::LDS) != hipSuccess)
       return -2;
     attr_set = true;
   }
-  hipLaunchKernelGGL(match_fft_plain_kernel<C>, dim3(job.n_cps), dim3(C::NT), C::LDS, st, job);
+  if (C::TG && !tg_ws) return -1;
+  hipLaunchKernelGGL(match_fft_kernel<C>, dim3(n_blocks), dim3(C::NT), C::LDS, st, job0, jobs, tasks, n_tasks,
+                     (float2*)tg_ws);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-template <class C>
-static int launch_tasks_t(const MatchJob* jobs, const int2* tasks, int n_tasks, int n_blocks, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)match_fft_tasks_kernel<C>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)C::LDS) != hipSuccess)
-      return -2;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(match_fft_tasks_kernel<C>, dim3(n_blocks), dim3(C::NT), C::LDS, st, jobs, tasks, n_tasks);
-  return hipGetLastError() == hipSuccess ? 0 : -2;
-}
-
-int launch_match_fft_plain(const FftPlan* plan, const MatchJob& job, hipStream_t st) {
-  if (job.n_cps <= 0) return 0;
-#define CFOG_PLAN_CASE(P_, R1_, R2_, NT_) \
-  if (plan->P == P_) return launch_plain_t<FftCfg<P_, R1_, R2_, NT_>>(job, st);
-  CFOG_PLANS(CFOG_PLAN_CASE)
-#undef CFOG_PLAN_CASE
-  return -1;
-}
-
-int launch_match_fft_tasks(const FftPlan* plan, const MatchJob* d_jobs, const int2* d_tasks, int n_tasks,
-                           int n_blocks, hipStream_t st) {
+int launch_match_fft(const FftPlan* plan, const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks,
+                     int n_tasks, int n_blocks, void* tg_ws, hipStream_t st) {
   if (n_tasks <= 0) return 0;
-#define CFOG_PLAN_CASE(P_, R1_, R2_, NT_) \
-  if (plan->P == P_) return launch_tasks_t<FftCfg<P_, R1_, R2_, NT_>>(d_jobs, d_tasks, n_tasks, n_blocks, st);
+#define CFOG_PLAN_CASE(P_, R1_, R2_, NT_, TG_) \
+  if (plan->P == P_)                           \
+    return launch_t<CFOG_CFG(P_, R1_, R2_, NT_, TG_)>(job0, d_jobs, d_tasks, n_tasks, n_blocks, tg_ws, st);
   CFOG_PLANS(CFOG_PLAN_CASE)
 #undef CFOG_PLAN_CASE
   return -1;

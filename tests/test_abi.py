@@ -51,7 +51,7 @@ def test_status_strings(lib):
 
 def test_null_context_is_rejected(lib):
     from paper_1808_06194_amd import cfog
-    assert lib.cfog_extract(None, None, 8, 8, 8, 9, 0.8, -1, None, None, None) == cfog.CFOG_EINVAL
+    assert lib.cfog_extract(None, None, 8, 8, 8, 9, 0.8, -1, None, None, None, 0, None) == cfog.CFOG_EINVAL
     assert lib.match_batch(None, None, 0, 9, 1, None, 0, None) == cfog.CFOG_EINVAL
     assert lib.match_batch_workspace_size(None, None, 0, 9, 1) == ctypes.c_size_t(-1).value
     assert lib.cfog_ctx_create(0, None) == cfog.CFOG_EINVAL
