@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--path", choices=["plain", "batched"], default="plain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed steps, run one plain device-to-device copy of this many MiB "
+                         "(a counter calibration point for HBM traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
@@ -190,6 +193,19 @@ def main():
         "recovered_1p5px": round(recovered, 4),
         "cp_status_ok": int(np.sum(st == 0)),
     }
+    if args.calib_copy_mib:
+        # source written first, then 1 GiB of other writes so that the copy's
+        # reads come from HBM rather than the last-level cache
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        junk = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        junk.fill_(2.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = nb
+        del junk
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, cps, N, r, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -219,3 +219,44 @@ def test_match_batched_equals_plain(cf):
         outs[flags] = [(jb.out.cpu(), jb.surfaces.cpu()) for jb in jobs]
     for (o1, s1), (o2, s2) in zip(outs[cf.PATH_PLAIN_FFT], outs[cf.PATH_BATCHED_FFT]):
         assert torch.equal(o1, o2) and torch.equal(s1, s2)
+
+
+def test_match_plain_2048_full_size_sampled(cf):
+    """The 2048^2 workload (400 CPs, template 100, radius 20; P = 144) in the
+    launch configuration the benchmark times.  Every point is checked for
+    self-consistency (status, argmin of its own surface); a seeded sample of
+    points is checked element-wise against the FP64 oracle."""
+    A, B, s, cps, N, r = synth.plain_workload(synth.PLAIN_2048)
+    _say("match plain_2048", A.shape, len(cps), N, r)
+    res, surf = _run_match(cf, A, B, cps, N, r)
+    K = 2 * r + 1
+    assert np.all(res["status"] == 0)
+    flat = surf.reshape(len(cps), -1)
+    i = np.argmin(flat, axis=1)
+    assert np.array_equal(i % K - r, res["dx"]) and np.array_equal(i // K - r, res["dy"])
+    assert np.array_equal(flat[np.arange(len(cps)), i], res["best"])
+    rng = np.random.default_rng(2048)
+    stats = {}
+    for k in rng.choice(len(cps), 6, replace=False):
+        S, E1, E2 = parity.oracle_point(A, B, cps[k], N, r)
+        parity.check_point(int(k), res, S, E1, E2, r, surf[k], stats)
+    print("stats", stats, flush=True)
+
+
+def test_extract_large_image_sampled(cf):
+    """A 4100 x 4096 image: sampled windows against the oracle, and the SAT
+    against box sums of the returned volume (a property at any size)."""
+    _say("extract 4100x4096")
+    rng = np.random.default_rng(41)
+    img = rng.random((4100, 4096)).astype(np.float32)
+    vol, sat = cf.cfog_extract(_dev(img))
+    torch.cuda.synchronize()
+    for (y0, x0, h, w) in [(0, 0, 20, 30), (4080, 4070, 20, 26), (2049, 1023, 40, 70), (17, 4000, 33, 96)]:
+        got = vol[:, y0:y0 + h, x0:x0 + w].cpu().numpy()
+        parity.check_volume(got, parity.cfog_window(img, y0, x0, h, w))
+    q = (vol.double() ** 2).sum(0)
+    S = sat.cpu().numpy()
+    for (y0, x0, h, w) in [(0, 0, 4100, 4096), (100, 200, 64, 64), (4000, 3000, 100, 1096), (1, 1, 1, 1)]:
+        box = S[y0 + h, x0 + w] - S[y0, x0 + w] - S[y0 + h, x0] + S[y0, x0]
+        ref = float(q[y0:y0 + h, x0:x0 + w].sum())
+        assert abs(box - ref) <= 1e-9 * max(1.0, abs(ref)), (y0, x0, h, w, box, ref)
