@@ -48,10 +48,14 @@ extern "C" {
 #define CFOG_CP_OUT_OF_BOUNDS 1 /* template leaves A or search window leaves B */
 #define CFOG_CP_NONFINITE 2     /* a similarity value was NaN or infinite */
 
-/* match_batch flags: exactly one path */
+/* match_batch flags: exactly one path ... */
 #define CFOG_PATH_PLAIN_FFT 0x1   /* one FFT launch per job, one workgroup per CP */
 #define CFOG_PATH_BATCHED_FFT 0x2 /* all jobs' CPs fused into persistent launches per FFT size */
 #define CFOG_PATH_MFMA_BF16 0x4   /* direct correlation as BF16 MFMA GEMMs (FP32 accumulate) */
+#define CFOG_PATH_MASK 0xF
+/* ... plus optional modifiers */
+#define CFOG_AUTOTUNE 0x100  /* FFT paths: time candidate FFT sizes per (N, r) on first use */
+#define CFOG_USE_GRAPH 0x200 /* batched path: capture the launches once, replay on identical calls */
 
 typedef struct cfog_ctx cfog_ctx;
 
@@ -149,7 +153,15 @@ size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n
  * match_batch - SSD template matching of every control point of every job
  * (Eqs. 3-6, 8-9; Eq. 4 argmin).  Volumes have m channels (1..16).
  *   jobs        host array of n_jobs jobs (n_jobs >= 0).
- *   flags       one CFOG_PATH_* value.
+ *   flags       one CFOG_PATH_* value, optionally | CFOG_AUTOTUNE (FFT paths:
+ *               the first call for a given (N, r, m) times up to three FFT sizes
+ *               on the job's own points and keeps the fastest; with the
+ *               environment variable CFOG_PLAN_CACHE naming a file, choices
+ *               persist across processes) and | CFOG_USE_GRAPH (batched path:
+ *               the task-table upload and the bucket launches are captured into a
+ *               hipGraph keyed by the exact jobs array, workspace pointer and size;
+ *               identical later calls replay it).  Query the workspace size again
+ *               after an autotuning call: a larger FFT size may need more.
  *   d_ws        device workspace of ws_bytes >= match_batch_workspace_size(); may be
  *               NULL when that size is 0.  It must stay untouched until the work
  *               completes on `stream`.
@@ -162,6 +174,16 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
 
 /* Largest N + 2r the FFT paths support. */
 int32_t cfog_max_window(void);
+
+/* Pin the FFT side P used for template side N and radius r on this context
+ * (P = 0 removes the pin).  Returns CFOG_EUNSUPPORTED if no kernel of side P
+ * fits (P < N + 2r or too little on-chip scratch).  Pins take precedence over
+ * the autotuner; both only change the rounding of the FFT, not the method. */
+int cfog_set_plan(cfog_ctx* ctx, int32_t N, int32_t r, int32_t P);
+
+/* FFT side P this context uses for (N, r) with m channels (pin, autotuned
+ * choice, or default); 0 if unsupported. */
+int32_t cfog_plan_for(cfog_ctx* ctx, int32_t N, int32_t r, int32_t m);
 
 /* FFT side P the FFT paths use for template side N and radius r (P >= N + 2r),
  * or 0 if unsupported. */

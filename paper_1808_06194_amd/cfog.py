@@ -30,12 +30,14 @@ CP_OK, CP_OUT_OF_BOUNDS, CP_NONFINITE = 0, 1, 2
 PATH_PLAIN_FFT = 0x1
 PATH_BATCHED_FFT = 0x2
 PATH_MFMA_BF16 = 0x4
+AUTOTUNE = 0x100
+USE_GRAPH = 0x200
 
 # Exported symbols, as declared in include/cfog.h.
 EXPORTS = (
     "cfog_ctx_create", "cfog_ctx_destroy", "cfog_ctx_last_error", "cfog_status_str",
     "cfog_extract", "cfog_extract_workspace_size", "match_batch_workspace_size", "match_batch",
-    "cfog_max_window", "cfog_fft_size",
+    "cfog_max_window", "cfog_fft_size", "cfog_set_plan", "cfog_plan_for",
 )
 
 
@@ -81,6 +83,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cfog_max_window.restype = i32
     lib.cfog_fft_size.argtypes = [i32, i32]
     lib.cfog_fft_size.restype = i32
+    lib.cfog_set_plan.argtypes = [vp, i32, i32, i32]
+    lib.cfog_plan_for.argtypes = [vp, i32, i32, i32]
+    lib.cfog_plan_for.restype = i32
     _lib = lib
     return lib
 
@@ -213,21 +218,36 @@ def make_jobs_array(jobs: List[Job]):
 def match_batch(jobs: List[Job], m: int = 9, flags: int = PATH_PLAIN_FFT, stream=None,
                 workspace: Optional[torch.Tensor] = None) -> List[torch.Tensor]:
     """Match every control point of every job; returns the (n, 6) int32 result
-    tensors (see `results`).  Asynchronous on `stream`."""
+    tensors (see `results`).  Asynchronous on `stream`.  Without an explicit
+    `workspace` the context's cached one is used (grown on demand)."""
     if not jobs:
         return []
     dev = jobs[0].cps.device.index
     ctx = context(dev)
     arr = make_jobs_array(jobs)
     lib = load()
-    need = lib.match_batch_workspace_size(ctx.handle, arr, len(jobs), m, flags)
-    if need == ctypes.c_size_t(-1).value:
-        raise CfogError(CFOG_EINVAL, "match_batch_workspace_size")
-    ws = workspace if workspace is not None else ctx.workspace(need)
-    rc = lib.match_batch(ctx.handle, arr, len(jobs), m, flags, _ptr(ws) if need else None,
-                         ws.numel() if (need and ws is not None) else 0, _stream_ptr(stream))
+    for attempt in range(2):
+        need = lib.match_batch_workspace_size(ctx.handle, arr, len(jobs), m, flags)
+        if need == ctypes.c_size_t(-1).value:
+            raise CfogError(CFOG_EINVAL, "match_batch_workspace_size")
+        ws = workspace if workspace is not None else ctx.workspace(need)
+        rc = lib.match_batch(ctx.handle, arr, len(jobs), m, flags, _ptr(ws) if need else None,
+                             ws.numel() if (need and ws is not None) else 0, _stream_ptr(stream))
+        # an autotuning call may have picked a larger FFT size: query again
+        if rc == CFOG_ENOMEM and workspace is None and attempt == 0:
+            continue
+        break
     _check(rc, "match_batch")
     return [j.out for j in jobs]
+
+
+def set_plan(N: int, r: int, P: int, device: Optional[int] = None):
+    """Pin the FFT side used for (N, r) on the device's context (0 unpins)."""
+    _check(load().cfog_set_plan(context(device).handle, int(N), int(r), int(P)), "cfog_set_plan")
+
+
+def plan_for(N: int, r: int, m: int = 9, device: Optional[int] = None) -> int:
+    return int(load().cfog_plan_for(context(device).handle, int(N), int(r), int(m)))
 
 
 def max_window() -> int:

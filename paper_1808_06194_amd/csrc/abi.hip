@@ -1,13 +1,44 @@
-// C-ABI entry points of libcfog: argument validation, plan selection,
-// workspace layout and launch sequencing.  All compute runs in the HIP
-// kernels of cfog_extract.hip and match_fft.hip.
+// C-ABI entry points of libcfog: argument validation, FFT-plan selection
+// (pinned, autotuned or default), workspace layout, batched task tables,
+// multi-stream bucket launches and the hipGraph cache.  All compute runs in
+// the HIP kernels of cfog_extract.hip, match_fft.hip and match_direct.hip.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 #include <algorithm>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
 #include <vector>
 #include "cfog.h"
 #include "kernels.hpp"
+
+namespace {
+
+constexpr int kBucketStreams = 4;
+
+struct GraphEntry {
+  std::vector<unsigned char> key;  // exact call signature (jobs bytes + scalars)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* host_tables = nullptr;     // pinned copy of the task tables the graph uploads
+  ~GraphEntry() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (host_tables) (void)hipHostFree(host_tables);
+  }
+};
+
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  return h;
+}
+
+}  // namespace
 
 struct cfog_ctx {
   int device = 0;
@@ -15,12 +46,22 @@ struct cfog_ctx {
   int num_cus = 0;
   void* ext_ws = nullptr;  // context-owned extraction workspace
   size_t ext_ws_bytes = 0;
-  void* stage = nullptr;   // pinned host staging for task tables
+  void* stage = nullptr;   // pinned host staging for task tables (eager path)
   size_t stage_bytes = 0;
   hipEvent_t stage_done = nullptr;  // recorded after the last copy out of `stage`
+  hipStream_t bucket[kBucketStreams] = {};
+  hipEvent_t fork = nullptr, join[kBucketStreams] = {};
+  hipStream_t capture = nullptr;
+  std::map<long, int> pinned;   // (N, r) -> P chosen by the caller
+  std::map<long, int> tuned;    // (N, r, m) -> P chosen by the autotuner
+  std::string plan_cache_path;  // optional persistent autotuner cache
+  std::unordered_map<uint64_t, std::unique_ptr<GraphEntry>> graphs;
 };
 
 namespace {
+
+long nr_key(int N, int r) { return (long)N * 4096 + r; }
+long nrm_key(int N, int r, int m) { return ((long)N * 4096 + r) * 32 + m; }
 
 int record(cfog_ctx* ctx, hipError_t e) {
   if (e != hipSuccess) {
@@ -56,40 +97,117 @@ cfog::MatchJob to_device_job(const cfog_job& j, int m) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Workspace of match_batch: [template-spectrum buffers of the large-P plans]
-// [batched path: MatchJob x n_jobs | int2 x total CPs]
-struct WsLayout {
-  size_t tg = 0;       // bytes of the template-spectrum region
-  size_t jobs_off = 0, tasks_off = 0, total = 0;
+const cfog::FftPlan* plan_by_P(int P) {
+  int n = 0;
+  const cfog::FftPlan* all = cfog::fft_plans(&n);
+  for (int i = 0; i < n; ++i)
+    if (all[i].P == P) return &all[i];
+  return nullptr;
+}
+
+// The FFT plan used for (N, r, m): a caller pin, else the autotuner's pick,
+// else the smallest fitting size.
+const cfog::FftPlan* select_plan(cfog_ctx* ctx, int N, int r, int m) {
+  auto it = ctx->pinned.find(nr_key(N, r));
+  if (it != ctx->pinned.end()) return plan_by_P(it->second);
+  auto jt = ctx->tuned.find(nrm_key(N, r, m));
+  if (jt != ctx->tuned.end()) return plan_by_P(jt->second);
+  return cfog::choose_fft_plan(N, r);
+}
+
+// ------------------------------------------------------------- batch plans
+
+struct Bucket {
+  const cfog::FftPlan* plan;
+  int begin, count, blocks;
+  size_t tg_off;  // this bucket's template-spectrum region in the workspace
 };
 
-WsLayout ws_layout(cfog_ctx* ctx, const cfog_job* jobs, int n_jobs, int flags,
-                   const std::vector<const cfog::FftPlan*>& plans) {
-  WsLayout L;
-  size_t ncp = 0;
+struct BatchPlan {
+  std::vector<cfog::MatchJob> jobs;
+  std::vector<int2> tasks;
+  std::vector<Bucket> buckets;
+  size_t jobs_off = 0, tasks_off = 0, table_bytes = 0, total = 0;
+};
+
+int build_batch(cfog_ctx* ctx, const cfog_job* jobs, int n_jobs, int m, BatchPlan& B) {
+  std::vector<const cfog::FftPlan*> plans(n_jobs);
   for (int i = 0; i < n_jobs; ++i) {
-    ncp += (size_t)std::max(0, jobs[i].n_cps);
-    const cfog::FftPlan* p = plans[i];
-    if (p && p->tg_bytes && jobs[i].n_cps > 0) {
-      // plain path: one launch per job; batched path: one per plan over all jobs
-      const int blocks = flags == CFOG_PATH_PLAIN_FFT ? std::min(jobs[i].n_cps, cfog::plan_slots(p, ctx->num_cus))
-                                                      : cfog::plan_slots(p, ctx->num_cus);
-      L.tg = std::max(L.tg, (size_t)blocks * p->tg_bytes);
-    }
+    int rc = validate_job(jobs[i], m);
+    if (rc != CFOG_OK) return rc;
+    plans[i] = select_plan(ctx, jobs[i].N, jobs[i].r, m);
+    if (!plans[i]) return CFOG_EUNSUPPORTED;
   }
-  L.tg = align_up(L.tg, 256);
-  L.total = L.tg;
-  if (flags == CFOG_PATH_BATCHED_FFT && ncp > 0) {
-    L.jobs_off = L.total;
-    L.tasks_off = align_up(L.jobs_off + sizeof(cfog::MatchJob) * (size_t)n_jobs, 256);
-    L.total = L.tasks_off + sizeof(int2) * ncp;
+  B.jobs.resize(n_jobs);
+  for (int i = 0; i < n_jobs; ++i) B.jobs[i] = to_device_job(jobs[i], m);
+  int nplans = 0;
+  const cfog::FftPlan* all = cfog::fft_plans(&nplans);
+  size_t tg = 0;
+  for (int p = 0; p < nplans; ++p) {
+    Bucket b{&all[p], (int)B.tasks.size(), 0, 0, 0};
+    for (int i = 0; i < n_jobs; ++i)
+      if (plans[i] == &all[p])
+        for (int c = 0; c < jobs[i].n_cps; ++c) B.tasks.push_back(make_int2(i, c));
+    b.count = (int)B.tasks.size() - b.begin;
+    if (b.count == 0) continue;
+    b.blocks = std::min(b.count, cfog::plan_slots(b.plan, ctx->num_cus));
+    b.tg_off = tg;
+    tg += align_up((size_t)b.blocks * b.plan->tg_bytes, 256);  // buckets run concurrently
+    B.buckets.push_back(b);
   }
-  return L;
+  B.jobs_off = tg;
+  B.tasks_off = align_up(B.jobs_off + sizeof(cfog::MatchJob) * (size_t)n_jobs, 256);
+  B.total = B.tasks_off + sizeof(int2) * B.tasks.size();
+  B.table_bytes = B.total - B.jobs_off;
+  return CFOG_OK;
+}
+
+void fill_tables(const BatchPlan& B, void* host) {
+  char* h = (char*)host;
+  memcpy(h, B.jobs.data(), sizeof(cfog::MatchJob) * B.jobs.size());
+  memcpy(h + (B.tasks_off - B.jobs_off), B.tasks.data(), sizeof(int2) * B.tasks.size());
+}
+
+// Enqueue the upload of the tables from `host` and one persistent launch per
+// bucket, the buckets on the context's streams forked from / joined to `st`.
+int enqueue_batch(cfog_ctx* ctx, const BatchPlan& B, char* ws, const void* host, hipStream_t st) {
+  if (hipMemcpyAsync(ws + B.jobs_off, host, B.table_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+    return record(ctx, hipGetLastError());
+  const cfog::MatchJob* d_jobs = (const cfog::MatchJob*)(ws + B.jobs_off);
+  const int2* d_tasks = (const int2*)(ws + B.tasks_off);
+  if (B.buckets.size() == 1) {
+    const Bucket& b = B.buckets[0];
+    if (cfog::launch_match_fft(b.plan, cfog::MatchJob{}, d_jobs, d_tasks + b.begin, b.count, b.blocks, ws + b.tg_off,
+                               st) != 0)
+      return record(ctx, hipGetLastError());
+    return CFOG_OK;
+  }
+  if (hipEventRecord(ctx->fork, st) != hipSuccess) return record(ctx, hipGetLastError());
+  const int ns = std::min<int>(kBucketStreams, (int)B.buckets.size());
+  for (int s = 0; s < ns; ++s)
+    if (hipStreamWaitEvent(ctx->bucket[s], ctx->fork, 0) != hipSuccess) return record(ctx, hipGetLastError());
+  // largest buckets first, round-robin over the streams
+  std::vector<int> order(B.buckets.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    return (long)B.buckets[a].count * B.buckets[a].plan->P * B.buckets[a].plan->P >
+           (long)B.buckets[b].count * B.buckets[b].plan->P * B.buckets[b].plan->P;
+  });
+  for (size_t k = 0; k < order.size(); ++k) {
+    const Bucket& b = B.buckets[order[k]];
+    hipStream_t s = ctx->bucket[k % ns];
+    if (cfog::launch_match_fft(b.plan, cfog::MatchJob{}, d_jobs, d_tasks + b.begin, b.count, b.blocks, ws + b.tg_off,
+                               s) != 0)
+      return record(ctx, hipGetLastError());
+  }
+  for (int s = 0; s < ns; ++s) {
+    if (hipEventRecord(ctx->join[s], ctx->bucket[s]) != hipSuccess) return record(ctx, hipGetLastError());
+    if (hipStreamWaitEvent(st, ctx->join[s], 0) != hipSuccess) return record(ctx, hipGetLastError());
+  }
+  return CFOG_OK;
 }
 
 int ensure_stage(cfog_ctx* ctx, size_t bytes) {
-  if (!ctx->stage_done && hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming) != hipSuccess)
-    return record(ctx, hipGetLastError());
   // wait until the previous copy out of the staging buffer has completed
   if (hipEventSynchronize(ctx->stage_done) != hipSuccess) return record(ctx, hipGetLastError());
   if (ctx->stage_bytes >= bytes) return CFOG_OK;
@@ -102,14 +220,88 @@ int ensure_stage(cfog_ctx* ctx, size_t bytes) {
   return CFOG_OK;
 }
 
-int resolve_plans(const cfog_job* jobs, int n_jobs, int m, std::vector<const cfog::FftPlan*>& plans) {
-  plans.assign(n_jobs, nullptr);
-  for (int i = 0; i < n_jobs; ++i) {
-    int rc = validate_job(jobs[i], m);
-    if (rc != CFOG_OK) return rc;
-    plans[i] = cfog::choose_fft_plan(jobs[i].N, jobs[i].r);
-    if (!plans[i]) return CFOG_EUNSUPPORTED;
+// ---------------------------------------------------------------- autotuner
+
+void load_plan_cache(cfog_ctx* ctx) {
+  if (ctx->plan_cache_path.empty()) return;
+  FILE* f = fopen(ctx->plan_cache_path.c_str(), "r");
+  if (!f) return;
+  int N, r, m, P;
+  while (fscanf(f, "%d %d %d %d", &N, &r, &m, &P) == 4) {
+    const cfog::FftPlan* p = plan_by_P(P);
+    if (p && N >= 1 && r >= 0 && cfog::plan_fits(p, N, r)) ctx->tuned[nrm_key(N, r, m)] = P;
   }
+  fclose(f);
+}
+
+void save_plan_cache(cfog_ctx* ctx) {
+  if (ctx->plan_cache_path.empty()) return;
+  std::string tmp = ctx->plan_cache_path + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (auto& kv : ctx->tuned) {
+    const long nrm = kv.first;
+    const int m = (int)(nrm % 32), nr = (int)(nrm / 32);
+    fprintf(f, "%d %d %d %d\n", nr / 4096, nr % 4096, m, kv.second);
+  }
+  fclose(f);
+  rename(tmp.c_str(), ctx->plan_cache_path.c_str());
+}
+
+// Time the candidate FFT sizes for (N, r) on up to 2 x #CU control points of
+// job j and keep the fastest.  The trial launches write into the job's own
+// result buffer; the real launch that follows on the same stream overwrites
+// them.  tg_ws/tg_bytes: scratch for the template spectra of the large sizes.
+int autotune(cfog_ctx* ctx, const cfog_job& j, int m, hipStream_t st, void* tg_ws, size_t tg_bytes) {
+  const long key = nrm_key(j.N, j.r, m);
+  if (ctx->pinned.count(nr_key(j.N, j.r)) || ctx->tuned.count(key) || j.n_cps == 0) return CFOG_OK;
+  int nplans = 0;
+  const cfog::FftPlan* all = cfog::fft_plans(&nplans);
+  const cfog::FftPlan* first = cfog::choose_fft_plan(j.N, j.r);
+  if (!first) return CFOG_EUNSUPPORTED;
+  std::vector<const cfog::FftPlan*> cands;
+  for (int p = 0; p < nplans && cands.size() < 3; ++p)
+    if (all[p].P >= first->P && cfog::plan_fits(&all[p], j.N, j.r)) cands.push_back(&all[p]);
+  if (cands.size() <= 1) {
+    ctx->tuned[key] = first->P;
+    return CFOG_OK;
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return record(ctx, hipGetLastError());
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return record(ctx, hipGetLastError());
+  }
+  cfog::MatchJob dj = to_device_job(j, m);
+  dj.n_cps = std::min(j.n_cps, 2 * ctx->num_cus);
+  dj.surfaces = nullptr;
+  float best = 1e30f;
+  int bestP = first->P;
+  for (const cfog::FftPlan* p : cands) {
+    const int blocks = p->tg_bytes ? std::min(dj.n_cps, cfog::plan_slots(p, ctx->num_cus)) : dj.n_cps;
+    if (p->tg_bytes && (!tg_ws || (size_t)blocks * p->tg_bytes > tg_bytes)) continue;
+    float ms = 0.f;
+    bool ok = true;
+    for (int rep = 0; rep < 2 && ok; ++rep) {  // the first launch warms up
+      ok = hipEventRecord(e0, st) == hipSuccess &&
+           cfog::launch_match_fft(p, dj, nullptr, nullptr, dj.n_cps, blocks, tg_ws, st) == 0 &&
+           hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    }
+    if (!ok) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return record(ctx, hipGetLastError());
+    }
+    if (ms < best) {
+      best = ms;
+      bestP = p->P;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->tuned[key] = bestP;
+  save_plan_cache(ctx);
   return CFOG_OK;
 }
 
@@ -123,22 +315,38 @@ int cfog_ctx_create(int device, cfog_ctx** out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return CFOG_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return CFOG_EHIP;
-  cfog_ctx* c = new cfog_ctx();
+  std::unique_ptr<cfog_ctx> c(new cfog_ctx());
   c->device = device;
   if (hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     c->num_cus = 256;
-  *out = c;
+  if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) return CFOG_EHIP;
+  if (hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess) return CFOG_EHIP;
+  for (int s = 0; s < kBucketStreams; ++s) {
+    if (hipStreamCreateWithFlags(&c->bucket[s], hipStreamNonBlocking) != hipSuccess) return CFOG_EHIP;
+    if (hipEventCreateWithFlags(&c->join[s], hipEventDisableTiming) != hipSuccess) return CFOG_EHIP;
+  }
+  if (hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) return CFOG_EHIP;
+  if (cfog::init_kernel_attributes() != 0) return CFOG_EHIP;
+  if (const char* p = getenv("CFOG_PLAN_CACHE")) c->plan_cache_path = p;
+  load_plan_cache(c.get());
+  *out = c.release();
   return CFOG_OK;
 }
 
 int cfog_ctx_destroy(cfog_ctx* ctx) {
   if (!ctx) return CFOG_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->graphs.clear();
   if (ctx->ext_ws) (void)hipFree(ctx->ext_ws);
-  if (ctx->stage_done) {
-    (void)hipEventSynchronize(ctx->stage_done);
-    (void)hipEventDestroy(ctx->stage_done);
-  }
+  if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
   if (ctx->stage) (void)hipHostFree(ctx->stage);
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  for (int s = 0; s < kBucketStreams; ++s) {
+    if (ctx->bucket[s]) (void)hipStreamDestroy(ctx->bucket[s]);
+    if (ctx->join[s]) (void)hipEventDestroy(ctx->join[s]);
+  }
+  if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   delete ctx;
   return CFOG_OK;
 }
@@ -170,6 +378,25 @@ int32_t cfog_max_window(void) {
 int32_t cfog_fft_size(int32_t N, int32_t r) {
   if (N < 1 || r < 0) return 0;
   const cfog::FftPlan* p = cfog::choose_fft_plan(N, r);
+  return p ? p->P : 0;
+}
+
+int cfog_set_plan(cfog_ctx* ctx, int32_t N, int32_t r, int32_t P) {
+  if (!ctx || N < 1 || r < 0 || P < 0) return CFOG_EINVAL;
+  if (P == 0) {
+    ctx->pinned.erase(nr_key(N, r));
+  } else {
+    const cfog::FftPlan* p = plan_by_P(P);
+    if (!p || !cfog::plan_fits(p, N, r)) return CFOG_EUNSUPPORTED;
+    ctx->pinned[nr_key(N, r)] = P;
+  }
+  ctx->graphs.clear();  // captured launches baked in the old choice
+  return CFOG_OK;
+}
+
+int32_t cfog_plan_for(cfog_ctx* ctx, int32_t N, int32_t r, int32_t m) {
+  if (!ctx || N < 1 || r < 0) return 0;
+  const cfog::FftPlan* p = select_plan(ctx, N, r, m);
   return p ? p->P : 0;
 }
 
@@ -217,72 +444,135 @@ int cfog_extract(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_
 size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m,
                                   int32_t flags) {
   if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return (size_t)-1;
-  std::vector<const cfog::FftPlan*> plans;
-  if (resolve_plans(jobs, n_jobs, m, plans) == CFOG_EINVAL) return (size_t)-1;
-  return ws_layout(ctx, jobs, n_jobs, flags, plans).total;
+  const int path = flags & CFOG_PATH_MASK;
+  for (int i = 0; i < n_jobs; ++i)
+    if (validate_job(jobs[i], m) != CFOG_OK) return (size_t)-1;
+  if (path == CFOG_PATH_MFMA_BF16) return cfog::direct_workspace_bytes(jobs, n_jobs, m, ctx->num_cus);
+  // the autotuner may try sizes above the default: reserve for the largest
+  size_t tune = 0;
+  if (flags & CFOG_AUTOTUNE)
+    for (int i = 0; i < n_jobs; ++i)
+      tune = std::max(tune, cfog::max_tg_bytes(jobs[i].N, jobs[i].r) * (size_t)std::min(jobs[i].n_cps, 2 * ctx->num_cus));
+  if (path == CFOG_PATH_PLAIN_FFT) {
+    size_t tg = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+      const cfog::FftPlan* p = select_plan(ctx, jobs[i].N, jobs[i].r, m);
+      if (!p) return 0;  // match_batch reports CFOG_EUNSUPPORTED
+      if (p->tg_bytes && jobs[i].n_cps > 0)
+        tg = std::max(tg, (size_t)std::min(jobs[i].n_cps, cfog::plan_slots(p, ctx->num_cus)) * p->tg_bytes);
+    }
+    return align_up(std::max(tg, tune), 256);
+  }
+  BatchPlan B;
+  if (build_batch(ctx, jobs, n_jobs, m, B) != CFOG_OK) return 0;
+  return std::max(B.total, align_up(tune, 256));
 }
 
 int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags, void* d_ws,
                 size_t ws_bytes, void* stream) {
   if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return CFOG_EINVAL;
-  if (flags != CFOG_PATH_PLAIN_FFT && flags != CFOG_PATH_BATCHED_FFT && flags != CFOG_PATH_MFMA_BF16)
+  const int path = flags & CFOG_PATH_MASK;
+  if (flags & ~(CFOG_PATH_MASK | CFOG_AUTOTUNE | CFOG_USE_GRAPH)) return CFOG_EINVAL;
+  if (path != CFOG_PATH_PLAIN_FFT && path != CFOG_PATH_BATCHED_FFT && path != CFOG_PATH_MFMA_BF16)
     return CFOG_EINVAL;
-  std::vector<const cfog::FftPlan*> plans;
-  int rc = resolve_plans(jobs, n_jobs, m, plans);
-  if (rc != CFOG_OK) return rc;
-  if (flags == CFOG_PATH_MFMA_BF16) return CFOG_EUNSUPPORTED;
-  const WsLayout W = ws_layout(ctx, jobs, n_jobs, flags, plans);
-  if (W.total > 0 && (!d_ws || ws_bytes < W.total)) return CFOG_ENOMEM;
+  if ((flags & CFOG_USE_GRAPH) && path != CFOG_PATH_BATCHED_FFT) return CFOG_EINVAL;
+  if ((flags & CFOG_AUTOTUNE) && path == CFOG_PATH_MFMA_BF16) return CFOG_EINVAL;
+  for (int i = 0; i < n_jobs; ++i) {
+    int rc = validate_job(jobs[i], m);
+    if (rc != CFOG_OK) return rc;
+  }
   if (!aligned(d_ws, 256)) return CFOG_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)d_ws;
-  void* tg_ws = W.tg ? ws : nullptr;
-  if (flags == CFOG_PATH_PLAIN_FFT) {
+
+  if (path == CFOG_PATH_MFMA_BF16) {
+    const size_t need = cfog::direct_workspace_bytes(jobs, n_jobs, m, ctx->num_cus);
+    if (need > 0 && (!d_ws || ws_bytes < need)) return CFOG_ENOMEM;
+    int rc = cfog::launch_match_direct(jobs, n_jobs, m, d_ws, ctx->num_cus, st);
+    if (rc == -1) return CFOG_EUNSUPPORTED;
+    return rc == 0 ? CFOG_OK : record(ctx, hipGetLastError());
+  }
+
+  for (int i = 0; i < n_jobs; ++i)
+    if (!cfog::choose_fft_plan(jobs[i].N, jobs[i].r)) return CFOG_EUNSUPPORTED;
+  const size_t need = match_batch_workspace_size(ctx, jobs, n_jobs, m, flags);
+  if (need > 0 && (!d_ws || ws_bytes < need)) return CFOG_ENOMEM;
+  if (flags & CFOG_AUTOTUNE) {
+    // tune each distinct (N, r) on its first job, with the workspace's front as
+    // template-spectrum scratch (stream-ordered before its real use below)
+    std::map<long, int> seen;
+    for (int i = 0; i < n_jobs; ++i) {
+      if (seen.count(nr_key(jobs[i].N, jobs[i].r)) || jobs[i].n_cps == 0) continue;
+      seen[nr_key(jobs[i].N, jobs[i].r)] = 1;
+      int rc = autotune(ctx, jobs[i], m, st, ws, ws_bytes);
+      if (rc != CFOG_OK) return rc;
+    }
+  }
+
+  if (path == CFOG_PATH_PLAIN_FFT) {
     for (int i = 0; i < n_jobs; ++i) {
       if (jobs[i].n_cps == 0) continue;
-      const cfog::FftPlan* p = plans[i];
+      const cfog::FftPlan* p = select_plan(ctx, jobs[i].N, jobs[i].r, m);
       const int blocks = p->tg_bytes ? std::min(jobs[i].n_cps, cfog::plan_slots(p, ctx->num_cus)) : jobs[i].n_cps;
-      if (cfog::launch_match_fft(p, to_device_job(jobs[i], m), nullptr, nullptr, jobs[i].n_cps, blocks, tg_ws, st) !=
-          0)
+      if (p->tg_bytes && (size_t)blocks * p->tg_bytes > ws_bytes) return CFOG_ENOMEM;
+      if (cfog::launch_match_fft(p, to_device_job(jobs[i], m), nullptr, nullptr, jobs[i].n_cps, blocks, ws, st) != 0)
         return record(ctx, hipGetLastError());
     }
     return CFOG_OK;
   }
-  // batched: one persistent launch per FFT plan over a (job, cp) task table
-  int nplans = 0;
-  const cfog::FftPlan* all = cfog::fft_plans(&nplans);
-  size_t ncp = 0;
-  for (int i = 0; i < n_jobs; ++i) ncp += jobs[i].n_cps;
-  if (ncp == 0) return CFOG_OK;
-  const size_t table_bytes = W.total - W.jobs_off;
-  rc = ensure_stage(ctx, table_bytes);
+
+  // ---- batched path
+  uint64_t h = 0;
+  std::vector<unsigned char> key;
+  if (flags & CFOG_USE_GRAPH) {
+    const size_t jb = sizeof(cfog_job) * (size_t)n_jobs;
+    key.resize(jb + 4 * sizeof(uint64_t));
+    if (jb) memcpy(key.data(), jobs, jb);
+    uint64_t sc[4] = {(uint64_t)n_jobs, (uint64_t)m, (uint64_t)(uintptr_t)d_ws, (uint64_t)ws_bytes};
+    memcpy(key.data() + jb, sc, sizeof(sc));
+    h = fnv1a(key.data(), key.size());
+    auto it = ctx->graphs.find(h);
+    if (it != ctx->graphs.end() && it->second->key == key) {
+      if (hipGraphLaunch(it->second->exec, st) != hipSuccess) return record(ctx, hipGetLastError());
+      return CFOG_OK;
+    }
+  }
+  BatchPlan B;
+  int rc = build_batch(ctx, jobs, n_jobs, m, B);
   if (rc != CFOG_OK) return rc;
-  char* stage = (char*)ctx->stage;
-  cfog::MatchJob* hj = (cfog::MatchJob*)stage;
-  int2* ht = (int2*)(stage + (W.tasks_off - W.jobs_off));
-  for (int i = 0; i < n_jobs; ++i) hj[i] = to_device_job(jobs[i], m);
-  std::vector<int> bucket_begin(nplans + 1, 0);
-  size_t nt = 0;
-  for (int p = 0; p < nplans; ++p) {
-    bucket_begin[p] = (int)nt;
-    for (int i = 0; i < n_jobs; ++i)
-      if (plans[i] == &all[p])
-        for (int c = 0; c < jobs[i].n_cps; ++c) ht[nt++] = make_int2(i, c);
+  if (B.tasks.empty()) return CFOG_OK;
+  if (!d_ws || ws_bytes < B.total) return CFOG_ENOMEM;
+
+  if (!(flags & CFOG_USE_GRAPH)) {
+    rc = ensure_stage(ctx, B.table_bytes);
+    if (rc != CFOG_OK) return rc;
+    fill_tables(B, ctx->stage);
+    rc = enqueue_batch(ctx, B, ws, ctx->stage, st);
+    if (rc != CFOG_OK) return rc;
+    if (hipEventRecord(ctx->stage_done, st) != hipSuccess) return record(ctx, hipGetLastError());
+    return CFOG_OK;
   }
-  bucket_begin[nplans] = (int)nt;
-  if (hipMemcpyAsync(ws + W.jobs_off, stage, table_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+
+  // capture the upload + bucket launches once on the context's capture stream
+  std::unique_ptr<GraphEntry> g(new GraphEntry());
+  g->key = key;
+  if (hipHostMalloc(&g->host_tables, B.table_bytes, hipHostMallocDefault) != hipSuccess) return CFOG_ENOMEM;
+  fill_tables(B, g->host_tables);
+  if (hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return record(ctx, hipGetLastError());
-  if (hipEventRecord(ctx->stage_done, st) != hipSuccess) return record(ctx, hipGetLastError());
-  const cfog::MatchJob* d_jobs = (const cfog::MatchJob*)(ws + W.jobs_off);
-  const int2* d_tasks = (const int2*)(ws + W.tasks_off);
-  for (int p = 0; p < nplans; ++p) {
-    const int n = bucket_begin[p + 1] - bucket_begin[p];
-    if (n == 0) continue;
-    const int blocks = std::min(n, cfog::plan_slots(&all[p], ctx->num_cus));
-    if (cfog::launch_match_fft(&all[p], cfog::MatchJob{}, d_jobs, d_tasks + bucket_begin[p], n, blocks, tg_ws, st) !=
-        0)
-      return record(ctx, hipGetLastError());
+  rc = enqueue_batch(ctx, B, ws, g->host_tables, ctx->capture);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(ctx->capture, &graph);
+  if (rc != CFOG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
   }
+  if (ec != hipSuccess) return record(ctx, ec);
+  g->graph = graph;
+  if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) return record(ctx, hipGetLastError());
+  if (hipGraphLaunch(g->exec, st) != hipSuccess) return record(ctx, hipGetLastError());
+  if (ctx->graphs.size() >= 64) ctx->graphs.clear();
+  ctx->graphs[h] = std::move(g);
   return CFOG_OK;
 }
 

@@ -330,17 +330,25 @@ size_t extract_workspace_bytes(int H, int W) {
 
 template <int R>
 static int launch_r(const ExtractArgs& a, hipStream_t st) {
-  static bool attr = false;
   const size_t lds = lds_bytes(a.m, R);
-  if (!attr) {
-    if (hipFuncSetAttribute((const void*)cfog_extract_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)kMaxLds) != hipSuccess)
-      return -2;
-    attr = true;
-  }
   dim3 grid(a.ntx, a.nty);
   hipLaunchKernelGGL(cfog_extract_kernel<R>, grid, dim3(EX_NT), lds, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <int R>
+static int set_attr() {
+  return hipFuncSetAttribute((const void*)cfog_extract_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kMaxLds) == hipSuccess
+             ? 0
+             : -2;
+}
+
+int init_extract_attributes() {
+  if (set_attr<0>() || set_attr<1>() || set_attr<2>() || set_attr<3>() || set_attr<4>() || set_attr<5>() ||
+      set_attr<6>() || set_attr<7>() || set_attr<8>())
+    return -2;
+  return 0;
 }
 
 int launch_extract(const float* img, int64_t stride, int H, int W, int m, float sigma, int R, float* vol,

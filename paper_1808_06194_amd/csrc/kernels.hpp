@@ -42,6 +42,14 @@ const FftPlan* fft_plans(int* count);
 // Smallest supported plan with P >= Ws whose LDS scratch also fits the
 // inverse row pass for K = 2r + 1; nullptr if none.
 const FftPlan* choose_fft_plan(int N, int r);
+// Whether plan p can match template side N with radius r.
+bool plan_fits(const FftPlan* p, int N, int r);
+// Largest per-workgroup template-spectrum workspace among the sizes the
+// autotuner considers for (N, r).
+size_t max_tg_bytes(int N, int r);
+// Set the dynamic-LDS limits of every matcher and extraction kernel (once per
+// process; must precede any stream capture).  0 on success.
+int init_kernel_attributes();
 // Workgroups of this plan that fit the device at once.
 int plan_slots(const FftPlan* p, int num_cus);
 // Launch the FFT matcher.  d_jobs == nullptr: n_tasks control points of job0
@@ -49,5 +57,16 @@ int plan_slots(const FftPlan* p, int num_cus);
 // tg_ws: n_blocks * tg_bytes bytes when tg_bytes > 0.
 int launch_match_fft(const FftPlan* plan, const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks,
                      int n_tasks, int n_blocks, void* tg_ws, hipStream_t st);
+int init_match_fft_attributes();
+int init_extract_attributes();
+
+}  // namespace cfog
+
+#include "cfog.h"
+namespace cfog {
+// Direct correlation as BF16 MFMA GEMMs with FP32 accumulation (match_direct.hip).
+size_t direct_workspace_bytes(const cfog_job* jobs, int n_jobs, int m, int num_cus);
+// 0 on success, -1 unsupported configuration, -2 HIP error.
+int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, void* ws, int num_cus, hipStream_t st);
 
 }  // namespace cfog

@@ -460,16 +460,29 @@ const FftPlan* fft_plans(int* count) {
   return kPlans;
 }
 
-const FftPlan* choose_fft_plan(int N, int r) {
+bool plan_fits(const FftPlan* p, int N, int r) {
   const int Ws = N + 2 * r, K = 2 * r + 1;
-  for (const FftPlan& p : kPlans) {
-    if (p.P < Ws) continue;
-    const int PH = p.P / 2 + 1;
-    // inverse row scratch and the K x K correlation behind it must fit in LDS
-    if (2L * ((long)(K + 1) / 2 * p.P) + (long)K * K > 2L * (long)(p.P - K) * PH) continue;
-    return &p;
-  }
+  if (p->P < Ws) return false;
+  const int PH = p->P / 2 + 1;
+  // inverse row scratch and the K x K correlation behind it must fit in LDS
+  return 2L * ((long)(K + 1) / 2 * p->P) + (long)K * K <= 2L * (long)(p->P - K) * PH;
+}
+
+const FftPlan* choose_fft_plan(int N, int r) {
+  for (const FftPlan& p : kPlans)
+    if (plan_fits(&p, N, r)) return &p;
   return nullptr;
+}
+
+size_t max_tg_bytes(int N, int r) {
+  size_t m = 0;
+  int taken = 0;
+  for (const FftPlan& p : kPlans)
+    if (plan_fits(&p, N, r) && taken < 3) {
+      m = std::max(m, p.tg_bytes);
+      ++taken;
+    }
+  return m;
 }
 
 int plan_slots(const FftPlan* p, int num_cus) {
@@ -481,17 +494,30 @@ int plan_slots(const FftPlan* p, int num_cus) {
 template <class C>
 static int launch_t(const MatchJob& job0, const MatchJob* jobs, const int2* tasks, int n_tasks, int n_blocks,
                     void* tg_ws, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)match_fft_kernel<C>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)C::LDS) != hipSuccess)
-      return -2;
-    attr_set = true;
-  }
   if (C::TG && !tg_ws) return -1;
   hipLaunchKernelGGL(match_fft_kernel<C>, dim3(n_blocks), dim3(C::NT), C::LDS, st, job0, jobs, tasks, n_tasks,
                      (float2*)tg_ws);
   return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int init_match_fft_attributes() {
+#define CFOG_PLAN_ATTR(P_, R1_, R2_, NT_, TG_)                                                               \
+  if (hipFuncSetAttribute((const void*)match_fft_kernel<CFOG_CFG(P_, R1_, R2_, NT_, TG_)>,                   \
+                          hipFuncAttributeMaxDynamicSharedMemorySize,                                        \
+                          (int)CFOG_CFG(P_, R1_, R2_, NT_, TG_)::LDS) != hipSuccess)                         \
+    return -2;
+  CFOG_PLANS(CFOG_PLAN_ATTR)
+#undef CFOG_PLAN_ATTR
+  return 0;
+}
+
+int init_kernel_attributes() {
+  static int rc = 1;
+  if (rc == 1) {
+    rc = init_match_fft_attributes();
+    if (rc == 0) rc = init_extract_attributes();
+  }
+  return rc;
 }
 
 int launch_match_fft(const FftPlan* plan, const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks,

@@ -65,7 +65,14 @@ def test_job_struct_layout_matches_header():
 
 
 def test_max_window(lib):
-    assert lib.cfog_max_window() >= 144
+    assert lib.cfog_max_window() >= 192
+
+
+def test_fft_size_choice(lib):
+    from paper_1808_06194_amd import cfog
+    assert cfog.fft_size(100, 20) >= 140 and cfog.fft_size(48, 10) >= 68
+    assert cfog.fft_size(128, 32) >= 192 and cfog.fft_size(300, 10) == 0
+    assert lib.cfog_set_plan(None, 10, 2, 16) == cfog.CFOG_EINVAL
 
 
 def test_dft_codelets_host_build(tmp_path):

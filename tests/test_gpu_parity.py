@@ -260,3 +260,79 @@ def test_extract_large_image_sampled(cf):
         box = S[y0 + h, x0 + w] - S[y0, x0 + w] - S[y0 + h, x0] + S[y0, x0]
         ref = float(q[y0:y0 + h, x0:x0 + w].sum())
         assert abs(box - ref) <= 1e-9 * max(1.0, abs(ref)), (y0, x0, h, w, box, ref)
+
+
+def _batch_jobs(cf, jobs_np, surfaces=True):
+    jobs = []
+    for j in jobs_np:
+        vA, sA = cf.cfog_extract(_dev(j["A"]))
+        vB, sB = cf.cfog_extract(_dev(j["B"]))
+        K = 2 * j["r"] + 1
+        surf = torch.empty((len(j["cps"]), K, K), device="cuda") if surfaces else None
+        jobs.append(cf.Job(vA, sA, vB, sB, _dev(j["cps"]), j["N"], j["r"], surfaces=surf))
+    return jobs
+
+
+def test_fft_size_independence(cf):
+    """Pinning larger FFT sizes for the same (N, r) changes only rounding: every
+    size agrees with the oracle under the parity rules."""
+    N, r, H = 40, 10, 120
+    _say("match P independence", N, r)
+    spec = synth.PairSpec(H, H, 20, (2.0, 9.0), 8, 3)
+    A, B, s = synth.make_pair(spec, (55, 5))
+    cps = synth.random_cps(np.random.default_rng(5), H, H, N, r, 6)
+    oracle_pts = [parity.oracle_point(A, B, cp, N, r) for cp in cps]
+    sizes = []
+    for P in (60, 64, 72, 80, 96, 128, 160, 192):
+        cf.set_plan(N, r, P)
+        assert cf.plan_for(N, r) == P
+        res, surf = _run_match(cf, A, B, cps, N, r)
+        for k in range(len(cps)):
+            S, E1, E2 = oracle_pts[k]
+            parity.check_point(k, res, S, E1, E2, r, surf[k])
+        sizes.append(P)
+    cf.set_plan(N, r, 0)
+    with pytest.raises(cf.CfogError):
+        cf.set_plan(N, r, 48)  # smaller than the search window
+    assert sizes
+
+
+def test_batched_graph_replays_match_eager(cf):
+    """A captured batched launch replayed several times, with eager work and
+    synchronisations in between, reproduces the eager result bit for bit."""
+    _say("match batched graph replay")
+    jobs_np = synth.batch_workload(n_pairs=5, sides=(256, 512), seed=11, max_cps=30, min_cps=4)
+    jobs = _batch_jobs(cf, jobs_np)
+    cf.match_batch(jobs, flags=cf.PATH_BATCHED_FFT)
+    torch.cuda.synchronize()
+    ref = [(j.out.clone(), j.surfaces.clone()) for j in jobs]
+    for rep in range(4):
+        for j in jobs:
+            j.out.fill_(-7)
+            j.surfaces.fill_(float("nan"))
+        torch.cuda.synchronize()
+        cf.match_batch(jobs, flags=cf.PATH_BATCHED_FFT | cf.USE_GRAPH)
+        torch.cuda.synchronize()
+        for j, (o, sfc) in zip(jobs, ref):
+            assert torch.equal(j.out, o) and torch.equal(j.surfaces, sfc), rep
+        # eager work between replays
+        cf.match_batch(jobs[:2], flags=cf.PATH_PLAIN_FFT)
+        torch.cuda.synchronize()
+
+
+def test_batched_autotuned_against_oracle(cf):
+    """Autotuned batched matching over heterogeneous pairs, checked against
+    the oracle on every point."""
+    _say("match batched autotune")
+    jobs_np = synth.batch_workload(n_pairs=4, sides=(256,), seed=12, max_cps=6, min_cps=3)
+    jobs = _batch_jobs(cf, jobs_np)
+    cf.match_batch(jobs, flags=cf.PATH_BATCHED_FFT | cf.AUTOTUNE)
+    torch.cuda.synchronize()
+    stats = {}
+    for j_np, j in zip(jobs_np, jobs):
+        res = {k: v.cpu().numpy() for k, v in cf.results(j.out).items()}
+        surf = j.surfaces.cpu().numpy()
+        for k, cp in enumerate(j_np["cps"]):
+            S, E1, E2 = parity.oracle_point(j_np["A"], j_np["B"], cp, j_np["N"], j_np["r"])
+            parity.check_point(k, res, S, E1, E2, j_np["r"], surf[k], stats)
+    print("stats", stats, flush=True)
