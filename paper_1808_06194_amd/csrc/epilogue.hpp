@@ -1,0 +1,105 @@
+// SSD assembly (Eq. 5 of Ye et al.) from a correlation surface held in LDS,
+// with the energy terms from FP64 summed-area tables, optional surface output
+// and the lexicographic argmin / second-best of Eq. 4.  Shared by the FFT and
+// the direct (MFMA) matchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include "kernels.hpp"
+
+namespace cfog {
+
+struct ArgminState {
+  float bv;  // best value
+  int bi;    // its row-major index (u_y * K + u_x)
+  float sv;  // smallest value among all other indices
+  int bad;   // a non-finite value was seen
+};
+
+__device__ __forceinline__ void am_push(ArgminState& s, float v, int i) {
+  if (!(v == v) || fabsf(v) == INFINITY) { s.bad = 1; return; }
+  if (v < s.bv || (v == s.bv && i < s.bi)) {
+    s.sv = fminf(s.sv, s.bv);
+    s.bv = v;
+    s.bi = i;
+  } else {
+    s.sv = fminf(s.sv, v);
+  }
+}
+
+__device__ __forceinline__ void am_merge(ArgminState& s, const ArgminState& o) {
+  s.bad |= o.bad;
+  if (o.bv < s.bv || (o.bv == s.bv && o.bi < s.bi)) {
+    s.sv = fminf(fminf(s.sv, s.bv), o.sv);
+    s.bv = o.bv;
+    s.bi = o.bi;
+  } else {
+    s.sv = fminf(s.sv, fminf(o.bv, o.sv));
+  }
+}
+
+// Sum of Q over an n x n box with top-left (y0, x0) from its SAT (row stride ld).
+__device__ __forceinline__ double box_sum(const double* sat, int ld, int y0, int x0, int n) {
+  const double* a = sat + (size_t)y0 * ld + x0;
+  const double* b = a + (size_t)n * ld;
+  return (b[n] - a[n]) - (b[0] - a[0]);
+}
+
+// Writes the result of control point cpi of job jd from the correlation
+// Cs[u_y * K + u_x] (LDS, all K*K values visible to the workgroup):
+//   SSD(u) = E1 + E2(u) - 2 C(u), summed in FP64 and rounded to FP32,
+// surfaces (if requested), argmin (ties to the smallest index) and the
+// smallest other value.  (tx0, ty0): template top-left in A; (sx0, sy0):
+// search-window top-left in B.  red: NT/64 ArgminState of LDS scratch.
+template <int NT>
+__device__ __forceinline__ void ssd_epilogue(const MatchJob& jd, int cpi, int tx0, int ty0, int sx0, int sy0,
+                                             const float* Cs, ArgminState* red) {
+  const int N = jd.N, r = jd.r, K = 2 * r + 1;
+  ArgminState st{INFINITY, INT_MAX, INFINITY, 0};
+  const double E1 = box_sum(jd.satA, jd.wA + 1, ty0, tx0, N);
+  const int ldB = jd.wB + 1;
+  float* surf = jd.surfaces ? jd.surfaces + (size_t)cpi * K * K : nullptr;
+  for (int idx = threadIdx.x; idx < K * K; idx += NT) {
+    const int uy = idx / K, ux = idx - uy * K;
+    const double E2 = box_sum(jd.satB, ldB, sy0 + uy, sx0 + ux, N);
+    const float s = (float)(E1 + E2 - 2.0 * (double)Cs[idx]);
+    am_push(st, s, idx);
+    if (surf) surf[idx] = s;
+  }
+  // wave reduction then across waves
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    ArgminState t;
+    t.bv = __shfl_xor(st.bv, o, 64);
+    t.bi = __shfl_xor(st.bi, o, 64);
+    t.sv = __shfl_xor(st.sv, o, 64);
+    t.bad = __shfl_xor(st.bad, o, 64);
+    am_merge(st, t);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = st;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < NT / 64; ++i) am_merge(st, red[i]);
+    Result* res = jd.out + cpi;
+    if (st.bad) {
+      *res = Result{0, 0, NAN, NAN, kCpNonFinite, 0};
+    } else {
+      const int uy = st.bi / K, ux = st.bi - uy * K;
+      *res = Result{ux - r, uy - r, st.bv, st.sv, kCpOk, 0};
+    }
+  }
+}
+
+// Out-of-bounds control point: status, NaN surface.
+template <int NT>
+__device__ __forceinline__ void oob_result(const MatchJob& jd, int cpi) {
+  const int K = 2 * jd.r + 1;
+  if (threadIdx.x == 0) jd.out[cpi] = Result{0, 0, NAN, NAN, kCpOutOfBounds, 0};
+  if (jd.surfaces) {
+    float* s = jd.surfaces + (size_t)cpi * K * K;
+    for (int i = threadIdx.x; i < K * K; i += NT) s[i] = NAN;
+  }
+}
+
+}  // namespace cfog

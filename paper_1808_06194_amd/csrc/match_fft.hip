@@ -36,6 +36,7 @@
 #include <limits.h>
 #include <algorithm>
 #include "dft.hpp"
+#include "epilogue.hpp"
 #include "kernels.hpp"
 
 namespace cfog {
@@ -63,41 +64,6 @@ struct FftCfg {
   static constexpr size_t LDS = sizeof(float2) * ((size_t)P * PH + P) + NW * 16;
   static constexpr size_t TG_BYTES = TG ? sizeof(float2) * (size_t)P * PH : 0;
 };
-
-struct ArgminState {
-  float bv;
-  int bi;
-  float sv;
-  int bad;
-};
-
-__device__ __forceinline__ void am_push(ArgminState& s, float v, int i) {
-  if (!(v == v) || fabsf(v) == INFINITY) { s.bad = 1; return; }
-  if (v < s.bv || (v == s.bv && i < s.bi)) {
-    s.sv = fminf(s.sv, s.bv);
-    s.bv = v;
-    s.bi = i;
-  } else {
-    s.sv = fminf(s.sv, v);
-  }
-}
-
-__device__ __forceinline__ void am_merge(ArgminState& s, const ArgminState& o) {
-  s.bad |= o.bad;
-  if (o.bv < s.bv || (o.bv == s.bv && o.bi < s.bi)) {
-    s.sv = fminf(fminf(s.sv, s.bv), o.sv);
-    s.bv = o.bv;
-    s.bi = o.bi;
-  } else {
-    s.sv = fminf(s.sv, fminf(o.bv, o.sv));
-  }
-}
-
-__device__ __forceinline__ double box_sum(const double* sat, int ld, int y0, int x0, int n) {
-  const double* a = sat + (size_t)y0 * ld + x0;
-  const double* b = a + (size_t)n * ld;
-  return (b[n] - a[n]) - (b[0] - a[0]);
-}
 
 // Lane identity within the FFT group layout.
 template <class C>
@@ -219,15 +185,10 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   const int N = jd.N, r = jd.r, K = 2 * r + 1, h = N / 2, Ws = N + 2 * r;
   const int tx0 = cp.x - h, ty0 = cp.y - h;
   const int sx0 = cp.z - h - r, sy0 = cp.w - h - r;
-  Result* res = jd.out + cpi;
   const bool inA = tx0 >= 0 && ty0 >= 0 && tx0 + N <= jd.wA && ty0 + N <= jd.hA;
   const bool inB = sx0 >= 0 && sy0 >= 0 && sx0 + Ws <= jd.wB && sy0 + Ws <= jd.hB;
   if (!(inA && inB)) {
-    if (threadIdx.x == 0) *res = Result{0, 0, NAN, NAN, kCpOutOfBounds, 0};
-    if (jd.surfaces) {
-      float* s = jd.surfaces + (size_t)cpi * K * K;
-      for (int i = threadIdx.x; i < K * K; i += NT) s[i] = NAN;
-    }
+    oob_result<NT>(jd, cpi);
     return;
   }
 
@@ -351,40 +312,7 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   }
   __syncthreads();
 
-  // ---- SSD (Eq. 5) with FP64 energies, surface output, running argmin
-  ArgminState st{INFINITY, INT_MAX, INFINITY, 0};
-  const double E1 = box_sum(jd.satA, jd.wA + 1, ty0, tx0, N);
-  const int ldB = jd.wB + 1;
-  float* surf = jd.surfaces ? jd.surfaces + (size_t)cpi * K * K : nullptr;
-  for (int idx = threadIdx.x; idx < K * K; idx += NT) {
-    const int uy = idx / K, ux = idx - uy * K;
-    const double E2 = box_sum(jd.satB, ldB, sy0 + uy, sx0 + ux, N);
-    const float s = (float)(E1 + E2 - 2.0 * (double)Cs[idx]);
-    am_push(st, s, idx);
-    if (surf) surf[idx] = s;
-  }
-  // wave reduction then across waves
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    ArgminState t;
-    t.bv = __shfl_xor(st.bv, o, 64);
-    t.bi = __shfl_xor(st.bi, o, 64);
-    t.sv = __shfl_xor(st.sv, o, 64);
-    t.bad = __shfl_xor(st.bad, o, 64);
-    am_merge(st, t);
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) red[wv] = st;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < C::NW; ++i) am_merge(st, red[i]);
-    if (st.bad) {
-      *res = Result{0, 0, NAN, NAN, kCpNonFinite, 0};
-    } else {
-      const int uy = st.bi / K, ux = st.bi - uy * K;
-      *res = Result{ux - r, uy - r, st.bv, st.sv, kCpOk, 0};
-    }
-  }
+  ssd_epilogue<NT>(jd, cpi, tx0, ty0, sx0, sy0, Cs, red);
 }
 
 // One kernel for both paths: with jobs == nullptr every task t is control

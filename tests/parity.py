@@ -18,6 +18,7 @@ import oracle as O
 
 SURF_TOL = 1e-4
 VOL_TOL = 1e-5
+BF16_TOL = 2.0 ** -8 + 1e-5
 
 
 def check_volume(vol_gpu: np.ndarray, vol_ora: np.ndarray, tol: float = VOL_TOL) -> float:
@@ -27,9 +28,11 @@ def check_volume(vol_gpu: np.ndarray, vol_ora: np.ndarray, tol: float = VOL_TOL)
     return err / max(scale, 1e-30)
 
 
-def check_point(k, gpu, ora_surface, E1, E2, r, surf_gpu=None, stats=None):
+def check_point(k, gpu, ora_surface, E1, E2, r, surf_gpu=None, stats=None, tol=SURF_TOL):
     """Check control point k: gpu is a dict of numpy arrays (dx, dy, best,
-    second, status); ora_surface (2r+1, 2r+1) fp64; E2 (2r+1, 2r+1)."""
+    second, status); ora_surface (2r+1, 2r+1) fp64; E2 (2r+1, 2r+1).  tol is
+    the surface bound relative to E1 + E2 (1e-4 for FP32 paths)."""
+    SURF_TOL = tol
     K = 2 * r + 1
     assert int(gpu["status"][k]) == O.STATUS_OK, (k, int(gpu["status"][k]))
     dxo, dyo, bo, so = O.argmin_lex(ora_surface)

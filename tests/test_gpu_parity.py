@@ -336,3 +336,27 @@ def test_batched_autotuned_against_oracle(cf):
             S, E1, E2 = parity.oracle_point(j_np["A"], j_np["B"], cp, j_np["N"], j_np["r"])
             parity.check_point(k, res, S, E1, E2, j_np["r"], surf[k], stats)
     print("stats", stats, flush=True)
+
+
+@pytest.mark.parametrize("N,r,H,seed", [(128, 32, 256, 31), (48, 10, 128, 32), (37, 5, 96, 33),
+                                        (100, 20, 200, 34), (16, 0, 40, 35), (64, 39, 160, 36)])
+def test_mfma_bf16_direct_against_oracle(cf, N, r, H, seed):
+    """BF16-MFMA direct correlation: surfaces within the BF16 bound of the
+    FP64 oracle, offsets equal unless a near-tie under that bound."""
+    _say("match mfma bf16", N, r, H, seed)
+    spec = synth.PairSpec(H, H, max(6, H // 6), (2.0, 12.0), 6, 3)
+    A, B, s = synth.make_pair(spec, (300, seed))
+    cps = synth.random_cps(np.random.default_rng(seed), H, H, N, r, 4)
+    res, surf = _run_match(cf, A, B, cps, N, r, flags=cf.PATH_MFMA_BF16)
+    stats = {}
+    for k, cp in enumerate(cps):
+        S, E1, E2 = parity.oracle_point(A, B, cp, N, r)
+        parity.check_point(k, res, S, E1, E2, r, surf[k], stats, tol=parity.BF16_TOL)
+    print("stats", stats, flush=True)
+
+
+def test_mfma_rejects_radius_above_39(cf):
+    _say("match mfma unsupported")
+    A = np.random.default_rng(4).random((200, 200)).astype(np.float32)
+    with pytest.raises(cf.CfogError):
+        _run_match(cf, A, A, [[100, 100, 100, 100]], 32, 40, flags=cf.PATH_MFMA_BF16)
