@@ -1,21 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the CFOG + 3-D-FFT SSD matching hot path on one MI355X.
 
-One step = the whole hot path on one synthetic pair: CFOG extraction of A and B
-(volume + FP64 summed-area table each) and SSD matching of every control point
-(FFT correlation, FP64 energies, argmin).  Inputs are resident in HBM before the
-timed region starts.
+One step = the whole hot path on one batch of synthetic input: CFOG extraction
+of every image (volume + FP64 summed-area table) and SSD matching of every
+control point (correlation, FP64 energies, argmin).  Inputs are resident in
+HBM before the timed region starts.
 
-Default workload (plain_2048): one 2048^2 fp32 pair (800 blobs sigma 3-40,
-300 rectangles, |sin(3A)| x Gamma(4) speckle, |shift| <= 20), 400 control
-points on a 20x20 grid, template 100, search radius 20.
+Workloads (--workload):
+  plain_2048 (default): one 2048^2 fp32 pair (800 blobs sigma 3-40, 300
+      rectangles, |sin(3A)| x Gamma(4) speckle, |shift| <= 20), 400 control
+      points on a 20x20 grid, template 100, radius 20.
+  plain_256: one 256^2 pair, 25 control points, template 48, radius 10.
+  precision_4096: one 4096^2 pair (3200 blobs sigma 3-40, 1200 rectangles),
+      10,000 random control points, template 128, radius 32; --path fft
+      (FP32 FFT) or mfma (BF16 MFMA direct correlation).
+  batch_64: 64 pairs with sides from {512, 1024, 2048, 4096}, templates in
+      [40, 120], radii in [5, 30], 50-600 control points per pair; --path
+      batched (fused persistent launches, autotuned FFT sizes, hipGraph
+      replay) or plain (one launch per pair).
 
-Prints ONE JSON line (rank 0).  `--gpus N` with N > 1 is refused: this build
-runs on one GPU.
+Prints ONE JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +35,10 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFS = 157.3      # MI355X vector FP32 (packed); non-packed issue gives 78.6
+BF16_PEAK_TFS = 2500.0     # dense BF16 MFMA
 
 
 def algorithmic_bytes_per_cp(N: int, r: int, m: int = 9, surfaces: bool = False) -> int:
@@ -49,16 +63,22 @@ def fft_flops_per_cp(N: int, r: int, P: int, m: int = 9) -> float:
     return m * per_ch + (PH + (K + 1) // 2) * f
 
 
+def direct_flops_per_cp(N: int, r: int, m: int = 9) -> float:
+    """Useful multiply-adds of the spatial correlation: 2 m N^2 (2r+1)^2."""
+    return 2.0 * m * N * N * (2 * r + 1) ** 2
+
+
 def extract_bytes_per_px(m: int = 9) -> int:
     """Image read (4) + volume write (4m) + FP64 SAT write (8)."""
     return 4 + 4 * m + 8
 
 
-def cpu_baseline(A, B, cps, N, r, budget_s: float = 20.0):
-    """The FP64 oracle (CFOG of both images + brute-force SSD) on a bounded
-    sample of control points; scaled to CP matches/s of the whole workload."""
+def cpu_baseline(pairs, budget_s: float = 20.0):
+    """The FP64 oracle (CFOG of the first pair's images + brute-force SSD) on a
+    bounded sample of its control points, scaled to CP matches/s of that pair."""
     import oracle as O
     t0 = time.perf_counter()
+    A, B, cps, N, r = pairs[0]["A"], pairs[0]["B"], pairs[0]["cps"], pairs[0]["N"], pairs[0]["r"]
     D1 = O.cfog(A.astype(np.float64))
     D2 = O.cfog(B.astype(np.float64))
     t_ext = time.perf_counter() - t0
@@ -71,10 +91,53 @@ def cpu_baseline(A, B, cps, N, r, budget_s: float = 20.0):
             break
     t_cp = (time.perf_counter() - t1) / n
     total = t_ext + len(cps) * t_cp
-    return dict(value=len(cps) / total, unit="CP matches/s", cores=1, kind="oracle",
+    return dict(value=round(len(cps) / total, 3), unit="CP matches/s", cores=1, kind="oracle",
                 sample=f"FP64 CFOG of both {A.shape[0]}x{A.shape[1]} images ({t_ext:.1f} s) + direct SSD of "
                        f"{n} of {len(cps)} CPs ({t_cp:.3f} s/CP), extrapolated to all {len(cps)} CPs",
                 seconds=round(time.perf_counter() - t0, 2))
+
+
+def make_workload(name: str):
+    from paper_1808_06194_amd import synth
+    if name in ("plain_2048", "plain_256"):
+        w = synth.PLAIN_2048 if name == "plain_2048" else synth.PLAIN_256
+        A, B, s, cps, N, r = synth.plain_workload(w)
+        return [dict(A=A, B=B, shift=s, cps=cps, N=N, r=r)]
+    if name == "precision_4096":
+        spec = synth.PairSpec(4096, 4096, 3200, (3.0, 40.0), 1200, 20)
+        A, B, s = synth.make_pair(spec, (3, 0))
+        cps = synth.random_cps(np.random.default_rng(np.random.SeedSequence([3, 1])), 4096, 4096, 128, 32, 10000)
+        return [dict(A=A, B=B, shift=s, cps=cps, N=128, r=32)]
+    if name == "batch_64":
+        return synth.batch_workload(n_pairs=64)
+    raise ValueError(name)
+
+
+def describe(name: str, pairs) -> str:
+    ncp = sum(len(p["cps"]) for p in pairs)
+    if name == "plain_2048":
+        return "plain_2048: 2048^2 pair, 400 CPs (20x20 grid), template 100, radius 20, m=9, sigma=0.8"
+    if name == "plain_256":
+        return "plain_256: 256^2 pair, 25 CPs (5x5 grid), template 48, radius 10, m=9, sigma=0.8"
+    if name == "precision_4096":
+        return "precision_4096: 4096^2 pair, 10000 random CPs, template 128, radius 32, m=9, sigma=0.8"
+    return f"batch_64: 64 pairs (sides 512-4096), {ncp} CPs, templates 40-120, radii 5-30, m=9, sigma=0.8"
+
+
+def traffic_record(kernel_key: str):
+    """HBM bytes per launch measured by counters, if recorded for the current
+    matcher source (profiles/traffic.json); None otherwise."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_1808_06194_amd", "csrc", "match_fft.hip")
+    try:
+        rec = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        e = rec.get(kernel_key)
+        if e and e.get("source_sha256") == digest:
+            return e["bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+    return None
 
 
 def main():
@@ -82,7 +145,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--path", choices=["plain", "batched"], default="plain")
+    ap.add_argument("--workload", default="plain_2048",
+                    choices=["plain_2048", "plain_256", "precision_4096", "batch_64"])
+    ap.add_argument("--path", choices=["plain", "batched", "fft", "mfma"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -95,36 +160,40 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1808_06194_amd import cfog, synth
+    from paper_1808_06194_amd import cfog
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    w = synth.PLAIN_2048
-    A, B, shift, cps, N, r = synth.plain_workload(w)
     m = 9
-    H, W = A.shape
-    K = 2 * r + 1
-    dA = torch.from_numpy(A).to(dev)
-    dB = torch.from_numpy(B).to(dev)
-    dcps = torch.from_numpy(cps).to(dev)
-    volA = torch.empty((m, H, W), dtype=torch.float32, device=dev)
-    volB = torch.empty_like(volA)
-    satA = torch.empty((H + 1, W + 1), dtype=torch.float64, device=dev)
-    satB = torch.empty_like(satA)
-    job = cfog.Job(volA, satA, volB, satB, dcps, N, r)
-    flags = cfog.PATH_PLAIN_FFT if args.path == "plain" else cfog.PATH_BATCHED_FFT
+    path = args.path or {"batch_64": "batched", "precision_4096": "fft"}.get(args.workload, "plain")
+    flags = {"plain": cfog.PATH_PLAIN_FFT, "fft": cfog.PATH_PLAIN_FFT, "mfma": cfog.PATH_MFMA_BF16,
+             "batched": cfog.PATH_BATCHED_FFT | cfog.AUTOTUNE | cfog.USE_GRAPH}[path]
+    pairs = make_workload(args.workload)
+    imgs, jobs = [], []
+    for p in pairs:
+        H, W = p["A"].shape
+        dA, dB = torch.from_numpy(p["A"]).to(dev), torch.from_numpy(p["B"]).to(dev)
+        vA = torch.empty((m, H, W), dtype=torch.float32, device=dev)
+        vB = torch.empty_like(vA)
+        sA = torch.empty((H + 1, W + 1), dtype=torch.float64, device=dev)
+        sB = torch.empty_like(sA)
+        imgs.append((dA, vA, sA))
+        imgs.append((dB, vB, sB))
+        jobs.append(cfog.Job(vA, sA, vB, sB, torch.from_numpy(p["cps"]).to(dev), p["N"], p["r"]))
+    ws_ext = torch.empty(max(cfog.extract_workspace_size(*img[0].shape) for img in imgs),
+                         dtype=torch.uint8, device=dev)
+    n_cps = sum(len(p["cps"]) for p in pairs)
     stream = torch.cuda.current_stream()
-
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
     def step(evs=None):
         if evs:
             evs[0].record(stream)
-        cfog.cfog_extract(dA, m=m, vol=volA, sat=satA, stream=stream)
-        cfog.cfog_extract(dB, m=m, vol=volB, sat=satB, stream=stream)
+        for img, vol, sat in imgs:
+            cfog.cfog_extract(img, m=m, vol=vol, sat=sat, stream=stream, workspace=ws_ext)
         if evs:
             evs[1].record(stream)
-        cfog.match_batch([job], m=m, flags=flags, stream=stream)
+        cfog.match_batch(jobs, m=m, flags=flags, stream=stream)
         if evs:
             evs[2].record(stream)
 
@@ -142,34 +211,18 @@ def main():
     step_ms = np.array([e[0].elapsed_time(e[2]) for e in evs])
     ext_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
     match_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
-    n = len(cps)
-
-    res = cfog.results(job.out)
-    dx, dy, st = (res[k].cpu().numpy() for k in ("dx", "dy", "status"))
-    recovered = float(np.mean(np.hypot(dx - shift[0], dy - shift[1]) <= 1.5))
-
-    P = cfog.fft_size(N, r)
-    bytes_launch = n * algorithmic_bytes_per_cp(N, r, m)
-    flops_launch = n * fft_flops_per_cp(N, r, P, m)
     t_match = float(np.mean(match_ms)) * 1e-3
-    gbs = bytes_launch / t_match / 1e9
-    tfs = flops_launch / t_match / 1e12
-    alu_peak = 157.3
-    hbm_peak = 8000.0
-    t_hbm = bytes_launch / (hbm_peak * 1e9)
-    t_alu = flops_launch / (alu_peak * 1e12)
-    if t_alu > t_hbm:
-        roof = dict(bound="alu", achieved=round(tfs, 3), peak=alu_peak, unit="TFLOP/s", frac=round(tfs / alu_peak, 4))
-    else:
-        roof = dict(bound="hbm", achieved=round(gbs, 1), peak=hbm_peak, unit="GB/s", frac=round(gbs / hbm_peak, 4))
-    roof.update(kernel=f"match_fft_plain_kernel<P={P}>", traffic=None,
-                bytes_per_launch=bytes_launch, flops_per_launch=flops_launch,
-                hbm=dict(achieved=round(gbs, 1), peak=hbm_peak, unit="GB/s", frac=round(gbs / hbm_peak, 4)),
-                alu=dict(achieved=round(tfs, 3), peak=alu_peak, unit="TFLOP/s", frac=round(tfs / alu_peak, 4),
-                         nonpacked_peak=78.6))
+
+    ok = recovered = 0
+    for p, j in zip(pairs, jobs):
+        res = cfog.results(j.out)
+        dx, dy, st = (res[k].cpu().numpy() for k in ("dx", "dy", "status"))
+        ok += int(np.sum(st == 0))
+        recovered += int(np.sum(np.hypot(dx - p["shift"][0], dy - p["shift"][1]) <= 1.5))
+
     out = {
         "metric": "CP matches/sec (CFOG+3DFFT SSD) on 1 MI355X; p50/p99 match latency",
-        "value": round(n / (ms * 1e-3), 1),
+        "value": round(n_cps / (ms * 1e-3), 1),
         "unit": "CP matches/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -178,21 +231,51 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (FP64 energies)",
+        "dtype": "bf16 x bf16 -> f32 (FP64 energies)" if path == "mfma" else "f32 (FP64 energies)",
         "data": "synthetic",
-        "config": {"workload": "plain_2048: 2048^2 pair, 400 CPs (20x20 grid), template 100, radius 20, m=9, sigma=0.8",
-                   "path": args.path, "fft_size": P},
+        "config": {"workload": describe(args.workload, pairs), "path": path, "n_cps": n_cps},
         "latency_ms": {"step_p50": round(float(np.percentile(step_ms, 50)), 4),
                        "step_p99": round(float(np.percentile(step_ms, 99)), 4),
                        "match_p50": round(float(np.percentile(match_ms, 50)), 4),
                        "match_p99": round(float(np.percentile(match_ms, 99)), 4),
                        "extract_p50": round(float(np.percentile(ext_ms, 50)), 4)},
-        "match_only_cp_per_s": round(n / t_match, 1),
-        "extract_gbs": round(2 * H * W * extract_bytes_per_px(m) / (np.mean(ext_ms) * 1e-3) / 1e9, 1),
-        "roofline": roof,
-        "recovered_1p5px": round(recovered, 4),
-        "cp_status_ok": int(np.sum(st == 0)),
+        "match_only_cp_per_s": round(n_cps / t_match, 1),
+        "extract_gbs": round(sum(i[0].numel() for i in imgs) * extract_bytes_per_px(m)
+                             / (np.mean(ext_ms) * 1e-3) / 1e9, 1),
+        "recovered_1p5px": round(recovered / max(1, n_cps), 4),
+        "cp_status_ok": ok,
     }
+
+    # roofline of the dominant kernel (the matcher launch timed above)
+    bytes_launch = sum(len(p["cps"]) * algorithmic_bytes_per_cp(p["N"], p["r"], m) for p in pairs)
+    gbs = bytes_launch / t_match / 1e9
+    hbm = dict(achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4))
+    if path == "mfma":
+        flops = sum(len(p["cps"]) * direct_flops_per_cp(p["N"], p["r"], m) for p in pairs)
+        tfs = flops / t_match / 1e12
+        roof = dict(bound="mfma", achieved=round(tfs, 2), peak=BF16_PEAK_TFS, unit="TFLOP/s",
+                    frac=round(tfs / BF16_PEAK_TFS, 4))
+        kernel = "match_direct_kernel"
+    else:
+        flops = 0.0
+        for p in pairs:
+            P = cfog.plan_for(p["N"], p["r"], m)
+            flops += len(p["cps"]) * fft_flops_per_cp(p["N"], p["r"], P, m)
+        tfs = flops / t_match / 1e12
+        if flops / (FP32_PEAK_TFS * 1e12) > bytes_launch / (HBM_PEAK_GBS * 1e9):
+            roof = dict(bound="alu", achieved=round(tfs, 3), peak=FP32_PEAK_TFS, unit="TFLOP/s",
+                        frac=round(tfs / FP32_PEAK_TFS, 4))
+        else:
+            roof = dict(hbm)
+            roof["bound"] = "hbm"
+        kernel = "match_fft_kernel" + (f"<P={cfog.plan_for(pairs[0]['N'], pairs[0]['r'], m)}>"
+                                       if len(pairs) == 1 else "<mixed P>")
+    traffic = traffic_record(f"{args.workload}:{path}") if path != "mfma" else None
+    roof.update(kernel=kernel, traffic=traffic, bytes_per_launch=bytes_launch, flops_per_launch=flops,
+                hbm=hbm, alu=dict(achieved=round(tfs, 3), unit="TFLOP/s",
+                                  peak=BF16_PEAK_TFS if path == "mfma" else FP32_PEAK_TFS))
+    out["roofline"] = roof
+
     if args.calib_copy_mib:
         # source written first, then 1 GiB of other writes so that the copy's
         # reads come from HBM rather than the last-level cache
@@ -207,7 +290,7 @@ def main():
         out["calib_copy_bytes"] = nb
         del junk
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, B, cps, N, r, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(pairs, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -37,6 +37,8 @@ constexpr int D_NT = 64 * D_NB;    // one wave per u_x block
 
 struct DirectGeom {
   int N, r, K, nblk, NP, Ws, OFF, TROWS, SW;
+  int TLD;  // template row stride in dwords: NP/2 + 4, so that the 16 rows a
+            // B fragment reads start in different LDS banks
   size_t lds;
 };
 
@@ -51,7 +53,8 @@ static DirectGeom direct_geom(int N, int r) {
   g.OFF = 16 * g.nblk;               // template rows start here in LDS
   g.TROWS = g.Ws + g.OFF;            // rows s - u_y + OFF, s < Ws, u_y < 16 nblk
   g.SW = g.NP + 16 * g.nblk + 2;     // search row width incl. the fragment over-read
-  const size_t t = (size_t)g.TROWS * g.NP * 2, sb = (size_t)g.Ws * g.SW * 2;
+  g.TLD = g.NP / 2 + 4;
+  const size_t t = (size_t)g.TROWS * g.TLD * 4, sb = (size_t)g.Ws * g.SW * 2;
   const size_t c = (size_t)g.K * g.K * 4;
   g.lds = std::max(t + sb, c) + 16 * D_NB;
   return g;
@@ -64,8 +67,8 @@ __device__ __forceinline__ unsigned pack_bf16x2(float lo, float hi) {
 
 __global__ __launch_bounds__(D_NT) void match_direct_kernel(MatchJob jd, DirectGeom g) {
   extern __shared__ unsigned char dsm[];
-  unsigned* Tl = reinterpret_cast<unsigned*>(dsm);                                  // TROWS x NP/2 dwords
-  unsigned* Sl = Tl + (size_t)g.TROWS * (g.NP / 2);                                  // Ws x SW/2 dwords
+  unsigned* Tl = reinterpret_cast<unsigned*>(dsm);                                  // TROWS x TLD dwords
+  unsigned* Sl = Tl + (size_t)g.TROWS * g.TLD;                                       // Ws x SW/2 dwords
   float* Cs = reinterpret_cast<float*>(dsm);                                         // aliases T after the loop
   ArgminState* red = reinterpret_cast<ArgminState*>(dsm + g.lds - 16 * D_NB);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(D_NT) void match_direct_kernel(MatchJob jd, DirectG
             if (x < N) a = TA[(size_t)ty * jd.wA + x];
             if (x + 1 < N) b = TA[(size_t)ty * jd.wA + x + 1];
           }
-          Tl[(size_t)t * (NP / 2) + x / 2] = pack_bf16x2(a, b);
+          Tl[(size_t)t * g.TLD + x / 2] = pack_bf16x2(a, b);
         }
       }
       for (int y = wv; y < Ws; y += D_NB) {
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(D_NT) void match_direct_kernel(MatchJob jd, DirectG
             for (int n = 0; n < D_NB; ++n) {
               if (n >= nlo && n <= nhi) {
                 const int t = s - (16 * n + uyl) + g.OFF;
-                const uint4 bw = *reinterpret_cast<const uint4*>(Tl + (size_t)t * (NP / 2) + (32 * kc + 8 * kg) / 2);
+                const uint4 bw = *reinterpret_cast<const uint4*>(Tl + (size_t)t * g.TLD + (32 * kc + 8 * kg) / 2);
                 const bf16x8 B = __builtin_bit_cast(bf16x8, bw);
                 acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[n], 0, 0, 0);
               }
