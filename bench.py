@@ -37,7 +37,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFS = 157.3      # MI355X vector FP32 (packed); non-packed issue gives 78.6
+# Vector FP32 without packed instructions (the library is compiled with packed
+# FP32 disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+FP32_PEAK_TFS = 78.6
 BF16_PEAK_TFS = 2500.0     # dense BF16 MFMA
 
 
@@ -143,8 +145,8 @@ def traffic_record(kernel_key: str):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="plain_2048",
                     choices=["plain_2048", "plain_256", "precision_4096", "batch_64"])
     ap.add_argument("--path", choices=["plain", "batched", "fft", "mfma"], default=None)
