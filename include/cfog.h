@@ -189,6 +189,103 @@ int32_t cfog_plan_for(cfog_ctx* ctx, int32_t N, int32_t r, int32_t m);
  * or 0 if unsupported. */
 int32_t cfog_fft_size(int32_t N, int32_t r);
 
+/* ------------------------------------------------------------- serving
+ *
+ * A matching server: a request loop that keeps the CFOG volumes of
+ * registered image pairs resident in device memory and matches the control
+ * points of requests as they arrive (the same method as match_batch).
+ *
+ *   - Memory: the server allocates one device region of `hbm_budget` bytes.
+ *     A pair's volumes and SATs (4*m + 8 bytes per pixel of each image, plus
+ *     one SAT row and column) are computed by cfog_extract on first use and
+ *     stay resident; each admitted request holds a block for its CP list,
+ *     results and optional surfaces (16 + 24 + 4*(2r+1)^2 bytes per CP) until
+ *     it completes.
+ *   - Admission: strictly in arrival order, as soon as the request's pair is
+ *     resident (or room for it can be made) and its own block fits.  Making
+ *     room evicts the least recently used pairs that no admitted request uses;
+ *     an evicted pair is recomputed when a later request needs it.
+ *   - Continuous batching: consecutive admitted requests form one batch (up to
+ *     max_batch_cps control points and max_batch_reqs requests) that runs as
+ *     one match_batch call on one of n_slots streams; while batches run, new
+ *     arrivals are admitted into the next free slot, so their work overlaps
+ *     on the device.
+ *   - A request's result does not depend on what it is batched with: every
+ *     control point is matched by the same kernel and FFT size as alone.
+ *   - Threads: the server runs one host worker thread.  Its entry points may
+ *     be called from any host thread (they are serialised internally).
+ *   - Timestamps are CLOCK_MONOTONIC nanoseconds.
+ */
+typedef struct cfog_server cfog_server;
+
+typedef struct {
+  size_t hbm_budget;       /* bytes of device memory for volumes and request buffers */
+  int32_t n_slots;         /* batches in flight at once, 1..16 (streams) */
+  int32_t max_batch_cps;   /* control points per batch, >= 1 (and per request) */
+  int32_t max_batch_reqs;  /* requests per batch, >= 1 */
+  int32_t m;               /* orientation channels, 1..16 */
+  float sigma;             /* Gaussian std of the extraction, > 0 */
+  int32_t flags;           /* match_batch path: CFOG_PATH_BATCHED_FFT, _PLAIN_FFT or _MFMA_BF16 */
+  size_t max_batch_surf;   /* surface values per batch (and per request) staged for the host */
+} cfog_server_config;
+
+typedef struct {
+  int64_t id;              /* request id returned by cfog_server_submit */
+  int32_t status;          /* CFOG_OK, or a negative code if the request failed */
+  int32_t n_cps;
+  int64_t t_submit_ns;     /* cfog_server_submit called */
+  int64_t t_admit_ns;      /* admitted into a batch (memory granted) */
+  int64_t t_launch_ns;     /* its batch enqueued on the device */
+  int64_t t_done_ns;       /* results copied into the caller's buffers */
+  int32_t batch_reqs;      /* requests in its batch */
+  int32_t pad;
+} cfog_request_info;
+
+typedef struct {
+  int64_t submitted, completed, batches, evictions, extractions, blocked;
+  size_t arena_bytes, arena_used, arena_peak;
+  int32_t max_in_flight;   /* most batches seen on the device at once */
+  int32_t pad;
+} cfog_server_stats;
+
+/* Create a server on HIP device `device`.  cfg may be NULL for defaults
+ * (budget 80% of free device memory, 4 slots, 8192 CPs and 256 requests per
+ * batch, m = 9, sigma = 0.8, batched FFT path, 2^22 surface values).
+ * CFOG_EINVAL for out-of-range fields, CFOG_ENOMEM if the region cannot be
+ * allocated. */
+int cfog_server_create(int device, const cfog_server_config* cfg, cfog_server** out);
+
+/* Finish every submitted request, then free what the server owns.  NULL is
+ * accepted. */
+int cfog_server_destroy(cfog_server* srv);
+
+/* Register an image pair: A and B are DEVICE fp32 images [h][stride] owned by
+ * the caller, which must keep them unchanged while the server lives.  *pair_id
+ * receives the pair's id (0, 1, ...).  Volumes are computed on first use.
+ * CFOG_ENOMEM if the pair alone exceeds the budget. */
+int cfog_server_add_pair(cfog_server* srv, const float* d_imgA, int32_t hA, int32_t wA, int64_t strideA,
+                         const float* d_imgB, int32_t hB, int32_t wB, int64_t strideB, int32_t* pair_id);
+
+/* Submit a request: match n_cps control points (HOST array, copied before the
+ * call returns) of pair `pair_id` with template side N and radius r.  Results
+ * are written to the caller's HOST buffers h_out[n_cps] and, if h_surfaces is
+ * not NULL, h_surfaces[n_cps][2r+1][2r+1]; both must stay valid until the
+ * request is reported by cfog_server_poll.  *req_id receives the id.
+ * CFOG_EINVAL for bad arguments, CFOG_EUNSUPPORTED for (N, r) the path cannot
+ * match, CFOG_ENOMEM for a request that could never fit the budget or the
+ * per-batch limits, CFOG_EHIP after a device failure of the server. */
+int cfog_server_submit(cfog_server* srv, int32_t pair_id, const cfog_cp* h_cps, int32_t n_cps, int32_t N,
+                       int32_t r, cfog_result* h_out, float* h_surfaces, int64_t* req_id);
+
+/* Report up to `max` completed requests (each exactly once) into infos[];
+ * waits up to timeout_us microseconds for the first one (0: do not wait).
+ * *n_done receives the count. */
+int cfog_server_poll(cfog_server* srv, cfog_request_info* infos, int32_t max, int64_t timeout_us,
+                     int32_t* n_done);
+
+/* Counters since creation. */
+int cfog_server_get_stats(cfog_server* srv, cfog_server_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

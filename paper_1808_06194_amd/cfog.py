@@ -38,6 +38,8 @@ EXPORTS = (
     "cfog_ctx_create", "cfog_ctx_destroy", "cfog_ctx_last_error", "cfog_status_str",
     "cfog_extract", "cfog_extract_workspace_size", "match_batch_workspace_size", "match_batch",
     "cfog_max_window", "cfog_fft_size", "cfog_set_plan", "cfog_plan_for",
+    "cfog_server_create", "cfog_server_destroy", "cfog_server_add_pair", "cfog_server_submit",
+    "cfog_server_poll", "cfog_server_get_stats",
 )
 
 
@@ -53,6 +55,31 @@ class cfog_job(ctypes.Structure):
         ("volB", ctypes.c_void_p), ("satB", ctypes.c_void_p), ("hB", ctypes.c_int32), ("wB", ctypes.c_int32),
         ("cps", ctypes.c_void_p), ("n_cps", ctypes.c_int32), ("N", ctypes.c_int32), ("r", ctypes.c_int32),
         ("pad_", ctypes.c_int32), ("out", ctypes.c_void_p), ("surfaces", ctypes.c_void_p),
+    ]
+
+
+class cfog_server_config(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_size_t), ("n_slots", ctypes.c_int32), ("max_batch_cps", ctypes.c_int32),
+        ("max_batch_reqs", ctypes.c_int32), ("m", ctypes.c_int32), ("sigma", ctypes.c_float),
+        ("flags", ctypes.c_int32), ("max_batch_surf", ctypes.c_size_t),
+    ]
+
+
+class cfog_request_info(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64), ("status", ctypes.c_int32), ("n_cps", ctypes.c_int32),
+        ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64), ("t_launch_ns", ctypes.c_int64),
+        ("t_done_ns", ctypes.c_int64), ("batch_reqs", ctypes.c_int32), ("pad", ctypes.c_int32),
+    ]
+
+
+class cfog_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+        ("evictions", ctypes.c_int64), ("extractions", ctypes.c_int64), ("blocked", ctypes.c_int64),
+        ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t),
+        ("max_in_flight", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
 
@@ -86,6 +113,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cfog_set_plan.argtypes = [vp, i32, i32, i32]
     lib.cfog_plan_for.argtypes = [vp, i32, i32, i32]
     lib.cfog_plan_for.restype = i32
+    lib.cfog_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(cfog_server_config), ctypes.POINTER(vp)]
+    lib.cfog_server_destroy.argtypes = [vp]
+    lib.cfog_server_add_pair.argtypes = [vp, vp, i32, i32, i64, vp, i32, i32, i64, ctypes.POINTER(i32)]
+    lib.cfog_server_submit.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp, ctypes.POINTER(i64)]
+    lib.cfog_server_poll.argtypes = [vp, ctypes.POINTER(cfog_request_info), i32, i64, ctypes.POINTER(i32)]
+    lib.cfog_server_get_stats.argtypes = [vp, ctypes.POINTER(cfog_server_stats)]
     _lib = lib
     return lib
 
@@ -257,3 +290,120 @@ def max_window() -> int:
 def fft_size(N: int, r: int) -> int:
     """FFT side P used for template side N and radius r (0 if unsupported)."""
     return int(load().cfog_fft_size(int(N), int(r)))
+
+
+# ------------------------------------------------------------------ serving
+
+@dataclasses.dataclass
+class Completed:
+    """A finished server request: results (n, 6) int32 host array (see
+    `results_np`), optional surfaces (n, 2r+1, 2r+1) fp32, status and
+    CLOCK_MONOTONIC timestamps in ns (same clock as time.monotonic_ns)."""
+    id: int
+    status: int
+    out: "np.ndarray"
+    surfaces: Optional["np.ndarray"]
+    t_submit: int
+    t_admit: int
+    t_launch: int
+    t_done: int
+    batch_reqs: int
+
+
+def results_np(out) -> dict:
+    """Split an (n, 6) int32 host result array into named fields."""
+    return dict(dx=out[:, 0], dy=out[:, 1], best=out[:, 2].view("float32"),
+                second=out[:, 3].view("float32"), status=out[:, 4])
+
+
+class Server:
+    """Matching server: resident CFOG volumes of registered pairs, admission by
+    device memory, continuous batching over `n_slots` streams (see the serving
+    section of include/cfog.h).  Images passed to add_pair stay referenced here
+    for the server's lifetime."""
+
+    def __init__(self, hbm_budget: int, n_slots: int = 4, max_batch_cps: int = 8192, max_batch_reqs: int = 256,
+                 m: int = 9, sigma: float = 0.8, flags: int = PATH_BATCHED_FFT, max_batch_surf: int = 1 << 22,
+                 device: int = 0):
+        lib = load()
+        cfg = cfog_server_config(int(hbm_budget), int(n_slots), int(max_batch_cps), int(max_batch_reqs), int(m),
+                                 float(sigma), int(flags), int(max_batch_surf))
+        h = ctypes.c_void_p()
+        _check(lib.cfog_server_create(int(device), ctypes.byref(cfg), ctypes.byref(h)), "cfog_server_create")
+        self.handle = h
+        self._images = []
+        self._live = {}   # id -> (out, surfaces, cps) host arrays kept alive until reported
+
+    def close(self):
+        if self.handle:
+            load().cfog_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def add_pair(self, imgA: torch.Tensor, imgB: torch.Tensor) -> int:
+        for t in (imgA, imgB):
+            if t.dim() != 2 or t.dtype != torch.float32 or not t.is_cuda or t.stride(1) != 1:
+                raise ValueError("images must be 2-D row-contiguous cuda float32 tensors")
+        pid = ctypes.c_int32()
+        _check(load().cfog_server_add_pair(self.handle, imgA.data_ptr(), imgA.shape[0], imgA.shape[1],
+                                           imgA.stride(0), imgB.data_ptr(), imgB.shape[0], imgB.shape[1],
+                                           imgB.stride(0), ctypes.byref(pid)), "cfog_server_add_pair")
+        self._images.append((imgA, imgB))
+        return pid.value
+
+    def submit(self, pair: int, cps, N: int, r: int, surfaces: bool = False) -> int:
+        """Submit control points `cps` ((n, 4) int32 array-like of x, y, bx, by)."""
+        import numpy as np
+        c = np.ascontiguousarray(np.asarray(cps, dtype=np.int32).reshape(-1, 4))
+        n = c.shape[0]
+        out = np.zeros((n, 6), np.int32)
+        K = 2 * int(r) + 1
+        surf = np.zeros((n, K, K), np.float32) if surfaces else None
+        rid = ctypes.c_int64()
+        _check(load().cfog_server_submit(self.handle, int(pair), c.ctypes.data, n, int(N), int(r),
+                                         out.ctypes.data, surf.ctypes.data if surf is not None else None,
+                                         ctypes.byref(rid)), "cfog_server_submit")
+        self._live[rid.value] = (out, surf)
+        return rid.value
+
+    def poll(self, max_n: int = 1024, timeout_us: int = 0) -> List[Completed]:
+        infos = (cfog_request_info * max(1, max_n))()
+        n = ctypes.c_int32()
+        _check(load().cfog_server_poll(self.handle, infos, int(max_n), int(timeout_us), ctypes.byref(n)),
+               "cfog_server_poll")
+        done = []
+        for i in range(n.value):
+            f = infos[i]
+            out, surf = self._live.pop(f.id)
+            done.append(Completed(f.id, f.status, out, surf, f.t_submit_ns, f.t_admit_ns, f.t_launch_ns,
+                                  f.t_done_ns, f.batch_reqs))
+        return done
+
+    def wait(self, ids, timeout_s: float = 60.0) -> dict:
+        """Poll until every id in `ids` is reported; returns {id: Completed}."""
+        import time
+        want, got = set(ids), {}
+        t_end = time.monotonic() + timeout_s
+        while want - got.keys():
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"{len(want - got.keys())} requests still pending")
+            for c in self.poll(timeout_us=10000):
+                got[c.id] = c
+        return got
+
+    def stats(self) -> dict:
+        st = cfog_server_stats()
+        _check(load().cfog_server_get_stats(self.handle, ctypes.byref(st)), "cfog_server_get_stats")
+        return {k: getattr(st, k) for k, _ in cfog_server_stats._fields_ if k != "pad"}

@@ -68,5 +68,7 @@ namespace cfog {
 size_t direct_workspace_bytes(const cfog_job* jobs, int n_jobs, int m, int num_cus);
 // 0 on success, -1 unsupported configuration, -2 HIP error.
 int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, void* ws, int num_cus, hipStream_t st);
+// Whether the direct path supports template side N with radius r.
+bool direct_supported(int N, int r);
 
 }  // namespace cfog

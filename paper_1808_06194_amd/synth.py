@@ -60,13 +60,23 @@ def make_canvas(spec: PairSpec, rng: np.random.Generator) -> np.ndarray:
         ey = np.exp(-((np.arange(y0, y1) - cy[i]) ** 2) / (2 * sg[i] ** 2))
         ex = np.exp(-((np.arange(x0, x1) - cx[i]) ** 2) / (2 * sg[i] ** 2))
         A[y0:y1, x0:x1] += amp[i] * np.outer(ey, ex)
+    # rectangles: value v added on [y0, y0+h) x [x0, x0+w) (clipped to the
+    # canvas), accumulated as +-v corner impulses and two cumulative sums so
+    # that the cost does not grow with the rectangle areas
     side_hi = max(8, spec.W // 4)
+    corners = np.zeros((Hc + 1, Wc + 1), np.float64)
     for _ in range(spec.n_rects):
         h = int(rng.integers(8, side_hi + 1))
         w = int(rng.integers(8, side_hi + 1))
         y0 = int(rng.integers(0, Hc))
         x0 = int(rng.integers(0, Wc))
-        A[y0:y0 + h, x0:x0 + w] += rng.uniform(0.0, 1.0)
+        v = rng.uniform(0.0, 1.0)
+        y1, x1 = min(Hc, y0 + h), min(Wc, x0 + w)
+        corners[y0, x0] += v
+        corners[y0, x1] -= v
+        corners[y1, x0] -= v
+        corners[y1, x1] += v
+    A += np.cumsum(np.cumsum(corners, axis=0), axis=1)[:Hc, :Wc]
     A += rng.normal(0.0, spec.noise_std, A.shape)
     return A
 
@@ -149,18 +159,58 @@ def area_scaled_spec(side: int, s_max: int, base=(256, 40, 20), sigma=(3.0, 15.0
     return PairSpec(side, side, max(1, int(round(nb * f))), sigma, max(1, int(round(nr * f))), s_max)
 
 
+def _batch_pair(args):
+    spec, seed, j = args
+    return make_pair(spec, (seed, j))
+
+
 def batch_workload(n_pairs: int = 64, sides=(512, 1024, 2048, 4096), seed: int = 2,
-                   max_cps: int = 600, min_cps: int = 50):
-    """Heterogeneous batch: list of dicts (A, B, shift, cps, N, r) per pair."""
+                   max_cps: int = 600, min_cps: int = 50, pool_map=map):
+    """Heterogeneous batch: list of dicts (A, B, shift, cps, N, r) per pair.
+    `pool_map` may be a process pool's map (each pair has its own seed)."""
     meta = _rng(seed, 999)
-    out = []
+    draws = []
     for j in range(n_pairs):
         side = int(meta.choice(sides))
         N = 2 * int(meta.integers(20, 61))
         r = int(meta.integers(5, 31))
         n = int(meta.integers(min_cps, max_cps + 1))
-        spec = area_scaled_spec(side, min(8, r))
-        A, B, s = make_pair(spec, (seed, j))
+        draws.append((side, N, r, n, area_scaled_spec(side, min(8, r))))
+    imgs = list(pool_map(_batch_pair, [(d[4], seed, j) for j, d in enumerate(draws)]))
+    out = []
+    for j, ((side, N, r, n, _), (A, B, s)) in enumerate(zip(draws, imgs)):
         cps = random_cps(_rng(seed, j, 1), side, side, N, r, n)
         out.append(dict(A=A, B=B, shift=s, cps=cps, N=N, r=r))
+    return out
+
+
+# ---------------------------------------------------------------- serving
+#
+# Serving recipe: 32 resident pairs, 8 each of 1024^2, 2048^2, 4096^2 and
+# 8192^2 (densities area-scaled from plain_256, |shift| <= 8, seeds (4, j));
+# requests arrive as a Poisson process; each names a pair uniformly and asks
+# for 1-500 control points at uniform valid positions with template side
+# 2 * U{20..64} and radius U{5..32}.
+
+SERVE_SIDES = (1024,) * 8 + (2048,) * 8 + (4096,) * 8 + (8192,) * 8
+
+
+def serve_pair(j: int, sides=SERVE_SIDES):
+    """(A, B, shift) of serving pair j."""
+    return make_pair(area_scaled_spec(sides[j], 8), (4, j))
+
+
+def serve_requests(n: int, rate: float, sides=SERVE_SIDES, seed: int = 999, max_cps: int = 500):
+    """n requests with Poisson arrivals of `rate` per second: list of dicts
+    (t arrival offset in s, pair, cps (k, 4) int32, N, r)."""
+    rng = _rng(4, seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n))
+    out = []
+    for i in range(n):
+        p = int(rng.integers(0, len(sides)))
+        N = 2 * int(rng.integers(20, 65))
+        r = int(rng.integers(5, 33))
+        k = int(rng.integers(1, max_cps + 1))
+        cps = random_cps(rng, sides[p], sides[p], N, r, k)
+        out.append(dict(t=float(t[i]), pair=p, cps=cps, N=N, r=r))
     return out

@@ -84,3 +84,37 @@ def test_dft_codelets_host_build(tmp_path):
     assert r.returncode == 0, r.stderr[-2000:]
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout
+
+
+def test_server_structs_match_header():
+    from paper_1808_06194_amd import cfog
+    assert ctypes.sizeof(cfog.cfog_server_config) == 40
+    assert cfog.cfog_server_config.max_batch_surf.offset == 32
+    assert ctypes.sizeof(cfog.cfog_request_info) == 56
+    assert cfog.cfog_request_info.batch_reqs.offset == 48
+    assert ctypes.sizeof(cfog.cfog_server_stats) == 80
+
+
+def test_server_null_handles_are_rejected(lib):
+    from paper_1808_06194_amd import cfog
+    i32, i64 = ctypes.c_int32(), ctypes.c_int64()
+    assert lib.cfog_server_create(0, None, None) == cfog.CFOG_EINVAL
+    assert lib.cfog_server_destroy(None) == cfog.CFOG_OK
+    assert lib.cfog_server_add_pair(None, None, 8, 8, 8, None, 8, 8, 8, ctypes.byref(i32)) == cfog.CFOG_EINVAL
+    assert lib.cfog_server_submit(None, 0, None, 1, 8, 1, None, None, ctypes.byref(i64)) == cfog.CFOG_EINVAL
+    assert lib.cfog_server_poll(None, None, 0, 0, ctypes.byref(i32)) == cfog.CFOG_EINVAL
+    assert lib.cfog_server_get_stats(None, None) == cfog.CFOG_EINVAL
+
+
+def test_server_scheduler_simulation(tmp_path):
+    """The serving scheduler (admission by memory, FIFO continuous batching,
+    LRU eviction) driven by a simulated executor, built for the host."""
+    src = os.path.join(ROOT, "tests", "cpp", "sched_sim.cpp")
+    exe = tmp_path / "sched_sim"
+    inc = os.path.join(ROOT, "paper_1808_06194_amd", "csrc")
+    r = subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-I", inc, src,
+                        "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
+    assert "ALL OK" in r.stdout
