@@ -68,17 +68,35 @@ __device__ __forceinline__ double wave_incl_scan(double v) {
   return v;
 }
 
+// LDS geometry of the extraction tile for Gaussian radius R.
+template <int R>
+struct ExTile {
+  static constexpr int IW = EX_TX + 2 * R + 2, IH = EX_TY + 2 * R + 2;  // image tile (+1 for the gradient)
+  static constexpr int GW = EX_TX + 2 * R, GH = EX_TY + 2 * R;          // gradient / channel tile
+  static constexpr int NQ = (4 + 2 * R + 3) / 4;  // 16-byte reads per 4 horizontal outputs
+  // channel row stride: a multiple of 4 floats covering the last quad's reads
+  static constexpr int GWP = ((GW + 3) / 4 * 4) > (EX_TX - 4 + 4 * NQ) ? ((GW + 3) / 4 * 4) : (EX_TX - 4 + 4 * NQ);
+  static constexpr int NPAIR = GH * GWP / 2;      // channel values computed two at a time
+  static constexpr int NQUAD = GH * EX_TX / 4;    // horizontal outputs four at a time
+  static constexpr size_t IMG = ((size_t)IH * IW + 3) / 4 * 4;   // floats
+  static constexpr size_t GXY = (size_t)GH * GWP;                // float2
+  static constexpr size_t G = (size_t)GH * GWP;                  // floats
+  static constexpr size_t HB = 2 * (size_t)GH * EX_TX;           // floats (two channels)
+  static constexpr size_t BYTES = 4 * IMG + 8 * GXY + 4 * G + 4 * HB + 8 * 4 * 64;
+};
+
 template <int R>
 __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
-  extern __shared__ float lds[];
-  constexpr int IW = EX_TX + 2 * R + 2, IH = EX_TY + 2 * R + 2;  // image tile
-  constexpr int GW = EX_TX + 2 * R, GH = EX_TY + 2 * R;          // gradient tile
+  using T = ExTile<R>;
+  constexpr int IW = T::IW, IH = T::IH, GW = T::GW, GH = T::GH, GWP = T::GWP;
+  extern __shared__ float4 lds4[];
+  float* lds = reinterpret_cast<float*>(lds4);
   const int m = a.m;
   float* img = lds;                                              // IH * IW
-  float2* gxy = reinterpret_cast<float2*>(img + ((IH * IW + 1) & ~1));  // GH * GW
-  float* G = reinterpret_cast<float*>(gxy + GH * GW);            // GH * GW (+1 pad)
-  float* Hb = G + ((GH * GW + 1) & ~1);                           // 2 * GH * EX_TX
-  double* qx = reinterpret_cast<double*>(Hb + 2 * GH * EX_TX);   // 4 x 64 wave carries
+  float2* gxy = reinterpret_cast<float2*>(img + T::IMG);         // GH * GWP
+  float* G = reinterpret_cast<float*>(gxy + T::GXY);             // GH * GWP
+  float* Hb = G + T::G;                                          // 2 * GH * EX_TX
+  double* qx = reinterpret_cast<double*>(Hb + T::HB);            // 4 x 64 wave carries
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * EX_TX, y0 = blockIdx.y * EX_TY;
   const int H = a.H, W = a.W;
@@ -108,16 +126,28 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   }
   __syncthreads();
 
-  // B. gradients at clamped positions of the halo tile
-  const int oy = y0 - R - 1, ox = x0 - R - 1;  // global coords of img[0][0]
-  for (int i = tid; i < GH * GW; i += EX_NT) {
-    int r = i / GW, c = i - r * GW;
-    int Yc = clampi(y0 - R + r, 0, H - 1), Xc = clampi(x0 - R + c, 0, W - 1);
-    int yl = Yc - oy, xl = Xc - ox;
-    int xp = clampi(Xc + 1, 0, W - 1) - ox, xm = clampi(Xc - 1, 0, W - 1) - ox;
-    int yp = clampi(Yc + 1, 0, H - 1) - oy, ym = clampi(Yc - 1, 0, H - 1) - oy;
-    gxy[i] = make_float2(img[yl * IW + xp] - img[yl * IW + xm], img[yp * IW + xl] - img[ym * IW + xl]);
+  // B. gradients of the halo tile.  Interior tiles read their neighbours
+  // directly; tiles at the border take them at clamped positions, which is
+  // what clamp-to-edge gradient and Gaussian borders read.
+  const bool interior = x0 - R - 1 >= 0 && y0 - R - 1 >= 0 && x0 + EX_TX + R <= W - 1 && y0 + EX_TY + R <= H - 1;
+  if (interior) {
+    for (int i = tid; i < GH * GW; i += EX_NT) {
+      const int r = i / GW, c = i - r * GW;
+      const float* p = img + (r + 1) * IW + c + 1;
+      gxy[r * GWP + c] = make_float2(p[1] - p[-1], p[IW] - p[-IW]);
+    }
+  } else {
+    const int oy = y0 - R - 1, ox = x0 - R - 1;  // global coords of img[0][0]
+    for (int i = tid; i < GH * GW; i += EX_NT) {
+      int r = i / GW, c = i - r * GW;
+      int Yc = clampi(y0 - R + r, 0, H - 1), Xc = clampi(x0 - R + c, 0, W - 1);
+      int yl = Yc - oy, xl = Xc - ox;
+      int xp = clampi(Xc + 1, 0, W - 1) - ox, xm = clampi(Xc - 1, 0, W - 1) - ox;
+      int yp = clampi(Yc + 1, 0, H - 1) - oy, ym = clampi(Yc - 1, 0, H - 1) - oy;
+      gxy[r * GWP + c] = make_float2(img[yl * IW + xp] - img[yl * IW + xm], img[yp * IW + xl] - img[ym * IW + xl]);
+    }
   }
+  // the padding columns of gxy feed only channel values that no output reads
   __syncthreads();
 
   // C. per channel: oriented gradient, horizontal then vertical Gaussian; the
@@ -130,12 +160,16 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
 #pragma unroll
   for (int p = 0; p < EX_RUN; ++p) { q[p] = 0.0; g0[p] = g1[p] = pm2[p] = pm1[p] = 0.f; }
   const size_t plane = (size_t)H * W;
+  float* const vout = a.vol + (size_t)min(y0 + orow, H - 1) * W + min(gxx, W - 1);
+  bool vok[EX_RUN];
+#pragma unroll
+  for (int o = 0; o < EX_RUN; ++o) vok[o] = y0 + orow + o < H && gxx < W;
   auto emit = [&](int k, const float (&d)[EX_RUN]) {
+    float* p = vout + k * plane;
 #pragma unroll
     for (int o = 0; o < EX_RUN; ++o) {
-      const int gyy = y0 + orow + o;
-      if (gyy < H && gxx < W) {
-        a.vol[k * plane + (size_t)gyy * W + gxx] = d[o];
+      if (vok[o]) {
+        p[(size_t)o * W] = d[o];
         q[o] = fma((double)d[o], (double)d[o], q[o]);
       }
     }
@@ -143,20 +177,43 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   for (int k = 0; k < m; ++k) {
     const float ck = a.cs[k], sk = a.sn[k];
     float* hb = Hb + (k & 1) * GH * EX_TX;
-    // oriented gradient of channel k at every pixel of the halo tile
-    for (int i = tid; i < GH * GW; i += EX_NT) {
-      const float2 g = gxy[i];
-      G[i] = fabsf(fmaf(ck, g.x, sk * g.y));
+    // oriented gradient of channel k at every pixel of the halo tile, two at a time
+#pragma unroll
+    for (int it = 0; it < (T::NPAIR + EX_NT - 1) / EX_NT; ++it) {
+      const int i = tid + it * EX_NT;
+      if (T::NPAIR % EX_NT == 0 || i < T::NPAIR) {
+        const float4 g = lds4[(T::IMG / 4) + i];  // gxy[2i], gxy[2i+1]
+        reinterpret_cast<float2*>(G)[i] = make_float2(fabsf(fmaf(ck, g.x, sk * g.y)), fabsf(fmaf(ck, g.z, sk * g.w)));
+      }
     }
     __syncthreads();
-    // horizontal pass: consecutive lanes on consecutive columns
-    for (int i = tid; i < GH * EX_TX; i += EX_NT) {
-      const int r = i / EX_TX, c = i - r * EX_TX;
-      const float* row = G + r * GW + c + R;
-      float s = w[0] * row[0];
+    // horizontal pass: each thread four consecutive outputs of one row from
+    // 16-byte reads (16 threads cover a row)
 #pragma unroll
-      for (int j = 1; j <= R; ++j) s = fmaf(w[j], row[-j] + row[j], s);
-      hb[i] = s;
+    for (int it = 0; it < (T::NQUAD + EX_NT - 1) / EX_NT; ++it) {
+      const int qd = tid + it * EX_NT;
+      if (T::NQUAD % EX_NT == 0 || qd < T::NQUAD) {
+        const int r = qd >> 4, c4 = (qd & 15) * 4;
+        const float4* src = reinterpret_cast<const float4*>(G + r * GWP + c4);
+        float x[4 * T::NQ];
+#pragma unroll
+        for (int u = 0; u < T::NQ; ++u) {
+          const float4 v = src[u];
+          x[4 * u] = v.x;
+          x[4 * u + 1] = v.y;
+          x[4 * u + 2] = v.z;
+          x[4 * u + 3] = v.w;
+        }
+        float o4[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float s = w[0] * x[j + R];
+#pragma unroll
+          for (int t = 1; t <= R; ++t) s = fmaf(w[t], x[j + R - t] + x[j + R + t], s);
+          o4[j] = s;
+        }
+        *reinterpret_cast<float4*>(hb + r * EX_TX + c4) = make_float4(o4[0], o4[1], o4[2], o4[3]);
+      }
     }
     __syncthreads();
     float cur[EX_RUN];
@@ -173,7 +230,7 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
         cur[o] = s;
       }
     }
-    // circular [1,2,1]/4 along orientation: D_{k-1} = Gs_{k-2}/4 + Gs_{k-1}/2 + Gs_k/4
+  // circular [1,2,1]/4 along orientation: D_{k-1} = Gs_{k-2}/4 + Gs_{k-1}/2 + Gs_k/4
     if (k == 0) {
 #pragma unroll
       for (int o = 0; o < EX_RUN; ++o) g0[o] = cur[o];
@@ -230,7 +287,10 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
 
 // Kernel 2: exclusive prefixes of the right columns along each image row (one
 // wave per row, lanes across tiles) and of the bottom rows along each image
-// column (one thread per column, 8 rows of loads in flight).
+// column (64 columns per workgroup, lanes across columns, the tile rows split
+// between the 4 waves: each wave sums its rows, the partial sums are
+// exchanged in LDS, then each wave writes its exclusive prefixes; no load
+// waits on another).
 constexpr int SAT_NT = 256;
 
 __device__ __forceinline__ double wave_excl_scan(double v, double& total) {
@@ -254,20 +314,38 @@ __global__ __launch_bounds__(SAT_NT) void sat_carry_kernel(double* rc, double* b
       if (j < ntx) p[j] = ex + carry;
       carry += tot;
     }
-  } else {
-    const int x = (blockIdx.x - row_blocks) * SAT_NT + threadIdx.x;
-    if (x >= W) return;
-    double run = 0.0;
+    return;
+  }
+  __shared__ double part[SAT_NT / 64][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x = (blockIdx.x - row_blocks) * 64 + lane;
+  const int per = (nty + SAT_NT / 64 - 1) / (SAT_NT / 64);
+  const int i0 = wv * per, i1 = min(nty, i0 + per);
+  double sum = 0.0;
+  if (x < W) {
     constexpr int CH = 8;
-    for (int i0 = 0; i0 < nty; i0 += CH) {
+    for (int i = i0; i < i1; i += CH) {
       double v[CH];
 #pragma unroll
-      for (int u = 0; u < CH; ++u) v[u] = (i0 + u < nty) ? bt[(size_t)(i0 + u) * W + x] : 0.0;
+      for (int u = 0; u < CH; ++u) v[u] = (i + u < i1) ? bt[(size_t)(i + u) * W + x] : 0.0;
 #pragma unroll
-      for (int u = 0; u < CH; ++u) {
-        if (i0 + u < nty) bt[(size_t)(i0 + u) * W + x] = run;
-        run += v[u];
-      }
+      for (int u = 0; u < CH; ++u) sum += v[u];
+    }
+  }
+  part[wv][lane] = sum;
+  __syncthreads();
+  if (x >= W) return;
+  double run = 0.0;
+  for (int k = 0; k < wv; ++k) run += part[k][lane];
+  constexpr int CH = 8;
+  for (int i = i0; i < i1; i += CH) {
+    double v[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) v[u] = (i + u < i1) ? bt[(size_t)(i + u) * W + x] : 0.0;
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      if (i + u < i1) bt[(size_t)(i + u) * W + x] = run;
+      run += v[u];
     }
   }
 }
@@ -314,11 +392,18 @@ __global__ __launch_bounds__(EX_NT) void sat_fix_kernel(double* sat, const doubl
 
 static size_t lds_bytes(int m, int R) {
   (void)m;
-  const int IW = EX_TX + 2 * R + 2, IH = EX_TY + 2 * R + 2;
-  const int GW = EX_TX + 2 * R, GH = EX_TY + 2 * R;
-  return sizeof(float) * (((size_t)IH * IW + 1) & ~(size_t)1) + sizeof(float2) * (size_t)GH * GW +
-         sizeof(float) * (((size_t)GH * GW + 1) & ~(size_t)1) + sizeof(float) * 2 * (size_t)GH * EX_TX +
-         sizeof(double) * 4 * 64;
+  switch (R) {
+    case 0: return ExTile<0>::BYTES;
+    case 1: return ExTile<1>::BYTES;
+    case 2: return ExTile<2>::BYTES;
+    case 3: return ExTile<3>::BYTES;
+    case 4: return ExTile<4>::BYTES;
+    case 5: return ExTile<5>::BYTES;
+    case 6: return ExTile<6>::BYTES;
+    case 7: return ExTile<7>::BYTES;
+    case 8: return ExTile<8>::BYTES;
+    default: return (size_t)-1;
+  }
 }
 
 size_t extract_lds_bytes(int m, int R) { return lds_bytes(m, R); }
@@ -383,8 +468,8 @@ int launch_extract(const float* img, int64_t stride, int H, int W, int m, float 
   }
   if (rc != 0 || !sat) return rc;
   const int row_blocks = (H + SAT_NT / 64 - 1) / (SAT_NT / 64);
-  hipLaunchKernelGGL(sat_carry_kernel, dim3(row_blocks + (W + SAT_NT - 1) / SAT_NT), dim3(SAT_NT), 0, st, a.rc,
-                     a.bt, H, W, a.ntx, a.nty, row_blocks);
+  hipLaunchKernelGGL(sat_carry_kernel, dim3(row_blocks + (W + 63) / 64), dim3(SAT_NT), 0, st, a.rc, a.bt, H, W,
+                     a.ntx, a.nty, row_blocks);
   hipLaunchKernelGGL(sat_fix_kernel, dim3(a.ntx, a.nty), dim3(EX_NT), 0, st, sat, a.rc, a.bt, H, W, a.ntx);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }

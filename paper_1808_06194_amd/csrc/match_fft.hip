@@ -49,6 +49,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// An integer the compiler must treat as computed here: addresses derived
+// from it are rebuilt near their use instead of being hoisted out of the
+// task loop and kept live (which costs registers).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 template <int P_, int R1_, int R2_, int NT_, bool TG_>
 struct FftCfg {
   static constexpr int P = P_, R1 = R1_, R2 = R2_, NT = NT_;
@@ -86,7 +94,7 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const float* __restr
   constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH;
   const int nrp = (nrows + 1) >> 1;
   for (int q = L.g; q < nrp; q += C::NG) {
-    float2* base = X + 2 * q * PH;
+    float2* base = X + 2 * opaque(q) * PH;
     if (L.li < R2) {
       const int j = L.li;
       const float* r0 = src + (int64_t)(2 * q) * ld;
@@ -150,7 +158,7 @@ __device__ __forceinline__ void ypass_fwd(const Lane<C>& L, float2* X, const flo
     constexpr int rnd = decltype(rndI)::value;
     const int kx = L.g + rnd * C::NG;
     if (kx < PH) {
-      float2* col = X + kx;
+      float2* col = X + opaque(kx);
       if (L.li < R2) {
         const int j = L.li;
         float2 v[R1];
@@ -227,7 +235,7 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   for (int rnd = 0; rnd < KF; ++rnd) {
     const int kx = L.g + rnd * C::NG;
     if (kx < PH) {
-      float2* col = X + kx;
+      float2* col = X + opaque(kx);
       if (L.li < R1) {
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) col[(L.li + R1 * k2) * PH] = acc[rnd][k2];
@@ -270,7 +278,7 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   float* Cs = reinterpret_cast<float*>(SC + npair * P);
   const float inv = 1.0f / ((float)P * (float)P);
   for (int p = L.g; p < npair; p += C::NG) {
-    float2* sc = SC + p * P;
+    float2* sc = SC + opaque(p) * P;
     if (L.li < R2) {
       const int j = L.li;
       const float2* v1r = X + (2 * p) * PH;
@@ -350,9 +358,12 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
 }
 
 // ------------------------------------------------------------------ plans
-//  P, R1, R2, NT, TG  (R1 >= R2 keeps the per-lane outputs of stage 2 small;
-//  NT chosen so that the groups cover the P/2+1 columns in one round where the
-//  registers allow)
+//  P, R1, R2, NT, TG  (R1 >= R2 keeps the per-lane outputs of stage 2 small).
+//  NT is set per size from measurement: as many waves as the registers allow
+//  without starving the column rounds (P = 96..108 at 768 threads take every
+//  column in one round; P >= 128 at 512 threads beat 256-384 threads despite
+//  some register spilling at P >= 180); the largest sizes park T^ in global
+//  memory.
 #define CFOG_PLANS(X)            \
   X(16, 4, 4, 64, false)         \
   X(24, 6, 4, 128, false)        \
@@ -364,15 +375,15 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
   X(72, 9, 8, 384, false)        \
   X(80, 10, 8, 448, false)       \
   X(90, 10, 9, 512, false)       \
-  X(96, 12, 8, 512, false)       \
-  X(100, 10, 10, 512, false)     \
-  X(108, 12, 9, 512, false)      \
+  X(96, 12, 8, 768, false)       \
+  X(100, 10, 10, 768, false)     \
+  X(108, 12, 9, 768, false)      \
   X(120, 12, 10, 512, false)     \
-  X(128, 16, 8, 384, false)      \
+  X(128, 16, 8, 512, false)      \
   X(144, 12, 12, 512, false)     \
-  X(160, 16, 10, 256, true)      \
-  X(180, 15, 12, 256, true)      \
-  X(192, 16, 12, 256, true)
+  X(160, 16, 10, 512, true)      \
+  X(180, 15, 12, 512, true)      \
+  X(192, 16, 12, 512, true)
 
 #define CFOG_CFG(P_, R1_, R2_, NT_, TG_) FftCfg<P_, R1_, R2_, NT_, TG_>
 
