@@ -424,10 +424,15 @@ size_t max_tg_bytes(int N, int r) {
   return m;
 }
 
+// Workgroups of each plan resident per CU, from the runtime's occupancy
+// calculator (registers, LDS and waves); filled by init_match_fft_attributes.
+static int g_plan_occupancy[64];
+
 int plan_slots(const FftPlan* p, int num_cus) {
-  const int by_lds = (int)(kMaxLds / p->lds);
-  const int by_waves = 32 / (p->NT / 64);
-  return num_cus * std::max(1, std::min(by_lds, by_waves));
+  const int i = (int)(p - kPlans);
+  int per_cu = (i >= 0 && i < 64) ? g_plan_occupancy[i] : 0;
+  if (per_cu <= 0) per_cu = std::max(1, std::min((int)(kMaxLds / p->lds), 32 / (p->NT / 64)));
+  return num_cus * per_cu;
 }
 
 template <class C>
@@ -440,11 +445,19 @@ static int launch_t(const MatchJob& job0, const MatchJob* jobs, const int2* task
 }
 
 int init_match_fft_attributes() {
+  int idx = 0;
 #define CFOG_PLAN_ATTR(P_, R1_, R2_, NT_, TG_)                                                               \
-  if (hipFuncSetAttribute((const void*)match_fft_kernel<CFOG_CFG(P_, R1_, R2_, NT_, TG_)>,                   \
-                          hipFuncAttributeMaxDynamicSharedMemorySize,                                        \
-                          (int)CFOG_CFG(P_, R1_, R2_, NT_, TG_)::LDS) != hipSuccess)                         \
-    return -2;
+  {                                                                                                          \
+    using Cfg = CFOG_CFG(P_, R1_, R2_, NT_, TG_);                                                            \
+    if (hipFuncSetAttribute((const void*)match_fft_kernel<Cfg>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
+                            (int)Cfg::LDS) != hipSuccess)                                                    \
+      return -2;                                                                                             \
+    int n = 0;                                                                                               \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, match_fft_kernel<Cfg>, Cfg::NT, Cfg::LDS) !=        \
+        hipSuccess)                                                                                          \
+      n = 0;                                                                                                 \
+    g_plan_occupancy[idx++] = n;                                                                             \
+  }
   CFOG_PLANS(CFOG_PLAN_ATTR)
 #undef CFOG_PLAN_ATTR
   return 0;
