@@ -11,13 +11,17 @@
 //   K = (c, s, tx)  (all channels, all search rows, the template columns),
 // so every output tile of C accumulates in MFMA registers with no scatter.
 // v_mfma_f32_16x16x32_bf16 tiles: M and N are padded to 16, the template
-// width to 32.  Per channel the template (bf16, with zero rows above and below
-// so that s - u_y never leaves it) and the search window (bf16) are staged in
-// LDS; wave w owns the u_x block w and all u_y blocks.  Operand fragments:
-//   A (lane l): 8 bf16 of search row s from column 32kc + 8(l/16) + u_x,
-//      read as 5 aligned dwords and realigned by a byte shift;
-//   B (lane l): 8 bf16 of template row s - u_y, columns 32kc + 8(l/16) .. +7,
-//      one aligned 16-byte LDS read.
+// width to 32.  Per channel the template (bf16, with 15 zero rows above and
+// below) and the search window (bf16) are staged in LDS.  Every wave keeps
+// all (2r+1)^2 outputs in registers (up to 5 x 5 tiles) and takes every 8th
+// search row s, so per (s, 32-column chunk) it reads 5 A and at most 5 B
+// fragments for up to 25 MFMAs; the waves' partial sums are added in wave
+// order at the end (deterministic).  Operand fragments:
+//   A (lane l, u_x block m): 8 bf16 of search row s from column
+//      32kc + 8(l/16) + 16m + l%16, read as 5 aligned dwords and realigned by a
+//      byte shift;
+//   B (lane l, u_y block n): 8 bf16 of template row s - 16n - l%16, columns
+//      32kc + 8(l/16) .. +7, one aligned 16-byte LDS read.
 // Inputs are rounded to BF16 (relative error 2^-9 each), so |C_bf16 - C| <=
 // 2^-8 sum |T S| <= 2^-9 (E1 + E2): the SSD surface is within 2^-8 (E1 + E2)
 // of the exact one, against ~1e-6 for the FP32 FFT path.
@@ -33,13 +37,18 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int D_NB = 5;            // max 16-wide blocks of u_x (and u_y): 2r+1 <= 80
-constexpr int D_NT = 64 * D_NB;    // one wave per u_x block
+constexpr int D_NW = 8;            // waves per workgroup
+constexpr int D_NT = 64 * D_NW;
+constexpr int D_TPAD = 15;         // zero template rows above and below
+constexpr int D_RB = 4;            // rows staged per batch of loads
 
 struct DirectGeom {
-  int N, r, K, nblk, NP, Ws, OFF, TROWS, SW;
-  int TLD;  // template row stride in dwords: NP/2 + 4, so that the 16 rows a
-            // B fragment reads start in different LDS banks
-  size_t lds;
+  int N, r, K, nblk, NP, Ws;
+  int TROWS;  // template rows staged: N + 2 * D_TPAD (row tr holds template row tr - D_TPAD)
+  int TLD;    // template row stride in dwords, NP/2 + 4: an odd multiple of 4, so the
+              // 16 rows one B fragment reads start in 16 different 4-bank groups
+  int SLD;    // search row stride in dwords (NP + 16 nblk + 2 bf16: the fragment over-read)
+  size_t t_bytes, lds;
 };
 
 static DirectGeom direct_geom(int N, int r) {
@@ -50,13 +59,13 @@ static DirectGeom direct_geom(int N, int r) {
   g.nblk = (g.K + 15) / 16;
   g.NP = (N + 31) / 32 * 32;
   g.Ws = N + 2 * r;
-  g.OFF = 16 * g.nblk;               // template rows start here in LDS
-  g.TROWS = g.Ws + g.OFF;            // rows s - u_y + OFF, s < Ws, u_y < 16 nblk
-  g.SW = g.NP + 16 * g.nblk + 2;     // search row width incl. the fragment over-read
+  g.TROWS = N + 2 * D_TPAD;
   g.TLD = g.NP / 2 + 4;
-  const size_t t = (size_t)g.TROWS * g.TLD * 4, sb = (size_t)g.Ws * g.SW * 2;
-  const size_t c = (size_t)g.K * g.K * 4;
-  g.lds = std::max(t + sb, c) + 16 * D_NB;
+  g.SLD = (g.NP + 16 * g.nblk + 2) / 2;
+  g.t_bytes = (size_t)g.TROWS * g.TLD * 4;
+  const size_t sb = (size_t)g.Ws * g.SLD * 4;
+  const size_t c = (size_t)g.K * g.K * 4 + 16 * D_NW;
+  g.lds = std::max(g.t_bytes + sb, c);
   return g;
 }
 
@@ -65,65 +74,85 @@ __device__ __forceinline__ unsigned pack_bf16x2(float lo, float hi) {
   return (unsigned)__builtin_bit_cast(unsigned short, a) | ((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
 }
 
+// Stage `nrows` rows of `ncols` valid fp32 values (row r at src + r * ld when
+// valid(r), zeros otherwise) as packed bf16 pairs, `width` bf16 per row, into
+// dst with a row stride of `ldd` dwords.  Rows r = wv, wv + NW, ...; the
+// loads of D_RB rows are issued before their conversions.
+template <class Valid>
+__device__ __forceinline__ void stage_rows(unsigned* dst, int ldd, int nrows, int width, const float* src,
+                                           size_t ld, int ncols, Valid valid, int wv, int lane) {
+  for (int r0 = wv; r0 < nrows; r0 += D_NW * D_RB) {
+    for (int x = 2 * lane; x < width; x += 128) {
+      float a[D_RB], b[D_RB];
+#pragma unroll
+      for (int u = 0; u < D_RB; ++u) {
+        const int r = r0 + u * D_NW;
+        a[u] = b[u] = 0.f;
+        if (r < nrows && valid(r)) {
+          const float* p = src + (size_t)r * ld;
+          if (x < ncols) a[u] = p[x];
+          if (x + 1 < ncols) b[u] = p[x + 1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < D_RB; ++u) {
+        const int r = r0 + u * D_NW;
+        if (r < nrows) dst[(size_t)r * ldd + x / 2] = pack_bf16x2(a[u], b[u]);
+      }
+    }
+  }
+}
+
+template <int NB>
 __global__ __launch_bounds__(D_NT) void match_direct_kernel(MatchJob jd, DirectGeom g) {
   extern __shared__ unsigned char dsm[];
-  unsigned* Tl = reinterpret_cast<unsigned*>(dsm);                                  // TROWS x TLD dwords
-  unsigned* Sl = Tl + (size_t)g.TROWS * g.TLD;                                       // Ws x SW/2 dwords
-  float* Cs = reinterpret_cast<float*>(dsm);                                         // aliases T after the loop
-  ArgminState* red = reinterpret_cast<ArgminState*>(dsm + g.lds - 16 * D_NB);
+  unsigned* Tl = reinterpret_cast<unsigned*>(dsm);                             // TROWS x TLD dwords
+  unsigned* Sl = reinterpret_cast<unsigned*>(dsm + g.t_bytes);                 // Ws x SLD dwords
+  float* Cs = reinterpret_cast<float*>(dsm);                                    // K x K, after the channels
+  ArgminState* red = reinterpret_cast<ArgminState*>(dsm + (size_t)g.K * g.K * 4);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int N = g.N, r = g.r, K = g.K, NP = g.NP, Ws = g.Ws, SW = g.SW;
+  const int l16 = lane & 15, kg = lane >> 4;
+  const int N = g.N, r = g.r, K = g.K, NP = g.NP, Ws = g.Ws;
   const size_t planeA = (size_t)jd.hA * jd.wA, planeB = (size_t)jd.hB * jd.wB;
 
   for (int cpi = blockIdx.x; cpi < jd.n_cps; cpi += gridDim.x) {
     const int4 cp = jd.cps[cpi];
     const int h = N / 2;
     const int tx0 = cp.x - h, ty0 = cp.y - h, sx0 = cp.z - h - r, sy0 = cp.w - h - r;
-    __syncthreads();  // previous task's epilogue is done with LDS
+    __syncthreads();  // the previous point's epilogue is done with LDS
     const bool inA = tx0 >= 0 && ty0 >= 0 && tx0 + N <= jd.wA && ty0 + N <= jd.hA;
     const bool inB = sx0 >= 0 && sy0 >= 0 && sx0 + Ws <= jd.wB && sy0 + Ws <= jd.hB;
     if (!(inA && inB)) {
       oob_result<D_NT>(jd, cpi);
       continue;
     }
-    f32x4 acc[D_NB];
+    // acc[m][n]: u_x block m, u_y block n; lane element q is
+    // u_x = 16 m + 4 (lane / 16) + q, u_y = 16 n + lane % 16
+    f32x4 acc[NB][NB];
 #pragma unroll
-    for (int n = 0; n < D_NB; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < NB; ++m)
+#pragma unroll
+      for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (int c = 0; c < jd.m; ++c) {
       __syncthreads();  // MFMA reads of the previous channel are done
-      const float* TA = jd.volA + c * planeA + (size_t)ty0 * jd.wA + tx0;
-      const float* SB = jd.volB + c * planeB + (size_t)sy0 * jd.wB + sx0;
-      for (int t = wv; t < g.TROWS; t += D_NB) {
-        const int ty = t - g.OFF;
-        const bool row_ok = ty >= 0 && ty < N;
-        for (int x = 2 * lane; x < NP; x += 128) {
-          float a = 0.f, b = 0.f;
-          if (row_ok) {
-            if (x < N) a = TA[(size_t)ty * jd.wA + x];
-            if (x + 1 < N) b = TA[(size_t)ty * jd.wA + x + 1];
-          }
-          Tl[(size_t)t * g.TLD + x / 2] = pack_bf16x2(a, b);
-        }
-      }
-      for (int y = wv; y < Ws; y += D_NB) {
-        for (int x = 2 * lane; x < SW; x += 128) {
-          const float a = x < Ws ? SB[(size_t)y * jd.wB + x] : 0.f;
-          const float b = x + 1 < Ws ? SB[(size_t)y * jd.wB + x + 1] : 0.f;
-          Sl[(size_t)y * (SW / 2) + x / 2] = pack_bf16x2(a, b);
-        }
-      }
+      stage_rows(Tl, g.TLD, g.TROWS, NP, jd.volA + c * planeA + (ptrdiff_t)(ty0 - D_TPAD) * jd.wA + tx0, jd.wA, N,
+                 [&](int tr) { return tr >= D_TPAD && tr < D_TPAD + N; }, wv, lane);
+      stage_rows(Sl, g.SLD, Ws, 2 * g.SLD, jd.volB + c * planeB + (size_t)sy0 * jd.wB + sx0, jd.wB, Ws,
+                 [](int) { return true; }, wv, lane);
       __syncthreads();
-      if (wv < g.nblk) {
-        const int ux = 16 * wv + (lane & 15), kg = lane >> 4;
-        const int uyl = lane & 15;
-        for (int s = 0; s < Ws; ++s) {
-          // u_y blocks with some template row s - u_y inside [0, N)
-          const int nhi = min(g.nblk - 1, s >> 4);
-          const int nlo = max(0, (s - N - 14 + 15) >> 4);
-          const unsigned* srow = Sl + (size_t)s * (SW / 2);
-          for (int kc = 0; kc < NP / 32; ++kc) {
-            const int e = 32 * kc + 8 * kg + ux;  // first search column of this lane's fragment
+      // this wave's search rows; for row s the u_y blocks n whose template
+      // rows s - u_y meet [0, N) are those with 0 <= s - 16 n <= N + 14
+      for (int s = wv; s < Ws; s += D_NW) {
+        const int nhi = min(NB - 1, s >> 4);
+        const int nlo = max(0, (s - N + 1) >> 4);
+        const unsigned* srow = Sl + (size_t)s * g.SLD;
+        for (int kc = 0; kc < NP / 32; ++kc) {
+          bf16x8 A[NB];
+#pragma unroll
+          for (int m = 0; m < NB; ++m) {
+            // 8 bf16 of search row s from column 32 kc + 8 kg + 16 m + lane % 16
+            const int e = 32 * kc + 8 * kg + 16 * m + l16;
             const unsigned* sp = srow + (e >> 1);
             const unsigned w0 = sp[0], w1 = sp[1], w2 = sp[2], w3 = sp[3], w4 = sp[4];
             const unsigned sh = (e & 1) * 2;
@@ -132,33 +161,41 @@ __global__ __launch_bounds__(D_NT) void match_direct_kernel(MatchJob jd, DirectG
             av[1] = __builtin_amdgcn_alignbyte(w2, w1, sh);
             av[2] = __builtin_amdgcn_alignbyte(w3, w2, sh);
             av[3] = __builtin_amdgcn_alignbyte(w4, w3, sh);
-            const bf16x8 A = __builtin_bit_cast(bf16x8, av);
+            A[m] = __builtin_bit_cast(bf16x8, av);
+          }
 #pragma unroll
-            for (int n = 0; n < D_NB; ++n) {
-              if (n >= nlo && n <= nhi) {
-                const int t = s - (16 * n + uyl) + g.OFF;
-                const uint4 bw = *reinterpret_cast<const uint4*>(Tl + (size_t)t * g.TLD + (32 * kc + 8 * kg) / 2);
-                const bf16x8 B = __builtin_bit_cast(bf16x8, bw);
-                acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[n], 0, 0, 0);
-              }
+          for (int n = 0; n < NB; ++n) {
+            if (n >= nlo && n <= nhi) {
+              // template row s - 16 n - lane % 16, columns 32 kc + 8 kg .. + 7
+              const int tr = s - 16 * n - l16 + D_TPAD;
+              const uint4 bw = *reinterpret_cast<const uint4*>(Tl + (size_t)tr * g.TLD + 16 * kc + 4 * kg);
+              const bf16x8 B = __builtin_bit_cast(bf16x8, bw);
+#pragma unroll
+              for (int m = 0; m < NB; ++m) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m], B, acc[m][n], 0, 0, 0);
             }
           }
         }
       }
     }
     __syncthreads();  // all MFMA reads of T/S are done: Cs may overwrite them
-    if (wv < g.nblk) {
+    // sum the waves' partial correlations in wave order (deterministic)
+    for (int w = 0; w < D_NW; ++w) {
+      if (wv == w) {
 #pragma unroll
-      for (int n = 0; n < D_NB; ++n) {
-        const int uy = 16 * n + (lane & 15);
+        for (int m = 0; m < NB; ++m)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int ux = 16 * wv + 4 * (lane >> 4) + q;
-          if (n < g.nblk && uy < K && ux < K) Cs[uy * K + ux] = acc[n][q];
-        }
+          for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int ux = 16 * m + 4 * kg + q, uy = 16 * n + l16;
+              if (ux < K && uy < K) {
+                float* p = Cs + uy * K + ux;
+                *p = (w == 0 ? 0.f : *p) + acc[m][n][q];
+              }
+            }
       }
+      __syncthreads();
     }
-    __syncthreads();
     ssd_epilogue<D_NT>(jd, cpi, tx0, ty0, sx0, sy0, Cs, red);
   }
 }
@@ -167,12 +204,20 @@ static int g_direct_attr = 1;
 
 size_t direct_workspace_bytes(const cfog_job*, int, int, int) { return 0; }
 
+template <int NB>
+static void launch_nb(const MatchJob& d, const DirectGeom& g, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(match_direct_kernel<NB>, dim3(blocks), dim3(D_NT), g.lds, st, d, g);
+}
+
 int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, void*, int num_cus, hipStream_t st) {
   if (g_direct_attr == 1) {
-    g_direct_attr = hipFuncSetAttribute((const void*)match_direct_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)kMaxLds) == hipSuccess
-                        ? 0
-                        : -2;
+    const void* k[D_NB] = {(const void*)match_direct_kernel<1>, (const void*)match_direct_kernel<2>,
+                           (const void*)match_direct_kernel<3>, (const void*)match_direct_kernel<4>,
+                           (const void*)match_direct_kernel<5>};
+    g_direct_attr = 0;
+    for (int i = 0; i < D_NB; ++i)
+      if (hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess)
+        g_direct_attr = -2;
   }
   if (g_direct_attr != 0) return -2;
   for (int i = 0; i < n_jobs; ++i) {
@@ -193,7 +238,13 @@ int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, void*, int num_
     d.surfaces = j.surfaces;
     const int per_cu = std::max(1, (int)(kMaxLds / g.lds));
     const int blocks = std::min(j.n_cps, num_cus * per_cu);
-    hipLaunchKernelGGL(match_direct_kernel, dim3(blocks), dim3(D_NT), g.lds, st, d, g);
+    switch (g.nblk) {
+      case 1: launch_nb<1>(d, g, blocks, st); break;
+      case 2: launch_nb<2>(d, g, blocks, st); break;
+      case 3: launch_nb<3>(d, g, blocks, st); break;
+      case 4: launch_nb<4>(d, g, blocks, st); break;
+      default: launch_nb<5>(d, g, blocks, st); break;
+    }
     if (hipGetLastError() != hipSuccess) return -2;
   }
   return 0;
