@@ -40,7 +40,7 @@ constexpr int D_NB = 5;            // max 16-wide blocks of u_x (and u_y): 2r+1 
 constexpr int D_NW = 8;            // waves per workgroup
 constexpr int D_NT = 64 * D_NW;
 constexpr int D_TPAD = 15;         // zero template rows above and below
-constexpr int D_RB = 4;            // rows staged per batch of loads
+constexpr int D_RB = 8;            // rows staged per batch of loads
 
 struct DirectGeom {
   int N, r, K, nblk, NP, Ws;
@@ -110,7 +110,8 @@ __global__ __launch_bounds__(D_NT) void match_direct_kernel(MatchJob jd, DirectG
   unsigned* Sl = reinterpret_cast<unsigned*>(dsm + g.t_bytes);                 // Ws x SLD dwords
   float* Cs = reinterpret_cast<float*>(dsm);                                    // K x K, after the channels
   ArgminState* red = reinterpret_cast<ArgminState*>(dsm + (size_t)g.K * g.K * 4);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar loop control
   const int l16 = lane & 15, kg = lane >> 4;
   const int N = g.N, r = g.r, K = g.K, NP = g.NP, Ws = g.Ws;
   const size_t planeA = (size_t)jd.hA * jd.wA, planeB = (size_t)jd.hB * jd.wB;
@@ -148,28 +149,36 @@ __global__ __launch_bounds__(D_NT) void match_direct_kernel(MatchJob jd, DirectG
         const int nlo = max(0, (s - N + 1) >> 4);
         const unsigned* srow = Sl + (size_t)s * g.SLD;
         for (int kc = 0; kc < NP / 32; ++kc) {
-          bf16x8 A[NB];
+          // issue every operand read of this chunk before the first use
+          unsigned raw[NB][5];
 #pragma unroll
           for (int m = 0; m < NB; ++m) {
             // 8 bf16 of search row s from column 32 kc + 8 kg + 16 m + lane % 16
-            const int e = 32 * kc + 8 * kg + 16 * m + l16;
-            const unsigned* sp = srow + (e >> 1);
-            const unsigned w0 = sp[0], w1 = sp[1], w2 = sp[2], w3 = sp[3], w4 = sp[4];
-            const unsigned sh = (e & 1) * 2;
+            const unsigned* sp = srow + ((32 * kc + 8 * kg + 16 * m + l16) >> 1);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) raw[m][i] = sp[i];
+          }
+          uint4 bw[NB];
+#pragma unroll
+          for (int n = 0; n < NB; ++n) {
+            // template row s - 16 n - lane % 16, columns 32 kc + 8 kg .. + 7
+            // (rows of blocks outside [nlo, nhi] are clamped and not used)
+            const int tr = min(max(s - 16 * n - l16 + D_TPAD, 0), g.TROWS - 1);
+            bw[n] = *reinterpret_cast<const uint4*>(Tl + (size_t)tr * g.TLD + 16 * kc + 4 * kg);
+          }
+          const unsigned sh = (l16 & 1) * 2;  // e & 1 for every m
+          bf16x8 A[NB];
+#pragma unroll
+          for (int m = 0; m < NB; ++m) {
             unsigned av[4];
-            av[0] = __builtin_amdgcn_alignbyte(w1, w0, sh);
-            av[1] = __builtin_amdgcn_alignbyte(w2, w1, sh);
-            av[2] = __builtin_amdgcn_alignbyte(w3, w2, sh);
-            av[3] = __builtin_amdgcn_alignbyte(w4, w3, sh);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = __builtin_amdgcn_alignbyte(raw[m][i + 1], raw[m][i], sh);
             A[m] = __builtin_bit_cast(bf16x8, av);
           }
 #pragma unroll
           for (int n = 0; n < NB; ++n) {
             if (n >= nlo && n <= nhi) {
-              // template row s - 16 n - lane % 16, columns 32 kc + 8 kg .. + 7
-              const int tr = s - 16 * n - l16 + D_TPAD;
-              const uint4 bw = *reinterpret_cast<const uint4*>(Tl + (size_t)tr * g.TLD + 16 * kc + 4 * kg);
-              const bf16x8 B = __builtin_bit_cast(bf16x8, bw);
+              const bf16x8 B = __builtin_bit_cast(bf16x8, bw[n]);
 #pragma unroll
               for (int m = 0; m < NB; ++m) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m], B, acc[m][n], 0, 0, 0);
             }
