@@ -32,6 +32,14 @@ Readings taken where the paper is silent (each is listed in the design notes):
   * ties are broken towards the smallest row-major index (dy first, then dx);
   * no per-pixel normalisation of the CFOG vector.
 
+Beyond the hot path (the first extension of the method):
+  * the correlation objective of Eq. 7 (maximise the template / window
+    correlation instead of minimising the SSD), evaluated by brute force;
+  * sub-pixel refinement of the best offset.  The paper fits a quadratic
+    polynomial around the integer match (Section V-B) without giving the
+    formula; the reading taken here is a separable three-point parabola along
+    x and along y through the best offset and its axis neighbours.
+
 Parity pins live in tests/test_oracle_pins.py.  No CFOG value, surface or
 offset is printed in the paper, so agreement with the authors' own code is
 "parity unpinned"; every function here is pinned by closed forms, invariants,
@@ -153,6 +161,46 @@ def ssd_surface_direct(D1: np.ndarray, D2: np.ndarray, cp, N: int, r: int) -> np
     return out
 
 
+def correlation_surface_direct(D1: np.ndarray, D2: np.ndarray, cp, N: int, r: int) -> np.ndarray:
+    """Eq. 7 objective by brute force, as a cost to minimise:
+    J(d) = - sum_{c,i,j} D1 template * D2 window at d, index [dy+r, dx+r]."""
+    x, y, bx, by = (int(v) for v in cp)
+    h = N // 2
+    T = D1[:, y - h:y - h + N, x - h:x - h + N]
+    out = np.empty((2 * r + 1, 2 * r + 1), np.float64)
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            Sw = D2[:, by - h + dy:by - h + dy + N, bx - h + dx:bx - h + dx + N]
+            out[dy + r, dx + r] = -np.sum(T * Sw)
+    return out
+
+
+def parabola_vertex(a: float, b: float, c: float) -> float:
+    """Abscissa, relative to the middle sample, of the vertex of the parabola
+    through (-1, a), (0, b), (1, c); 0 when the three samples are not convex
+    (b is not below their chord)."""
+    den = a - 2.0 * b + c
+    if not den > 0.0:
+        return 0.0
+    return 0.5 * (a - c) / den
+
+
+def subpixel(surface: np.ndarray, dx: int, dy: int):
+    """Sub-pixel refinement of the integer best offset (dx, dy) of a cost
+    surface: per axis, the parabola through the best value and its two axis
+    neighbours; an axis whose neighbour falls outside the surface keeps its
+    integer value.  Returns (fdx, fdy) as floats."""
+    r = (surface.shape[0] - 1) // 2
+    ix, iy = dx + r, dy + r
+    K = 2 * r + 1
+    fx, fy = float(dx), float(dy)
+    if 0 < ix < K - 1:
+        fx += parabola_vertex(surface[iy, ix - 1], surface[iy, ix], surface[iy, ix + 1])
+    if 0 < iy < K - 1:
+        fy += parabola_vertex(surface[iy - 1, ix], surface[iy, ix], surface[iy + 1, ix])
+    return fx, fy
+
+
 def argmin_lex(surface: np.ndarray):
     """Eq. 4 with ties broken to the smallest row-major index.  Returns
     (dx, dy, best, second) where second = min over all other offsets."""
@@ -166,11 +214,15 @@ def argmin_lex(surface: np.ndarray):
     return dx - r, dy - r, best, second
 
 
-def match(D1: np.ndarray, D2: np.ndarray, cps, N: int, r: int, surfaces: bool = False):
-    """Match every control point by brute-force SSD (Eqs. 3-4).
+def match(D1: np.ndarray, D2: np.ndarray, cps, N: int, r: int, surfaces: bool = False,
+          objective: str = "ssd", subpix: bool = False):
+    """Match every control point by brute force: objective "ssd" minimises
+    Eq. 3 (Eq. 4), "corr" maximises the correlation of Eq. 7 (as the cost
+    -C).
 
     Returns dict with int arrays dx, dy, status and float arrays best, second
-    (NaN for out-of-bounds points) and optionally surfaces (n, 2r+1, 2r+1)."""
+    (NaN for out-of-bounds points), optionally surfaces (n, 2r+1, 2r+1) and,
+    with subpix, the refined offsets fdx, fdy (NaN when not ok)."""
     cps = np.asarray(cps).reshape(-1, 4)
     n = len(cps)
     res = dict(dx=np.zeros(n, np.int32), dy=np.zeros(n, np.int32),
@@ -178,13 +230,16 @@ def match(D1: np.ndarray, D2: np.ndarray, cps, N: int, r: int, surfaces: bool = 
                status=np.zeros(n, np.int32))
     if surfaces:
         res["surfaces"] = np.full((n, 2 * r + 1, 2 * r + 1), np.nan)
+    if subpix:
+        res["fdx"], res["fdy"] = np.full(n, np.nan), np.full(n, np.nan)
+    cost = {"ssd": ssd_surface_direct, "corr": correlation_surface_direct}[objective]
     _, hA, wA = D1.shape
     _, hB, wB = D2.shape
     for k, cp in enumerate(cps):
         if not window_ok(cp, N, r, hA, wA, hB, wB):
             res["status"][k] = STATUS_OUT_OF_BOUNDS
             continue
-        S = ssd_surface_direct(D1, D2, cp, N, r)
+        S = cost(D1, D2, cp, N, r)
         if not np.all(np.isfinite(S)):
             res["status"][k] = STATUS_NONFINITE
             continue
@@ -192,6 +247,8 @@ def match(D1: np.ndarray, D2: np.ndarray, cps, N: int, r: int, surfaces: bool = 
         res["dx"][k], res["dy"][k], res["best"][k], res["second"][k] = dx, dy, b, s
         if surfaces:
             res["surfaces"][k] = S
+        if subpix:
+            res["fdx"][k], res["fdy"][k] = subpixel(S, dx, dy)
     return res
 
 

@@ -316,3 +316,90 @@ def test_paper_workload_recovers_most_shifts():
     res = O.match_fft(O.cfog(A), O.cfog(B), cps, 48, 10)
     ok = np.hypot(res["dx"] - s[0], res["dy"] - s[1]) <= 1.5
     assert ok.mean() >= 0.6
+
+
+# -------------------------------------- Eq. 7 objective, sub-pixel refinement
+
+def _python_loop_corr(D1, D2, cp, N, r):
+    x, y, bx, by = cp
+    h = N // 2
+    m = len(D1)
+    out = [[0.0] * (2 * r + 1) for _ in range(2 * r + 1)]
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            acc = 0.0
+            for c in range(m):
+                for i in range(N):
+                    for j in range(N):
+                        acc += float(D1[c][y - h + i][x - h + j]) * float(D2[c][by - h + dy + i][bx - h + dx + j])
+            out[dy + r][dx + r] = -acc
+    return np.array(out)
+
+
+@pytest.mark.parametrize("N,r,m", [(3, 1, 2), (4, 2, 1), (5, 2, 3)])
+def test_correlation_objective_against_python_loops(N, r, m):
+    rng = np.random.default_rng(N * 10 + r)
+    D1 = rng.normal(size=(m, 12, 12))
+    D2 = rng.normal(size=(m, 12, 12))
+    cp = (6, 6, 6, 5)
+    J = O.correlation_surface_direct(D1, D2, cp, N, r)
+    np.testing.assert_allclose(J, _python_loop_corr(D1.tolist(), D2.tolist(), cp, N, r), rtol=0, atol=1e-12)
+
+
+def test_correlation_objective_is_ssd_without_energies():
+    """Eq. 5 rearranged: -C(d) = (S(d) - E1 - E2(d)) / 2, from the SSD oracle
+    and the energies (a different formula for every term)."""
+    A, B, _ = synth.make_pair(synth.PairSpec(64, 64, 12, (3.0, 8.0), 6, 4), (9, 1))
+    D1, D2 = O.cfog(A.astype(np.float64)), O.cfog(B.astype(np.float64))
+    cp, N, r = (30, 31, 32, 30), 20, 5
+    S = O.ssd_surface_direct(D1, D2, cp, N, r)
+    E1, E2 = O.energies(D1, D2, cp, N, r)
+    J = O.correlation_surface_direct(D1, D2, cp, N, r)
+    np.testing.assert_allclose(J, 0.5 * (S - E1 - E2), rtol=1e-12, atol=1e-9 * E1)
+
+
+@pytest.mark.parametrize("t0,alpha,beta", [(0.0, 1.0, 0.0), (0.3, 2.5, -1.0), (-0.45, 0.1, 7.0), (0.49, 3.0, 2.0)])
+def test_parabola_vertex_is_exact_for_quadratics(t0, alpha, beta):
+    q = lambda t: alpha * (t - t0) ** 2 + beta  # noqa: E731
+    assert O.parabola_vertex(q(-1), q(0), q(1)) == pytest.approx(t0, abs=1e-12)
+
+
+def test_parabola_vertex_without_a_minimum_is_zero():
+    assert O.parabola_vertex(1.0, 1.0, 1.0) == 0.0   # flat
+    assert O.parabola_vertex(0.0, 1.0, 0.0) == 0.0   # a maximum
+    assert O.parabola_vertex(2.0, 1.0, 0.0) == 0.0   # a straight line
+
+
+@pytest.mark.parametrize("x0,y0", [(0.3, -1.2), (-2.49, 1.5001), (1.0, 0.0), (2.2, -2.4)])
+def test_subpixel_recovers_a_sampled_quadratic_bowl(x0, y0):
+    r = 3
+    d = np.arange(-r, r + 1)
+    S = 2.0 * (d[None, :] - x0) ** 2 + 0.5 * (d[:, None] - y0) ** 2 + 3.0
+    dx, dy, _, _ = O.argmin_lex(S)
+    assert (dx, dy) == (int(np.floor(x0 + 0.5)), int(np.floor(y0 + 0.5)))
+    fx, fy = O.subpixel(S, dx, dy)
+    assert fx == pytest.approx(x0, abs=1e-12) and fy == pytest.approx(y0, abs=1e-12)
+
+
+def test_subpixel_keeps_integer_offsets_at_the_border():
+    r = 2
+    d = np.arange(-r, r + 1)
+    S = (d[None, :] + 2.4) ** 2 + (d[:, None] - 0.25) ** 2   # x minimum beyond -r
+    dx, dy, _, _ = O.argmin_lex(S)
+    assert dx == -r
+    fx, fy = O.subpixel(S, dx, dy)
+    assert fx == -r and fy == pytest.approx(0.25, abs=1e-12)
+
+
+def test_match_with_correlation_objective_and_subpixel():
+    rng = np.random.default_rng(3)
+    D1, D2 = rng.random((2, 30, 30)), rng.random((2, 30, 30))
+    cps = [(12, 12, 13, 12), (15, 14, 15, 15), (1, 1, 1, 1)]
+    res = O.match(D1, D2, cps, 8, 3, surfaces=True, objective="corr", subpix=True)
+    assert list(res["status"]) == [0, 0, O.STATUS_OUT_OF_BOUNDS]
+    for k in range(2):
+        J = O.correlation_surface_direct(D1, D2, cps[k], 8, 3)
+        dx, dy, b, s = O.argmin_lex(J)
+        assert (res["dx"][k], res["dy"][k], res["best"][k]) == (dx, dy, b)
+        assert (res["fdx"][k], res["fdy"][k]) == O.subpixel(J, dx, dy)
+    assert np.isnan(res["fdx"][2])
