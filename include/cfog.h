@@ -56,6 +56,9 @@ extern "C" {
 /* ... plus optional modifiers */
 #define CFOG_AUTOTUNE 0x100  /* FFT paths: time candidate FFT sizes per (N, r) on first use */
 #define CFOG_USE_GRAPH 0x200 /* batched path: capture the launches once, replay on identical calls */
+#define CFOG_OBJ_CORR 0x400  /* any path: the objective of Eq. 7 (maximise the correlation
+                                C(d) = sum D1 * D2 over the window, no energy terms); every
+                                similarity value (ssd_best, ssd_second, surfaces) is then -C(d) */
 
 typedef struct cfog_ctx cfog_ctx;
 
@@ -128,7 +131,15 @@ typedef struct {
  *   cps      device array of n_cps cfog_cp (16-byte aligned).
  *   out      device array of n_cps cfog_result.
  *   surfaces nullable device array [n_cps][2r+1][2r+1] fp32 of SSD(d),
- *            index [dy + r][dx + r]; NaN for points that are not CFOG_CP_OK. */
+ *            index [dy + r][dx + r]; NaN for points that are not CFOG_CP_OK.
+ *   subpix   nullable device array [n_cps][2] fp32 (fdx, fdy): the best offset
+ *            refined to sub-pixel precision (the quadratic fit of Section V-B,
+ *            read as a three-point parabola per axis through the best value and
+ *            its two axis neighbours: fdx = dx + (S(dx-1) - S(dx+1)) /
+ *            (2 (S(dx-1) - 2 S(dx) + S(dx+1))), likewise fdy; an axis whose
+ *            neighbour lies outside [-r, r], or whose three values are not
+ *            convex, keeps its integer offset); NaN for points that are not
+ *            CFOG_CP_OK.  8-byte aligned. */
 typedef struct {
   const float* volA;
   const double* satA;
@@ -142,6 +153,7 @@ typedef struct {
   int32_t pad_;
   cfog_result* out;
   float* surfaces;
+  float* subpix;
 } cfog_job;
 
 /* Device workspace (bytes) match_batch needs for these jobs and flags; 0 for
@@ -153,7 +165,8 @@ size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n
  * match_batch - SSD template matching of every control point of every job
  * (Eqs. 3-6, 8-9; Eq. 4 argmin).  Volumes have m channels (1..16).
  *   jobs        host array of n_jobs jobs (n_jobs >= 0).
- *   flags       one CFOG_PATH_* value, optionally | CFOG_AUTOTUNE (FFT paths:
+ *   flags       one CFOG_PATH_* value, optionally | CFOG_OBJ_CORR (Eq. 7
+ *               objective) and | CFOG_AUTOTUNE (FFT paths:
  *               the first call for a given (N, r, m) times up to three FFT sizes
  *               on the job's own points and keeps the fastest; with the
  *               environment variable CFOG_PLAN_CACHE naming a file, choices
@@ -225,7 +238,8 @@ typedef struct {
   int32_t max_batch_reqs;  /* requests per batch, >= 1 */
   int32_t m;               /* orientation channels, 1..16 */
   float sigma;             /* Gaussian std of the extraction, > 0 */
-  int32_t flags;           /* match_batch path: CFOG_PATH_BATCHED_FFT, _PLAIN_FFT or _MFMA_BF16 */
+  int32_t flags;           /* match_batch path: CFOG_PATH_BATCHED_FFT, _PLAIN_FFT or _MFMA_BF16,
+                              optionally | CFOG_OBJ_CORR */
   size_t max_batch_surf;   /* surface values per batch (and per request) staged for the host */
 } cfog_server_config;
 

@@ -32,6 +32,7 @@ PATH_BATCHED_FFT = 0x2
 PATH_MFMA_BF16 = 0x4
 AUTOTUNE = 0x100
 USE_GRAPH = 0x200
+OBJ_CORR = 0x400
 
 # Exported symbols, as declared in include/cfog.h.
 EXPORTS = (
@@ -55,6 +56,7 @@ class cfog_job(ctypes.Structure):
         ("volB", ctypes.c_void_p), ("satB", ctypes.c_void_p), ("hB", ctypes.c_int32), ("wB", ctypes.c_int32),
         ("cps", ctypes.c_void_p), ("n_cps", ctypes.c_int32), ("N", ctypes.c_int32), ("r", ctypes.c_int32),
         ("pad_", ctypes.c_int32), ("out", ctypes.c_void_p), ("surfaces", ctypes.c_void_p),
+        ("subpix", ctypes.c_void_p),
     ]
 
 
@@ -223,6 +225,7 @@ class Job:
     r: int
     out: Optional[torch.Tensor] = None        # (n, 6) int32 view of cfog_result
     surfaces: Optional[torch.Tensor] = None   # (n, 2r+1, 2r+1) fp32
+    subpix: Optional[torch.Tensor] = None     # (n, 2) fp32 refined offsets (fdx, fdy)
 
     def to_c(self) -> cfog_job:
         n = int(self.cps.shape[0])
@@ -232,7 +235,7 @@ class Job:
             self.volA.data_ptr(), self.satA.data_ptr(), self.volA.shape[1], self.volA.shape[2],
             self.volB.data_ptr(), self.satB.data_ptr(), self.volB.shape[1], self.volB.shape[2],
             self.cps.data_ptr() if n else None, n, int(self.N), int(self.r), 0,
-            self.out.data_ptr(), _ptr(self.surfaces))
+            self.out.data_ptr(), _ptr(self.surfaces), _ptr(self.subpix))
 
 
 def results(out: torch.Tensor) -> dict:

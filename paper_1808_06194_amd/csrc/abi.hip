@@ -79,12 +79,12 @@ int validate_job(const cfog_job& j, int m) {
   if (j.hA < 1 || j.wA < 1 || j.hB < 1 || j.wB < 1) return CFOG_EINVAL;
   if (j.N < 1 || j.r < 0 || m < 1 || m > cfog::kMaxOrient) return CFOG_EINVAL;
   if (!aligned(j.cps, 16) || !aligned(j.out, 8) || !aligned(j.satA, 8) || !aligned(j.satB, 8) ||
-      !aligned(j.volA, 4) || !aligned(j.volB, 4) || !aligned(j.surfaces, 4))
+      !aligned(j.volA, 4) || !aligned(j.volB, 4) || !aligned(j.surfaces, 4) || !aligned(j.subpix, 8))
     return CFOG_EINVAL;
   return CFOG_OK;
 }
 
-cfog::MatchJob to_device_job(const cfog_job& j, int m) {
+cfog::MatchJob to_device_job(const cfog_job& j, int m, int obj) {
   cfog::MatchJob d{};
   d.volA = j.volA; d.satA = j.satA; d.hA = j.hA; d.wA = j.wA;
   d.volB = j.volB; d.satB = j.satB; d.hB = j.hB; d.wB = j.wB;
@@ -92,6 +92,8 @@ cfog::MatchJob to_device_job(const cfog_job& j, int m) {
   d.n_cps = j.n_cps; d.N = j.N; d.r = j.r; d.m = m;
   d.out = reinterpret_cast<cfog::Result*>(j.out);
   d.surfaces = j.surfaces;
+  d.subpix = reinterpret_cast<float2*>(j.subpix);
+  d.obj = obj;
   return d;
 }
 
@@ -130,7 +132,7 @@ struct BatchPlan {
   size_t jobs_off = 0, tasks_off = 0, table_bytes = 0, total = 0;
 };
 
-int build_batch(cfog_ctx* ctx, const cfog_job* jobs, int n_jobs, int m, BatchPlan& B) {
+int build_batch(cfog_ctx* ctx, const cfog_job* jobs, int n_jobs, int m, int obj, BatchPlan& B) {
   std::vector<const cfog::FftPlan*> plans(n_jobs);
   for (int i = 0; i < n_jobs; ++i) {
     int rc = validate_job(jobs[i], m);
@@ -139,7 +141,7 @@ int build_batch(cfog_ctx* ctx, const cfog_job* jobs, int n_jobs, int m, BatchPla
     if (!plans[i]) return CFOG_EUNSUPPORTED;
   }
   B.jobs.resize(n_jobs);
-  for (int i = 0; i < n_jobs; ++i) B.jobs[i] = to_device_job(jobs[i], m);
+  for (int i = 0; i < n_jobs; ++i) B.jobs[i] = to_device_job(jobs[i], m, obj);
   int nplans = 0;
   const cfog::FftPlan* all = cfog::fft_plans(&nplans);
   size_t tg = 0;
@@ -272,9 +274,10 @@ int autotune(cfog_ctx* ctx, const cfog_job& j, int m, hipStream_t st, void* tg_w
     (void)hipEventDestroy(e0);
     return record(ctx, hipGetLastError());
   }
-  cfog::MatchJob dj = to_device_job(j, m);
+  cfog::MatchJob dj = to_device_job(j, m, 0);
   dj.n_cps = std::min(j.n_cps, 2 * ctx->num_cus);
   dj.surfaces = nullptr;
+  dj.subpix = nullptr;
   float best = 1e30f;
   int bestP = first->P;
   for (const cfog::FftPlan* p : cands) {
@@ -464,7 +467,7 @@ size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n
     return align_up(std::max(tg, tune), 256);
   }
   BatchPlan B;
-  if (build_batch(ctx, jobs, n_jobs, m, B) != CFOG_OK) return 0;
+  if (build_batch(ctx, jobs, n_jobs, m, 0, B) != CFOG_OK) return 0;
   return std::max(B.total, align_up(tune, 256));
 }
 
@@ -472,7 +475,8 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
                 size_t ws_bytes, void* stream) {
   if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return CFOG_EINVAL;
   const int path = flags & CFOG_PATH_MASK;
-  if (flags & ~(CFOG_PATH_MASK | CFOG_AUTOTUNE | CFOG_USE_GRAPH)) return CFOG_EINVAL;
+  if (flags & ~(CFOG_PATH_MASK | CFOG_AUTOTUNE | CFOG_USE_GRAPH | CFOG_OBJ_CORR)) return CFOG_EINVAL;
+  const int obj = (flags & CFOG_OBJ_CORR) ? 1 : 0;
   if (path != CFOG_PATH_PLAIN_FFT && path != CFOG_PATH_BATCHED_FFT && path != CFOG_PATH_MFMA_BF16)
     return CFOG_EINVAL;
   if ((flags & CFOG_USE_GRAPH) && path != CFOG_PATH_BATCHED_FFT) return CFOG_EINVAL;
@@ -488,7 +492,7 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
   if (path == CFOG_PATH_MFMA_BF16) {
     const size_t need = cfog::direct_workspace_bytes(jobs, n_jobs, m, ctx->num_cus);
     if (need > 0 && (!d_ws || ws_bytes < need)) return CFOG_ENOMEM;
-    int rc = cfog::launch_match_direct(jobs, n_jobs, m, d_ws, ctx->num_cus, st);
+    int rc = cfog::launch_match_direct(jobs, n_jobs, m, obj, d_ws, ctx->num_cus, st);
     if (rc == -1) return CFOG_EUNSUPPORTED;
     return rc == 0 ? CFOG_OK : record(ctx, hipGetLastError());
   }
@@ -515,7 +519,7 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
       const cfog::FftPlan* p = select_plan(ctx, jobs[i].N, jobs[i].r, m);
       const int blocks = p->tg_bytes ? std::min(jobs[i].n_cps, cfog::plan_slots(p, ctx->num_cus)) : jobs[i].n_cps;
       if (p->tg_bytes && (size_t)blocks * p->tg_bytes > ws_bytes) return CFOG_ENOMEM;
-      if (cfog::launch_match_fft(p, to_device_job(jobs[i], m), nullptr, nullptr, jobs[i].n_cps, blocks, ws, st) != 0)
+      if (cfog::launch_match_fft(p, to_device_job(jobs[i], m, obj), nullptr, nullptr, jobs[i].n_cps, blocks, ws, st) != 0)
         return record(ctx, hipGetLastError());
     }
     return CFOG_OK;
@@ -528,7 +532,8 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
     const size_t jb = sizeof(cfog_job) * (size_t)n_jobs;
     key.resize(jb + 4 * sizeof(uint64_t));
     if (jb) memcpy(key.data(), jobs, jb);
-    uint64_t sc[4] = {(uint64_t)n_jobs, (uint64_t)m, (uint64_t)(uintptr_t)d_ws, (uint64_t)ws_bytes};
+    uint64_t sc[4] = {(uint64_t)n_jobs, ((uint64_t)m << 32) | (uint32_t)flags, (uint64_t)(uintptr_t)d_ws,
+                      (uint64_t)ws_bytes};
     memcpy(key.data() + jb, sc, sizeof(sc));
     h = fnv1a(key.data(), key.size());
     auto it = ctx->graphs.find(h);
@@ -538,7 +543,7 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
     }
   }
   BatchPlan B;
-  int rc = build_batch(ctx, jobs, n_jobs, m, B);
+  int rc = build_batch(ctx, jobs, n_jobs, m, obj, B);
   if (rc != CFOG_OK) return rc;
   if (B.tasks.empty()) return CFOG_OK;
   if (!d_ws || ws_bytes < B.total) return CFOG_ENOMEM;

@@ -1,7 +1,9 @@
 // SSD assembly (Eq. 5 of Ye et al.) from a correlation surface held in LDS,
 // with the energy terms from FP64 summed-area tables, optional surface output
-// and the lexicographic argmin / second-best of Eq. 4.  Shared by the FFT and
-// the direct (MFMA) matchers.
+// and the lexicographic argmin / second-best of Eq. 4 (or, for the objective
+// of Eq. 7, of the negated correlation), plus the optional sub-pixel
+// refinement of the best offset.  Shared by the FFT and the direct (MFMA)
+// matchers.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <limits.h>
@@ -45,24 +47,39 @@ __device__ __forceinline__ double box_sum(const double* sat, int ld, int y0, int
   return (b[n] - a[n]) - (b[0] - a[0]);
 }
 
+// Abscissa, relative to the middle sample, of the vertex of the parabola
+// through (-1, a), (0, b), (1, c); 0 unless the samples are convex.
+__device__ __forceinline__ double parabola_vertex(double a, double b, double c) {
+  const double den = a - 2.0 * b + c;
+  return den > 0.0 ? 0.5 * (a - c) / den : 0.0;
+}
+
 // Writes the result of control point cpi of job jd from the correlation
 // Cs[u_y * K + u_x] (LDS, all K*K values visible to the workgroup):
-//   SSD(u) = E1 + E2(u) - 2 C(u), summed in FP64 and rounded to FP32,
-// surfaces (if requested), argmin (ties to the smallest index) and the
-// smallest other value.  (tx0, ty0): template top-left in A; (sx0, sy0):
-// search-window top-left in B.  red: NT/64 ArgminState of LDS scratch.
+//   SSD(u) = E1 + E2(u) - 2 C(u), summed in FP64 and rounded to FP32
+//   (objective of Eq. 7: -C(u) instead, without the energies),
+// surfaces (if requested), argmin (ties to the smallest index), the smallest
+// other value and (if requested) the best offset refined per axis by the
+// parabola through the best value and its axis neighbours.  (tx0, ty0):
+// template top-left in A; (sx0, sy0): search-window top-left in B.
+// red: NT/64 ArgminState of LDS scratch.
 template <int NT>
 __device__ __forceinline__ void ssd_epilogue(const MatchJob& jd, int cpi, int tx0, int ty0, int sx0, int sy0,
                                              const float* Cs, ArgminState* red) {
   const int N = jd.N, r = jd.r, K = 2 * r + 1;
+  const bool corr = jd.obj != 0;
   ArgminState st{INFINITY, INT_MAX, INFINITY, 0};
-  const double E1 = box_sum(jd.satA, jd.wA + 1, ty0, tx0, N);
+  const double E1 = corr ? 0.0 : box_sum(jd.satA, jd.wA + 1, ty0, tx0, N);
   const int ldB = jd.wB + 1;
-  float* surf = jd.surfaces ? jd.surfaces + (size_t)cpi * K * K : nullptr;
-  for (int idx = threadIdx.x; idx < K * K; idx += NT) {
+  auto value = [&](int idx) -> float {
+    if (corr) return -Cs[idx];
     const int uy = idx / K, ux = idx - uy * K;
     const double E2 = box_sum(jd.satB, ldB, sy0 + uy, sx0 + ux, N);
-    const float s = (float)(E1 + E2 - 2.0 * (double)Cs[idx]);
+    return (float)(E1 + E2 - 2.0 * (double)Cs[idx]);
+  };
+  float* surf = jd.surfaces ? jd.surfaces + (size_t)cpi * K * K : nullptr;
+  for (int idx = threadIdx.x; idx < K * K; idx += NT) {
+    const float s = value(idx);
     am_push(st, s, idx);
     if (surf) surf[idx] = s;
   }
@@ -84,9 +101,19 @@ __device__ __forceinline__ void ssd_epilogue(const MatchJob& jd, int cpi, int tx
     Result* res = jd.out + cpi;
     if (st.bad) {
       *res = Result{0, 0, NAN, NAN, kCpNonFinite, 0};
+      if (jd.subpix) jd.subpix[cpi] = make_float2(NAN, NAN);
     } else {
       const int uy = st.bi / K, ux = st.bi - uy * K;
       *res = Result{ux - r, uy - r, st.bv, st.sv, kCpOk, 0};
+      if (jd.subpix) {
+        // the same FP32 values as the surface output
+        float fx = (float)(ux - r), fy = (float)(uy - r);
+        if (ux > 0 && ux < K - 1)
+          fx += (float)parabola_vertex(value(st.bi - 1), st.bv, value(st.bi + 1));
+        if (uy > 0 && uy < K - 1)
+          fy += (float)parabola_vertex(value(st.bi - K), st.bv, value(st.bi + K));
+        jd.subpix[cpi] = make_float2(fx, fy);
+      }
     }
   }
 }
@@ -95,7 +122,10 @@ __device__ __forceinline__ void ssd_epilogue(const MatchJob& jd, int cpi, int tx
 template <int NT>
 __device__ __forceinline__ void oob_result(const MatchJob& jd, int cpi) {
   const int K = 2 * jd.r + 1;
-  if (threadIdx.x == 0) jd.out[cpi] = Result{0, 0, NAN, NAN, kCpOutOfBounds, 0};
+  if (threadIdx.x == 0) {
+    jd.out[cpi] = Result{0, 0, NAN, NAN, kCpOutOfBounds, 0};
+    if (jd.subpix) jd.subpix[cpi] = make_float2(NAN, NAN);
+  }
   if (jd.surfaces) {
     float* s = jd.surfaces + (size_t)cpi * K * K;
     for (int i = threadIdx.x; i < K * K; i += NT) s[i] = NAN;

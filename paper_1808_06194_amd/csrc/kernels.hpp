@@ -25,6 +25,8 @@ struct MatchJob {
   int N, r, m;
   Result* out;
   float* surfaces;
+  float2* subpix;  // nullable: refined offsets
+  int obj;         // 0: SSD (Eq. 4), 1: correlation (Eq. 7)
 };
 
 enum : int { kCpOk = 0, kCpOutOfBounds = 1, kCpNonFinite = 2 };
@@ -67,7 +69,7 @@ namespace cfog {
 // Direct correlation as BF16 MFMA GEMMs with FP32 accumulation (match_direct.hip).
 size_t direct_workspace_bytes(const cfog_job* jobs, int n_jobs, int m, int num_cus);
 // 0 on success, -1 unsupported configuration, -2 HIP error.
-int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, void* ws, int num_cus, hipStream_t st);
+int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, int obj, void* ws, int num_cus, hipStream_t st);
 // Whether the direct path supports template side N with radius r.
 bool direct_supported(int N, int r);
 

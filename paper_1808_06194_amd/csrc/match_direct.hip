@@ -218,7 +218,7 @@ static void launch_nb(const MatchJob& d, const DirectGeom& g, int blocks, hipStr
   hipLaunchKernelGGL(match_direct_kernel<NB>, dim3(blocks), dim3(D_NT), g.lds, st, d, g);
 }
 
-int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, void*, int num_cus, hipStream_t st) {
+int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, int obj, void*, int num_cus, hipStream_t st) {
   if (g_direct_attr == 1) {
     const void* k[D_NB] = {(const void*)match_direct_kernel<1>, (const void*)match_direct_kernel<2>,
                            (const void*)match_direct_kernel<3>, (const void*)match_direct_kernel<4>,
@@ -245,6 +245,8 @@ int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, void*, int num_
     d.n_cps = j.n_cps; d.N = j.N; d.r = j.r; d.m = m;
     d.out = reinterpret_cast<Result*>(j.out);
     d.surfaces = j.surfaces;
+    d.subpix = reinterpret_cast<float2*>(j.subpix);
+    d.obj = obj;
     const int per_cu = std::max(1, (int)(kMaxLds / g.lds));
     const int blocks = std::min(j.n_cps, num_cus * per_cu);
     switch (g.nblk) {

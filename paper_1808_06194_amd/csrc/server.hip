@@ -179,6 +179,7 @@ int launch(cfog_server* s, Slot& sl) {
     j.r = r->r;
     j.out = sl.d_out + cp_off;
     j.surfaces = r->h_surf ? sl.d_surf + sf_off : nullptr;
+    j.subpix = nullptr;
     jobs.push_back(j);
     cp_off += n;
     if (r->h_surf) sf_off += n * K * K;
@@ -344,7 +345,7 @@ int cfog_server_create(int device, const cfog_server_config* cfg_in, cfog_server
   const int path = c.flags & CFOG_PATH_MASK;
   if (c.n_slots < 1 || c.n_slots > 16 || c.max_batch_cps < 1 || c.max_batch_reqs < 1 || c.m < 1 ||
       c.m > cfog::kMaxOrient || !(c.sigma > 0.f) || (int)(4.0 * c.sigma + 0.5) > cfog::kMaxGaussRadius ||
-      (c.flags & ~CFOG_PATH_MASK) ||
+      (c.flags & ~(CFOG_PATH_MASK | CFOG_OBJ_CORR)) ||
       (path != CFOG_PATH_BATCHED_FFT && path != CFOG_PATH_PLAIN_FFT && path != CFOG_PATH_MFMA_BF16))
     return CFOG_EINVAL;
   std::unique_ptr<cfog_server> s(new cfog_server());

@@ -60,8 +60,9 @@ def test_null_context_is_rejected(lib):
 
 def test_job_struct_layout_matches_header():
     from paper_1808_06194_amd import cfog
-    assert ctypes.sizeof(cfog.cfog_job) == 88
+    assert ctypes.sizeof(cfog.cfog_job) == 96
     assert cfog.cfog_job.out.offset == 72 and cfog.cfog_job.surfaces.offset == 80
+    assert cfog.cfog_job.subpix.offset == 88
 
 
 def test_max_window(lib):

@@ -360,3 +360,107 @@ def test_mfma_rejects_radius_above_39(cf):
     A = np.random.default_rng(4).random((200, 200)).astype(np.float32)
     with pytest.raises(cf.CfogError):
         _run_match(cf, A, A, [[100, 100, 100, 100]], 32, 40, flags=cf.PATH_MFMA_BF16)
+
+
+# ------------------------------- Eq. 7 objective and sub-pixel refinement
+
+def _run_opts(cf, A, B, cps, N, r, flags):
+    vA, sA = cf.cfog_extract(_dev(A))
+    vB, sB = cf.cfog_extract(_dev(B))
+    c = _dev(np.asarray(cps, np.int32).reshape(-1, 4))
+    K = 2 * r + 1
+    surf = torch.full((len(c), K, K), float("nan"), device="cuda")
+    sub = torch.full((len(c), 2), float("nan"), device="cuda")
+    job = cf.Job(vA, sA, vB, sB, c, N, r, surfaces=surf, subpix=sub)
+    cf.match_batch([job], flags=flags)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in cf.results(job.out).items()}
+    return res, surf.cpu().numpy(), sub.cpu().numpy()
+
+
+def _check_subpix(fd, surf_gpu, S_ora, dx, dy, r, eps):
+    """fd: GPU (fdx, fdy); surf_gpu: its own surface; S_ora: oracle cost
+    surface; eps: per-element bound of |surf_gpu - S_ora|."""
+    # the refinement is the parabola of the GPU's own (FP32) surface values
+    fs = O.subpixel(surf_gpu.astype(np.float64), dx, dy)
+    assert abs(fd[0] - fs[0]) <= 1e-5 * max(1.0, abs(fs[0])) and abs(fd[1] - fs[1]) <= 1e-5 * max(1.0, abs(fs[1]))
+    # and agrees with the oracle's within the surface bound carried through
+    # the vertex formula (first order, x2), where the fit is well conditioned
+    K = 2 * r + 1
+    fo = O.subpixel(S_ora, dx, dy)
+    iy, ix = dy + r, dx + r
+    for axis, (i0, i1, i2) in enumerate((((iy, ix - 1), (iy, ix), (iy, ix + 1)),
+                                         ((iy - 1, ix), (iy, ix), (iy + 1, ix)))):
+        if not (0 < (ix if axis == 0 else iy) < K - 1):
+            assert fd[axis] == (dx if axis == 0 else dy)
+            continue
+        a, b, c = S_ora[i0], S_ora[i1], S_ora[i2]
+        ea, eb, ec = eps[i0], eps[i1], eps[i2]
+        D = a - 2 * b + c
+        if D <= 4 * (ea + 2 * eb + ec):
+            continue  # curvature below the value error: the vertex is not determined
+        allow = 2 * (abs(c - b) * ea + abs(a - c) * eb + abs(b - a) * ec) / (D * D) + 1e-5
+        assert abs(fd[axis] - fo[axis]) <= allow, (axis, fd, fo, allow)
+
+
+def _opt_case(seed):
+    spec = synth.PairSpec(256, 256, 40, (3.0, 15.0), 20, 8)
+    A, B, _ = synth.make_pair(spec, (seed, 0))
+    cps = synth.grid_cps(256, 256, 48, 10, 4)
+    return A, B, cps, 48, 10
+
+
+@pytest.mark.parametrize("objective", ["ssd", "corr"])
+def test_fft_objective_and_subpixel_against_oracle(cf, objective):
+    A, B, cps, N, r = _opt_case(51)
+    _say("objective", objective, "+ sub-pixel, FFT path, 256^2, 16 CPs, template 48, radius 10, seed 51")
+    flags = cf.PATH_PLAIN_FFT | (cf.OBJ_CORR if objective == "corr" else 0)
+    res, surf, sub = _run_opts(cf, A, B, cps, N, r, flags)
+    D1, D2 = O.cfog(A.astype(np.float64)), O.cfog(B.astype(np.float64))
+    ora = O.match(D1, D2, cps, N, r, surfaces=True, objective=objective, subpix=True)
+    # J = -C carries half the error of S = E1 + E2 - 2C
+    scale = 0.5 if objective == "corr" else 1.0
+    excused = 0
+    for k, cp in enumerate(cps):
+        assert int(res["status"][k]) == 0
+        E1, E2 = O.energies(D1, D2, cp, N, r)
+        eps = scale * parity.SURF_TOL * (E1 + E2)
+        So = ora["surfaces"][k]
+        assert np.all(np.abs(surf[k] - So) <= eps), k
+        dg, do = (int(res["dx"][k]), int(res["dy"][k])), (int(ora["dx"][k]), int(ora["dy"][k]))
+        if dg != do:
+            gap = So[dg[1] + r, dg[0] + r] - So[do[1] + r, do[0] + r]
+            assert gap <= eps[dg[1] + r, dg[0] + r] + eps[do[1] + r, do[0] + r], (k, dg, do, gap)
+            excused += 1
+            continue
+        _check_subpix(sub[k], surf[k], So, dg[0], dg[1], r, eps)
+    _say("excused near-ties", excused)
+
+
+def test_mfma_objective_and_subpixel_against_oracle(cf):
+    A, B, cps, N, r = _opt_case(52)
+    _say("corr + sub-pixel, MFMA path, 256^2, 16 CPs, template 48, radius 10, seed 52")
+    res, surf, sub = _run_opts(cf, A, B, cps, N, r, cf.PATH_MFMA_BF16 | cf.OBJ_CORR)
+    D1, D2 = O.cfog(A.astype(np.float64)), O.cfog(B.astype(np.float64))
+    ora = O.match(D1, D2, cps, N, r, surfaces=True, objective="corr", subpix=True)
+    for k, cp in enumerate(cps):
+        E1, E2 = O.energies(D1, D2, cp, N, r)
+        eps = 0.5 * parity.BF16_TOL * (E1 + E2)
+        So = ora["surfaces"][k]
+        assert np.all(np.abs(surf[k] - So) <= eps), k
+        dg, do = (int(res["dx"][k]), int(res["dy"][k])), (int(ora["dx"][k]), int(ora["dy"][k]))
+        if dg == do:
+            _check_subpix(sub[k], surf[k], So, dg[0], dg[1], r, eps)
+
+
+def test_batched_objective_and_subpixel_equal_plain(cf):
+    A, B, cps, N, r = _opt_case(53)
+    oob = np.vstack([cps, [[1, 1, 1, 1]]]).astype(np.int32)
+    _say("corr + sub-pixel, batched vs plain, seed 53 (one point out of bounds)")
+    r1 = _run_opts(cf, A, B, oob, N, r, cf.PATH_PLAIN_FFT | cf.OBJ_CORR)
+    r2 = _run_opts(cf, A, B, oob, N, r, cf.PATH_BATCHED_FFT | cf.OBJ_CORR)
+    for k in r1[0]:  # bit patterns (the out-of-bounds point holds NaN)
+        assert np.array_equal(r1[0][k].view(np.int32), r2[0][k].view(np.int32)), k
+    assert np.array_equal(r1[1].view(np.int32), r2[1].view(np.int32))
+    assert np.array_equal(r1[2].view(np.int32), r2[2].view(np.int32))
+    assert int(r1[0]["status"][-1]) == cf.CP_OUT_OF_BOUNDS and np.all(np.isnan(r1[2][-1]))
