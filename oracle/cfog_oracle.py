@@ -40,6 +40,18 @@ Beyond the hot path (the first extension of the method):
     formula; the reading taken here is a separable three-point parabola along
     x and along y through the best offset and its axis neighbours.
 
+  * block-based Harris feature point detection in the reference image
+    (Section IV): the image is divided into n x n cells, a 60 x 60 chip
+    centred on each cell is read, and the k pixels with the largest Harris
+    response in the chip become feature points.  The paper does not give the
+    Harris details; the readings taken are: chip centre of cell (i, j) at
+    (floor((2j+1) W / 2n), floor((2i+1) H / 2n)), chip rows and columns
+    [centre - 30, centre + 30) clipped to the image, gradients by [-1, 0, 1]
+    with the chip's borders replicated, the structure tensor smoothed by a
+    normalised Gaussian (sigma 1, radius int(4 sigma + 0.5), chip borders
+    replicated), R = det - kappa trace^2 with kappa = 0.04, and the k largest R
+    with ties to the smallest row-major index in the chip.
+
 Parity pins live in tests/test_oracle_pins.py.  No CFOG value, surface or
 offset is printed in the paper, so agreement with the authors' own code is
 "parity unpinned"; every function here is pinned by closed forms, invariants,
@@ -338,3 +350,45 @@ def energies(D1, D2, cp, N, r):
         for ux in range(2 * r + 1):
             E2[uy, ux] = Q2[uy:uy + N, ux:ux + N].sum()
     return E1, E2
+
+
+# --------------------------------------------- feature points (Section IV)
+
+def harris_response(chip: np.ndarray, sigma: float = 1.0, kappa: float = 0.04) -> np.ndarray:
+    """Harris response R = det(M) - kappa trace(M)^2 of every pixel of a chip,
+    M the Gaussian-weighted structure tensor of the [-1, 0, 1] gradients (chip
+    borders replicated)."""
+    gx, gy = gradients(chip)
+    w = gaussian_weights(sigma)
+    smooth = lambda a: _conv1d_edge(_conv1d_edge(a, w, 1), w, 0)  # noqa: E731
+    a, b, c = smooth(gx * gx), smooth(gx * gy), smooth(gy * gy)
+    return a * c - b * b - kappa * (a + c) ** 2
+
+
+def harris_chip_origin(H: int, W: int, n: int, i: int, j: int, chip: int = 60):
+    """Top-left (y0, x0) and size (h, w) of the chip of cell (i, j), clipped."""
+    cy = ((2 * i + 1) * H) // (2 * n)
+    cx = ((2 * j + 1) * W) // (2 * n)
+    y0, x0 = max(0, cy - chip // 2), max(0, cx - chip // 2)
+    y1, x1 = min(H, cy - chip // 2 + chip), min(W, cx - chip // 2 + chip)
+    return y0, x0, y1 - y0, x1 - x0
+
+
+def harris_grid(img: np.ndarray, n: int, k: int, chip: int = 60, sigma: float = 1.0, kappa: float = 0.04):
+    """Feature points of Section IV: for each of the n x n cells (row-major),
+    the k pixels of its chip with the largest Harris response, in decreasing
+    response (ties: smaller row-major index in the chip first).  Returns
+    (points (n*n*k, 2) int (x, y) in image coordinates, responses (n*n*k,))."""
+    I = np.asarray(img, np.float64)
+    H, W = I.shape
+    pts, vals = [], []
+    for i in range(n):
+        for j in range(n):
+            y0, x0, h, w = harris_chip_origin(H, W, n, i, j, chip)
+            R = harris_response(I[y0:y0 + h, x0:x0 + w], sigma, kappa).reshape(-1)
+            order = np.lexsort((np.arange(R.size), -R))[:k]  # by -R, then by index
+            for q in order:
+                yy, xx = divmod(int(q), w)
+                pts.append((x0 + xx, y0 + yy))
+                vals.append(R[q])
+    return np.array(pts, np.int64).reshape(-1, 2), np.array(vals)

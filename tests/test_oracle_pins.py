@@ -403,3 +403,81 @@ def test_match_with_correlation_objective_and_subpixel():
         assert (res["dx"][k], res["dy"][k], res["best"][k]) == (dx, dy, b)
         assert (res["fdx"][k], res["fdy"][k]) == O.subpixel(J, dx, dy)
     assert np.isnan(res["fdx"][2])
+
+
+# ------------------------------------------ block-based Harris (Section IV)
+
+def _python_loop_harris(chip, sigma=1.0, kappa=0.04):
+    h, w = len(chip), len(chip[0])
+    cl = lambda v, n: min(max(v, 0), n - 1)  # noqa: E731
+    gx = [[chip[y][cl(x + 1, w)] - chip[y][cl(x - 1, w)] for x in range(w)] for y in range(h)]
+    gy = [[chip[cl(y + 1, h)][x] - chip[cl(y - 1, h)][x] for x in range(w)] for y in range(h)]
+    R = int(4 * sigma + 0.5)
+    wt = [np.exp(-j * j / (2 * sigma * sigma)) for j in range(-R, R + 1)]
+    tot = sum(wt)
+    wt = [v / tot for v in wt]
+
+    def smooth(a):
+        t = [[sum(wt[j + R] * a[y][cl(x + j, w)] for j in range(-R, R + 1)) for x in range(w)] for y in range(h)]
+        return [[sum(wt[j + R] * t[cl(y + j, h)][x] for j in range(-R, R + 1)) for x in range(w)] for y in range(h)]
+    A = smooth([[gx[y][x] * gx[y][x] for x in range(w)] for y in range(h)])
+    B = smooth([[gx[y][x] * gy[y][x] for x in range(w)] for y in range(h)])
+    C = smooth([[gy[y][x] * gy[y][x] for x in range(w)] for y in range(h)])
+    return np.array([[A[y][x] * C[y][x] - B[y][x] ** 2 - kappa * (A[y][x] + C[y][x]) ** 2
+                      for x in range(w)] for y in range(h)])
+
+
+def test_harris_response_against_python_loops():
+    chip = np.random.default_rng(4).random((9, 11))
+    np.testing.assert_allclose(O.harris_response(chip), _python_loop_harris(chip.tolist()), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.5, 0.25), (-1.0, 2.0), (0.0, 1.5)])
+def test_harris_of_a_ramp_is_the_closed_form(alpha, beta):
+    """I = alpha x + beta y: gradients (2 alpha, 2 beta) everywhere off the
+    border, so M is rank one (det = 0) and R = -kappa (4 alpha^2 + 4 beta^2)^2
+    wherever the smoothing window avoids the border rows and columns."""
+    y, x = np.mgrid[0:30, 0:30].astype(np.float64)
+    R = O.harris_response(alpha * x + beta * y)
+    want = -0.04 * (4 * alpha ** 2 + 4 * beta ** 2) ** 2
+    np.testing.assert_allclose(R[5:-5, 5:-5], want, rtol=1e-12, atol=1e-12)
+
+
+def test_harris_is_transpose_symmetric():
+    chip = np.random.default_rng(5).random((20, 20))
+    np.testing.assert_allclose(O.harris_response(chip.T), O.harris_response(chip).T, rtol=1e-13, atol=1e-15)
+
+
+def test_harris_constant_image_selects_first_pixels():
+    pts, vals = O.harris_grid(np.full((120, 120), 3.0), 2, 3)
+    assert np.all(vals == 0.0)
+    # cell (0, 0): chip centred at (30, 30) -> top-left (0, 0); ties: first three pixels
+    assert [tuple(p) for p in pts[:3]] == [(0, 0), (1, 0), (2, 0)]
+    y0, x0, h, w = O.harris_chip_origin(120, 120, 2, 1, 1)
+    assert (y0, x0, h, w) == (60, 60, 60, 60)
+
+
+def test_harris_finds_the_corners_of_a_square():
+    img = np.zeros((60, 60))
+    img[20:40, 20:40] = 1.0
+    pts, vals = O.harris_grid(img, 1, 4)
+    for x, y in pts:
+        # each of the four strongest responses sits within a pixel of a corner
+        assert min(abs(x - cx) + abs(y - cy) for cx, cy in [(19.5, 19.5), (39.5, 19.5), (19.5, 39.5), (39.5, 39.5)]) <= 1.0
+    assert len({(int(x) // 30, int(y) // 30) for x, y in pts}) == 4  # one per corner
+
+
+def test_harris_grid_chip_clipping_and_order():
+    img = np.random.default_rng(6).random((100, 130))
+    pts, vals = O.harris_grid(img, 3, 5, chip=60)
+    assert pts.shape == (45, 2)
+    for c in range(9):
+        v = vals[5 * c:5 * c + 5]
+        assert np.all(np.diff(v) <= 0)
+        i, j = divmod(c, 3)
+        y0, x0, h, w = O.harris_chip_origin(100, 130, 3, i, j)
+        assert h <= 60 and w <= 60 and y0 >= 0 and x0 >= 0 and y0 + h <= 100 and x0 + w <= 130
+        R = O.harris_response(img[y0:y0 + h, x0:x0 + w])
+        assert vals[5 * c] == R.max()
+        for (x, y), val in zip(pts[5 * c:5 * c + 5], v):
+            assert R[y - y0, x - x0] == val
