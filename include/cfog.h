@@ -202,6 +202,35 @@ int32_t cfog_plan_for(cfog_ctx* ctx, int32_t N, int32_t r, int32_t m);
  * or 0 if unsupported. */
 int32_t cfog_fft_size(int32_t N, int32_t r);
 
+/* ------------------------------------------------------ feature points
+ *
+ * cfog_harris_grid - block-based Harris feature points in a reference image
+ * (Section IV): the image is divided into n x n cells; for cell (i, j)
+ * (row-major) the chip of `chip` x `chip` pixels centred at
+ * (floor((2j+1) W / 2n), floor((2i+1) H / 2n)), clipped to the image, is read,
+ * and its k pixels with the largest Harris response become feature points.
+ * Details the paper leaves open, as implemented: gradients by [-1, 0, 1]
+ * with the chip's borders replicated; the structure tensor of the gradients
+ * smoothed by a normalised Gaussian of std `sigma` (radius int(4 sigma + 0.5),
+ * chip borders replicated); response R = det - kappa trace^2 (kappa = 0.04 is
+ * the usual choice); ties in R go to the smaller row-major index in the chip.
+ *   d_img       DEVICE [H][row_stride] fp32 image.
+ *   n, k        cells per axis (>= 1) and points per chip (1..64; every chip
+ *               must hold at least k pixels).
+ *   chip        chip side, 1..64 (the paper uses 60).
+ *   d_cps       DEVICE output [n*n*k] cfog_cp, 16-byte aligned: for cell c and
+ *               rank q (decreasing R) entry c*k + q holds (x, y, x, y), i.e. a
+ *               control point whose search centre defaults to the same
+ *               position; (-1, -1, -1, -1) if the chip has no finite response
+ *               left.
+ *   d_response  nullable DEVICE output [n*n*k] fp32: R of each point.
+ * Asynchronous on `stream`.  CFOG_EINVAL for bad arguments, CFOG_EUNSUPPORTED
+ * for a Gaussian radius above 8.
+ */
+int cfog_harris_grid(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride, int32_t n,
+                     int32_t k, int32_t chip, float sigma, float kappa, cfog_cp* d_cps, float* d_response,
+                     void* stream);
+
 /* ------------------------------------------------------------- serving
  *
  * A matching server: a request loop that keeps the CFOG volumes of

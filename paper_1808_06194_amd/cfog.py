@@ -38,7 +38,7 @@ OBJ_CORR = 0x400
 EXPORTS = (
     "cfog_ctx_create", "cfog_ctx_destroy", "cfog_ctx_last_error", "cfog_status_str",
     "cfog_extract", "cfog_extract_workspace_size", "match_batch_workspace_size", "match_batch",
-    "cfog_max_window", "cfog_fft_size", "cfog_set_plan", "cfog_plan_for",
+    "cfog_max_window", "cfog_fft_size", "cfog_set_plan", "cfog_plan_for", "cfog_harris_grid",
     "cfog_server_create", "cfog_server_destroy", "cfog_server_add_pair", "cfog_server_submit",
     "cfog_server_poll", "cfog_server_get_stats",
 )
@@ -115,6 +115,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cfog_set_plan.argtypes = [vp, i32, i32, i32]
     lib.cfog_plan_for.argtypes = [vp, i32, i32, i32]
     lib.cfog_plan_for.restype = i32
+    lib.cfog_harris_grid.argtypes = [vp, vp, i32, i32, i64, i32, i32, i32, ctypes.c_float, ctypes.c_float, vp, vp, vp]
     lib.cfog_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(cfog_server_config), ctypes.POINTER(vp)]
     lib.cfog_server_destroy.argtypes = [vp]
     lib.cfog_server_add_pair.argtypes = [vp, vp, i32, i32, i64, vp, i32, i32, i64, ctypes.POINTER(i32)]
@@ -275,6 +276,23 @@ def match_batch(jobs: List[Job], m: int = 9, flags: int = PATH_PLAIN_FFT, stream
         break
     _check(rc, "match_batch")
     return [j.out for j in jobs]
+
+
+def harris_grid(img: torch.Tensor, n: int, k: int, chip: int = 60, sigma: float = 1.0, kappa: float = 0.04,
+                stream=None):
+    """Block-based Harris feature points of a 2-D cuda fp32 image (see
+    cfog_harris_grid in include/cfog.h).  Returns (cps (n*n*k, 4) int32 cuda
+    tensor of (x, y, x, y), responses (n*n*k,) fp32), asynchronously."""
+    if img.dim() != 2 or img.dtype != torch.float32 or not img.is_cuda or img.stride(1) != 1:
+        raise ValueError("img must be a 2-D row-contiguous cuda float32 tensor")
+    H, W = img.shape
+    cps = torch.empty((n * n * k, 4), dtype=torch.int32, device=img.device)
+    resp = torch.empty((n * n * k,), dtype=torch.float32, device=img.device)
+    rc = load().cfog_harris_grid(context(img.device.index).handle, img.data_ptr(), H, W, img.stride(0), int(n),
+                                 int(k), int(chip), float(sigma), float(kappa), cps.data_ptr(), resp.data_ptr(),
+                                 _stream_ptr(stream))
+    _check(rc, "cfog_harris_grid")
+    return cps, resp
 
 
 def set_plan(N: int, r: int, P: int, device: Optional[int] = None):
