@@ -18,6 +18,9 @@ Workloads (--workload):
       [40, 120], radii in [5, 30], 50-600 control points per pair; --path
       batched (fused persistent launches, autotuned FFT sizes, hipGraph
       replay) or plain (one launch per pair).
+  harris_8192: block-based Harris feature points (Section IV) of one 8192^2
+      image: 128 x 128 cells, 60 x 60 chips, 4 points per chip; reports
+      feature points/s (the control-point producer, not a CP-match rate).
   serve: the matching server with 32 resident pairs (8 each of 1024^2,
       2048^2, 4096^2, 8192^2) under open-loop Poisson arrivals of requests
       (1-500 control points, template 40-128, radius 5-32): latency
@@ -157,7 +160,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="plain_2048",
-                    choices=["plain_2048", "plain_256", "precision_4096", "batch_64", "serve"])
+                    choices=["plain_2048", "plain_256", "precision_4096", "batch_64", "serve", "harris_8192"])
     ap.add_argument("--path", choices=["plain", "batched", "fft", "mfma"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -176,6 +179,9 @@ def main():
         sys.exit(2)
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "harris_8192":
+        run_harris(args)
         return
 
     pairs = make_workload(args.workload)  # before anything touches the GPU (worker processes fork)
@@ -310,6 +316,60 @@ def main():
         del junk
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pairs, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def harris_flops_per_px(R: int = 4) -> int:
+    """Flops per chip pixel: gradients (2), the three products (3), two
+    Gaussian passes of 2R+1 taps on three channels (2 x 3 x 2 (2R+1)) and the
+    response (6)."""
+    return 2 + 3 + 12 * (2 * R + 1) + 6
+
+
+def run_harris(args):
+    from paper_1808_06194_amd import synth
+    A, _, _ = synth.make_pair(synth.area_scaled_spec(8192, 8), (5, 0))
+    import torch
+    from paper_1808_06194_amd import cfog
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    img = torch.from_numpy(A).to(dev)
+    n, k, chip = 128, 4, 60
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        cfog.harris_grid(img, n, k, chip, stream=stream)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        cfog.harris_grid(img, n, k, chip, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    kms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    t = float(np.mean(kms)) * 1e-3
+    chips = n * n
+    pts = chips * k
+    bytes_launch = chips * chip * chip * 4 + pts * 20
+    flops = chips * chip * chip * harris_flops_per_px()
+    gbs, tfs = bytes_launch / t / 1e9, flops / t / 1e12
+    hbm = dict(achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4))
+    alu = dict(achieved=round(tfs, 3), peak=FP32_PEAK_TFS, unit="TFLOP/s", frac=round(tfs / FP32_PEAK_TFS, 4))
+    roof = dict(alu, bound="alu") if flops / (FP32_PEAK_TFS * 1e12) > bytes_launch / (HBM_PEAK_GBS * 1e9) \
+        else dict(hbm, bound="hbm")
+    roof.update(kernel="harris_grid_kernel", traffic=None, bytes_per_launch=bytes_launch, flops_per_launch=flops,
+                hbm=hbm, alu=alu)
+    out = {
+        "metric": "Harris feature points/s (block-based, Section IV) on 1 MI355X",
+        "value": round(pts / t, 1), "unit": "feature points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "harris_8192: one 8192^2 image, 128 x 128 cells, 60 x 60 chips, 4 points per chip, "
+                               "sigma 1, kappa 0.04", "chips": chips, "points": pts},
+        "latency_ms": {"p50": round(float(np.percentile(kms, 50)), 4), "p99": round(float(np.percentile(kms, 99)), 4)},
+        "roofline": roof,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -52,6 +52,16 @@ Beyond the hot path (the first extension of the method):
     replicated), R = det - kappa trace^2 with kappa = 0.04, and the k largest R
     with ties to the smallest row-major index in the chip.
 
+  * iterative outlier rejection (Section IV): fit a cubic polynomial mapping
+    from the points in A to their matches in B by least squares, remove the
+    point with the largest residual, and repeat until the RMSE falls below a
+    threshold (3.5 pixels in Table V).  Readings: coordinates normalised by
+    the bounding box of the input points (centre and half-extent per axis)
+    before forming the ten monomials; residual = Euclidean distance between
+    the mapped point and its match; RMSE = sqrt(mean residual^2); ties in the
+    largest residual go to the smaller index; the loop also stops when ten
+    points (the model's size) remain.
+
 Parity pins live in tests/test_oracle_pins.py.  No CFOG value, surface or
 offset is printed in the paper, so agreement with the authors' own code is
 "parity unpinned"; every function here is pinned by closed forms, invariants,
@@ -392,3 +402,46 @@ def harris_grid(img: np.ndarray, n: int, k: int, chip: int = 60, sigma: float = 
                 pts.append((x0 + xx, y0 + yy))
                 vals.append(R[q])
     return np.array(pts, np.int64).reshape(-1, 2), np.array(vals)
+
+
+# --------------------------------------------- outlier rejection (Section IV)
+
+def cubic_terms(u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """The ten monomials of a bivariate cubic, (n, 10):
+    1, u, v, u^2, u v, v^2, u^3, u^2 v, u v^2, v^3."""
+    return np.stack([np.ones_like(u), u, v, u * u, u * v, v * v, u ** 3, u * u * v, u * v * v, v ** 3], axis=1)
+
+
+def normalise_points(src: np.ndarray):
+    """(centre, half-extent) per axis of the bounding box of the points; a
+    degenerate extent becomes 1."""
+    lo, hi = src.min(axis=0), src.max(axis=0)
+    c = 0.5 * (lo + hi)
+    s = 0.5 * (hi - lo)
+    s[s <= 0] = 1.0
+    return c, s
+
+
+def reject_outliers(src, dst, threshold: float = 3.5):
+    """Iterative rejection with a cubic polynomial model (Section IV).
+    src, dst: (n, 2) point coordinates (x, y) in A and their matches in B.
+    Returns (keep (n,) bool, coefficients (10, 2) in normalised coordinates,
+    rmse of the last fit, number of points removed)."""
+    P = np.asarray(src, np.float64)
+    Q = np.asarray(dst, np.float64)
+    n = len(P)
+    if n < 10:
+        raise ValueError("a cubic model needs at least 10 points")
+    c, s = normalise_points(P)
+    Tm = cubic_terms((P[:, 0] - c[0]) / s[0], (P[:, 1] - c[1]) / s[1])
+    keep = np.ones(n, bool)
+    removed = 0
+    while True:
+        idx = np.flatnonzero(keep)
+        coef, *_ = np.linalg.lstsq(Tm[idx], Q[idx], rcond=None)
+        res = np.sqrt(np.sum((Tm[idx] @ coef - Q[idx]) ** 2, axis=1))
+        rmse = float(np.sqrt(np.mean(res ** 2)))
+        if rmse < threshold or len(idx) <= 10:
+            return keep, coef, rmse, removed
+        keep[idx[int(np.argmax(res))]] = False  # argmax: the first of equal maxima
+        removed += 1

@@ -3,7 +3,7 @@
 // on each cell is read and its k pixels with the largest Harris response
 // become feature points, which are the control points the matcher takes.
 //
-// One workgroup per chip, everything in LDS:
+// One workgroup per chip, everything in LDS (two chips per CU):
 //   1. the chip (clipped to the image);
 //   2. gradients by [-1, 0, 1] with the chip's borders replicated;
 //   3. the structure tensor products gx^2, gx gy, gy^2 smoothed by a
@@ -36,12 +36,23 @@ struct HarrisArgs {
 
 __device__ __forceinline__ int hclamp(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
 
+// Dynamic LDS: five chip-sized arrays (at most 80 KB, so two chips share a
+// CU).  The chip is dead once the gradients exist and shares storage with the
+// first smoothed product; the response reuses gx.
+static size_t harris_lds_bytes(int chip) { return (size_t)5 * chip * chip * sizeof(float); }
+
 __global__ __launch_bounds__(HR_NT) void harris_grid_kernel(HarrisArgs a) {
-  constexpr int MX = HR_MAX_CHIP * HR_MAX_CHIP;
-  __shared__ float img[MX], gx[MX], gy[MX], ta[MX], tb[MX], tc[MX];
+  extern __shared__ float hsm[];
+  const int cc = a.chip * a.chip;
+  float* gx = hsm;
+  float* gy = gx + cc;
+  float* ta = gy + cc;
+  float* tb = ta + cc;
+  float* tc = tb + cc;
+  float* img = ta;  // read only by the gradient pass
+  float* Rv = gx;   // written by the vertical pass, after the last gx read
   __shared__ float bestv[HR_NT / 64];
   __shared__ int besti[HR_NT / 64];
-  float* Rv = img;  // the response reuses the chip's storage
   const int cell = blockIdx.x, ci = cell / a.n, cj = cell - ci * a.n;
   // chip of cell (ci, cj): centred at ((2 cj + 1) W / 2n, (2 ci + 1) H / 2n), clipped
   const int cy = (int)(((int64_t)(2 * ci + 1) * a.H) / (2 * a.n));
@@ -90,7 +101,7 @@ __global__ __launch_bounds__(HR_NT) void harris_grid_kernel(HarrisArgs a) {
       sc = fmaf(wj, tc[q], sc);
     }
     const float tr = sa + sc;
-    Rv[i] = sa * sc - sb * sb - a.kappa * tr * tr;  // img is no longer read
+    Rv[i] = sa * sc - sb * sb - a.kappa * tr * tr;
   }
   __syncthreads();
 
@@ -180,7 +191,15 @@ extern "C" int cfog_harris_grid(cfog_ctx* ctx, const float* d_img, int32_t H, in
   for (int j = 0; j <= R; ++j) a.w[j] = (float)(ws[j] / tot);
   a.cps = d_cps;
   a.resp = d_response;
-  hipLaunchKernelGGL(cfog::harris_grid_kernel, dim3(n * n), dim3(cfog::HR_NT), 0, (hipStream_t)stream, a);
+  static int attr = 1;
+  if (attr == 1)
+    attr = hipFuncSetAttribute((const void*)cfog::harris_grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)cfog::harris_lds_bytes(cfog::HR_MAX_CHIP)) == hipSuccess
+               ? 0
+               : -1;
+  if (attr != 0) return CFOG_EHIP;
+  hipLaunchKernelGGL(cfog::harris_grid_kernel, dim3(n * n), dim3(cfog::HR_NT), cfog::harris_lds_bytes(chip),
+                     (hipStream_t)stream, a);
   if (hipGetLastError() != hipSuccess) return CFOG_EHIP;
   return CFOG_OK;
 }

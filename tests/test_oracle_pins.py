@@ -481,3 +481,80 @@ def test_harris_grid_chip_clipping_and_order():
         assert vals[5 * c] == R.max()
         for (x, y), val in zip(pts[5 * c:5 * c + 5], v):
             assert R[y - y0, x - x0] == val
+
+
+# ------------------------------------------- outlier rejection (Section IV)
+
+def _cubic_map(P, C):
+    """Apply a cubic (10, 2) given in pixel coordinates of the normalised
+    frame built from P itself."""
+    c, s = O.normalise_points(P)
+    return O.cubic_terms((P[:, 0] - c[0]) / s[0], (P[:, 1] - c[1]) / s[1]) @ C
+
+
+def _gauss_solve(A, b):
+    """Least squares by hand: normal equations and Gaussian elimination with
+    partial pivoting, in plain Python."""
+    n = len(A[0])
+    M = [[sum(A[k][i] * A[k][j] for k in range(len(A))) for j in range(n)] +
+         [sum(A[k][i] * b[k] for k in range(len(A)))] for i in range(n)]
+    for col in range(n):
+        piv = max(range(col, n), key=lambda r: abs(M[r][col]))
+        M[col], M[piv] = M[piv], M[col]
+        for r in range(col + 1, n):
+            f = M[r][col] / M[col][col]
+            for cc in range(col, n + 1):
+                M[r][cc] -= f * M[col][cc]
+    x = [0.0] * n
+    for r in range(n - 1, -1, -1):
+        x[r] = (M[r][n] - sum(M[r][cc] * x[cc] for cc in range(r + 1, n))) / M[r][r]
+    return x
+
+
+def test_cubic_fit_against_hand_normal_equations():
+    rng = np.random.default_rng(8)
+    P = rng.uniform(0, 500, (40, 2))
+    Q = P + rng.normal(0, 2.0, (40, 2))
+    keep, coef, rmse, removed = O.reject_outliers(P, Q, threshold=1e9)  # no removal: one fit
+    assert removed == 0 and keep.all()
+    c, s = O.normalise_points(P)
+    T = O.cubic_terms((P[:, 0] - c[0]) / s[0], (P[:, 1] - c[1]) / s[1]).tolist()
+    for axis in range(2):
+        np.testing.assert_allclose(coef[:, axis], _gauss_solve(T, Q[:, axis].tolist()), rtol=1e-8, atol=1e-8)
+
+
+def test_exact_cubic_map_is_recovered_without_removal():
+    rng = np.random.default_rng(9)
+    P = rng.uniform(100, 900, (60, 2))
+    C = rng.normal(0, 3.0, (10, 2))
+    C[1, 0] += 400.0  # mostly x -> x', y -> y'
+    C[2, 1] += 400.0
+    Q = _cubic_map(P, C)
+    keep, coef, rmse, removed = O.reject_outliers(P, Q)
+    assert removed == 0 and keep.all() and rmse < 1e-9
+    np.testing.assert_allclose(coef, C, rtol=1e-9, atol=1e-8)
+
+
+def test_gross_outliers_are_removed_first():
+    rng = np.random.default_rng(10)
+    P = rng.uniform(0, 1000, (80, 2))
+    C = np.zeros((10, 2))
+    C[0] = [500.0, 500.0]
+    C[1, 0], C[2, 1] = 500.0, 500.0     # identity in pixel units
+    C[3, 0], C[5, 1] = 2.0, -1.5         # mild curvature
+    Q = _cubic_map(P, C) + rng.normal(0, 0.5, (80, 2))
+    bad = [3, 17, 42, 77]
+    Q[bad] += np.array([[40.0, -25.0], [-30.0, 60.0], [55.0, 10.0], [-20.0, -45.0]])
+    keep, coef, rmse, removed = O.reject_outliers(P, Q, threshold=1.0)
+    assert set(np.flatnonzero(~keep)) == set(bad) and removed == 4
+    assert 0.3 < rmse < 1.0
+
+
+def test_rejection_stops_at_ten_points_and_needs_ten():
+    rng = np.random.default_rng(11)
+    P = rng.uniform(0, 100, (12, 2))
+    Q = rng.uniform(0, 100, (12, 2))   # no model fits: removal continues to ten points
+    keep, coef, rmse, removed = O.reject_outliers(P, Q, threshold=0.0)
+    assert keep.sum() == 10 and removed == 2 and rmse < 1e-6  # ten points are interpolated
+    with pytest.raises(ValueError):
+        O.reject_outliers(P[:9], Q[:9])
