@@ -231,6 +231,38 @@ int cfog_harris_grid(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, in
                      int32_t k, int32_t chip, float sigma, float kappa, cfog_cp* d_cps, float* d_response,
                      void* stream);
 
+/* ---------------------------------------------------- outlier rejection
+ *
+ * cfog_reject_outliers - iterative outlier rejection of control points with a
+ * cubic polynomial mapping model (Section IV): fit the model to all kept
+ * points by least squares, remove the point with the largest residual, repeat
+ * until the RMSE is below `threshold` pixels (Table V uses 3.5) or ten points
+ * (the model's size) remain.  Readings of what the paper leaves open: source
+ * coordinates normalised by the centre and half-extent of their bounding box;
+ * residual = Euclidean distance between the mapped source point and its match;
+ * RMSE = sqrt(mean residual^2) over the kept points; ties in the largest
+ * residual go to the smaller index.  FP64 normal equations, Cholesky solve.
+ *   d_src, d_dst  DEVICE [n][2] fp32 (x, y): points in A and their matches in
+ *                 B (e.g. (x + fdx, y + fdy) from match results), 8-byte aligned.
+ *   n             10 .. 2^20 points; the work grows as n * (points removed).
+ *   d_keep        DEVICE output [n] bytes: 1 kept, 0 removed.
+ *   d_result      DEVICE output, one cfog_reject_result, 8-byte aligned.
+ * Asynchronous on `stream`; CFOG_EINVAL for bad arguments.
+ */
+typedef struct {
+  double coef[10][2];    /* x' = sum_a coef[a][0] t_a, y' = sum_a coef[a][1] t_a with
+                            t = (1, u, v, u^2, u v, v^2, u^3, u^2 v, u v^2, v^3) */
+  double centre[2];      /* u = (x - centre[0]) / half_extent[0], v likewise with y */
+  double half_extent[2];
+  double rmse;           /* of the final fit (NaN if status != 0) */
+  int32_t removed, n_kept;
+  int32_t status;        /* 0 ok; 1 singular or non-finite fit (coef NaN) */
+  int32_t pad;
+} cfog_reject_result;
+
+int cfog_reject_outliers(cfog_ctx* ctx, const float* d_src, const float* d_dst, int32_t n, float threshold,
+                         unsigned char* d_keep, cfog_reject_result* d_result, void* stream);
+
 /* ------------------------------------------------------------- serving
  *
  * A matching server: a request loop that keeps the CFOG volumes of

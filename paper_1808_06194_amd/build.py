@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcfog.so")
 
-SOURCES = ["abi.hip", "cfog_extract.hip", "match_fft.hip", "match_direct.hip", "server.hip", "harris.hip"]
+SOURCES = ["abi.hip", "cfog_extract.hip", "match_fft.hip", "match_direct.hip", "server.hip", "harris.hip", "outlier.hip"]
 ARCH = os.environ.get("CFOG_OFFLOAD_ARCH", "gfx950")
 
 

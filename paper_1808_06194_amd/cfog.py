@@ -39,6 +39,7 @@ EXPORTS = (
     "cfog_ctx_create", "cfog_ctx_destroy", "cfog_ctx_last_error", "cfog_status_str",
     "cfog_extract", "cfog_extract_workspace_size", "match_batch_workspace_size", "match_batch",
     "cfog_max_window", "cfog_fft_size", "cfog_set_plan", "cfog_plan_for", "cfog_harris_grid",
+    "cfog_reject_outliers",
     "cfog_server_create", "cfog_server_destroy", "cfog_server_add_pair", "cfog_server_submit",
     "cfog_server_poll", "cfog_server_get_stats",
 )
@@ -57,6 +58,14 @@ class cfog_job(ctypes.Structure):
         ("cps", ctypes.c_void_p), ("n_cps", ctypes.c_int32), ("N", ctypes.c_int32), ("r", ctypes.c_int32),
         ("pad_", ctypes.c_int32), ("out", ctypes.c_void_p), ("surfaces", ctypes.c_void_p),
         ("subpix", ctypes.c_void_p),
+    ]
+
+
+class cfog_reject_result(ctypes.Structure):
+    _fields_ = [
+        ("coef", (ctypes.c_double * 2) * 10), ("centre", ctypes.c_double * 2), ("half_extent", ctypes.c_double * 2),
+        ("rmse", ctypes.c_double), ("removed", ctypes.c_int32), ("n_kept", ctypes.c_int32),
+        ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
 
@@ -116,6 +125,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cfog_plan_for.argtypes = [vp, i32, i32, i32]
     lib.cfog_plan_for.restype = i32
     lib.cfog_harris_grid.argtypes = [vp, vp, i32, i32, i64, i32, i32, i32, ctypes.c_float, ctypes.c_float, vp, vp, vp]
+    lib.cfog_reject_outliers.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, vp]
     lib.cfog_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(cfog_server_config), ctypes.POINTER(vp)]
     lib.cfog_server_destroy.argtypes = [vp]
     lib.cfog_server_add_pair.argtypes = [vp, vp, i32, i32, i64, vp, i32, i32, i64, ctypes.POINTER(i32)]
@@ -293,6 +303,30 @@ def harris_grid(img: torch.Tensor, n: int, k: int, chip: int = 60, sigma: float 
                                  _stream_ptr(stream))
     _check(rc, "cfog_harris_grid")
     return cps, resp
+
+
+def reject_outliers(src: torch.Tensor, dst: torch.Tensor, threshold: float = 3.5, stream=None):
+    """Iterative cubic-polynomial outlier rejection (see cfog_reject_outliers
+    in include/cfog.h).  src, dst: (n, 2) cuda fp32 point coordinates.
+    Returns (keep (n,) uint8 cuda tensor, result dict with coef (10, 2),
+    centre, half_extent, rmse, removed, n_kept, status); synchronises."""
+    if src.shape != dst.shape or src.dim() != 2 or src.shape[1] != 2:
+        raise ValueError("src and dst must be (n, 2)")
+    src = src.to(torch.float32).contiguous()
+    dst = dst.to(torch.float32).contiguous()
+    n = src.shape[0]
+    keep = torch.empty((n,), dtype=torch.uint8, device=src.device)
+    res = torch.empty((ctypes.sizeof(cfog_reject_result),), dtype=torch.uint8, device=src.device)
+    rc = load().cfog_reject_outliers(context(src.device.index).handle, src.data_ptr(), dst.data_ptr(), n,
+                                     float(threshold), keep.data_ptr(), res.data_ptr(), _stream_ptr(stream))
+    _check(rc, "cfog_reject_outliers")
+    torch.cuda.synchronize(src.device)
+    r = cfog_reject_result.from_buffer_copy(bytes(res.cpu().numpy()))
+    import numpy as np
+    out = dict(coef=np.array([[r.coef[a][c] for c in range(2)] for a in range(10)]),
+               centre=np.array(list(r.centre)), half_extent=np.array(list(r.half_extent)), rmse=r.rmse,
+               removed=r.removed, n_kept=r.n_kept, status=r.status)
+    return keep, out
 
 
 def set_plan(N: int, r: int, P: int, device: Optional[int] = None):

@@ -1,0 +1,269 @@
+// Iterative outlier rejection of control points with a cubic polynomial
+// mapping model (Section IV of Ye et al.): fit the model to all kept points by
+// least squares, remove the point with the largest residual, and repeat until
+// the RMSE falls below a threshold (or ten points, the model's size, remain).
+//
+// One workgroup per point set.  Per iteration, in FP64:
+//   1. the 55 + 20 entries of the normal equations (ten monomials of the
+//      normalised source coordinates; both target coordinates) summed over
+//      the kept points (per-thread partials, wave shuffles, LDS);
+//   2. a Cholesky solve of the 10 x 10 system for both right-hand sides;
+//   3. residuals |model(p) - q| of the kept points, their squared sum and the
+//      largest one (ties to the smaller index).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <limits.h>
+#include "cfog.h"
+
+namespace cfog {
+
+constexpr int RJ_NT = 256;
+constexpr int RJ_NW = RJ_NT / 64;
+constexpr int RJ_T = 10;                   // monomials of a bivariate cubic
+constexpr int RJ_G = RJ_T * (RJ_T + 1) / 2;  // unique entries of the normal matrix
+constexpr int RJ_V = RJ_G + 2 * RJ_T;      // plus the two right-hand sides
+
+__device__ __forceinline__ void cubic_terms(double u, double v, double (&t)[RJ_T]) {
+  t[0] = 1.0;
+  t[1] = u;
+  t[2] = v;
+  t[3] = u * u;
+  t[4] = u * v;
+  t[5] = v * v;
+  t[6] = u * u * u;
+  t[7] = u * u * v;
+  t[8] = u * v * v;
+  t[9] = v * v * v;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__global__ __launch_bounds__(RJ_NT) void reject_kernel(const float2* __restrict__ src, const float2* __restrict__ dst,
+                                                       int n, float thr, unsigned char* keep, cfog_reject_result* out) {
+  __shared__ double part[RJ_NW][RJ_V];
+  __shared__ double sys[RJ_V];
+  __shared__ double coef[RJ_T][2];
+  __shared__ double rd[RJ_NW];
+  __shared__ int ri[RJ_NW];
+  __shared__ double ext[4];
+  __shared__ int done, active, removed;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+  // bounding box of all points -> centre and half-extent per axis
+  {
+    double mn[2] = {INFINITY, INFINITY}, mx[2] = {-INFINITY, -INFINITY};
+    for (int i = tid; i < n; i += RJ_NT) {
+      const float2 p = src[i];
+      mn[0] = fmin(mn[0], (double)p.x);
+      mn[1] = fmin(mn[1], (double)p.y);
+      mx[0] = fmax(mx[0], (double)p.x);
+      mx[1] = fmax(mx[1], (double)p.y);
+      keep[i] = 1;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      mn[0] = fmin(mn[0], __shfl_xor(mn[0], o, 64));
+      mn[1] = fmin(mn[1], __shfl_xor(mn[1], o, 64));
+      mx[0] = fmax(mx[0], __shfl_xor(mx[0], o, 64));
+      mx[1] = fmax(mx[1], __shfl_xor(mx[1], o, 64));
+    }
+    if (lane == 0) {
+      part[wv][0] = mn[0];
+      part[wv][1] = mn[1];
+      part[wv][2] = mx[0];
+      part[wv][3] = mx[1];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < RJ_NW; ++w) {
+        mn[0] = fmin(mn[0], part[w][0]);
+        mn[1] = fmin(mn[1], part[w][1]);
+        mx[0] = fmax(mx[0], part[w][2]);
+        mx[1] = fmax(mx[1], part[w][3]);
+      }
+      for (int a = 0; a < 2; ++a) {
+        const double half = 0.5 * (mx[a] - mn[a]);
+        ext[a] = 0.5 * (mn[a] + mx[a]);
+        ext[2 + a] = half > 0.0 ? half : 1.0;
+      }
+      done = 0;
+      active = n;
+      removed = 0;
+    }
+    __syncthreads();
+  }
+  const double cx = ext[0], cy = ext[1], sx = ext[2], sy = ext[3];
+
+  for (;;) {
+    // 1. normal equations over the kept points
+    double acc[RJ_V];
+#pragma unroll
+    for (int e = 0; e < RJ_V; ++e) acc[e] = 0.0;
+    for (int i = tid; i < n; i += RJ_NT) {
+      if (!keep[i]) continue;
+      const float2 p = src[i], q = dst[i];
+      double t[RJ_T];
+      cubic_terms(((double)p.x - cx) / sx, ((double)p.y - cy) / sy, t);
+      int e = 0;
+#pragma unroll
+      for (int a = 0; a < RJ_T; ++a)
+#pragma unroll
+        for (int b = a; b < RJ_T; ++b) acc[e++] += t[a] * t[b];
+#pragma unroll
+      for (int a = 0; a < RJ_T; ++a) {
+        acc[RJ_G + 2 * a] += t[a] * (double)q.x;
+        acc[RJ_G + 2 * a + 1] += t[a] * (double)q.y;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < RJ_V; ++e) {
+      const double v = wave_sum(acc[e]);
+      if (lane == 0) part[wv][e] = v;
+    }
+    __syncthreads();
+    if (tid < RJ_V) {
+      double v = 0.0;
+      for (int w = 0; w < RJ_NW; ++w) v += part[w][tid];
+      sys[tid] = v;
+    }
+    __syncthreads();
+    // 2. Cholesky solve (one thread: 10 x 10)
+    if (tid == 0) {
+      double L[RJ_T][RJ_T];
+      int e = 0;
+      for (int a = 0; a < RJ_T; ++a)
+        for (int b = a; b < RJ_T; ++b) {
+          L[b][a] = sys[e];
+          L[a][b] = sys[e];
+          ++e;
+        }
+      bool ok = true;
+      for (int j = 0; j < RJ_T && ok; ++j) {
+        double d = L[j][j];
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        if (!(d > 0.0)) {
+          ok = false;
+          break;
+        }
+        L[j][j] = sqrt(d);
+        for (int i = j + 1; i < RJ_T; ++i) {
+          double s = L[i][j];
+          for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+          L[i][j] = s / L[j][j];
+        }
+      }
+      if (!ok) {
+        done = 2;  // singular normal matrix (degenerate point layout)
+      } else {
+        for (int c = 0; c < 2; ++c) {
+          double y[RJ_T];
+          for (int i = 0; i < RJ_T; ++i) {
+            double s = sys[RJ_G + 2 * i + c];
+            for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+            y[i] = s / L[i][i];
+          }
+          for (int i = RJ_T - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int k = i + 1; k < RJ_T; ++k) s -= L[k][i] * coef[k][c];
+            coef[i][c] = s / L[i][i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (done == 2) break;
+    // 3. residuals, RMSE, largest residual
+    double ss = 0.0, best = -1.0;
+    int bi = INT_MAX;
+    for (int i = tid; i < n; i += RJ_NT) {
+      if (!keep[i]) continue;
+      const float2 p = src[i], q = dst[i];
+      double t[RJ_T];
+      cubic_terms(((double)p.x - cx) / sx, ((double)p.y - cy) / sy, t);
+      double mxv = 0.0, myv = 0.0;
+#pragma unroll
+      for (int a = 0; a < RJ_T; ++a) {
+        mxv += t[a] * coef[a][0];
+        myv += t[a] * coef[a][1];
+      }
+      const double ex = mxv - (double)q.x, ey = myv - (double)q.y;
+      const double r2 = ex * ex + ey * ey;
+      ss += r2;
+      const double rr = sqrt(r2);
+      if (rr > best || (rr == best && i < bi)) {
+        best = rr;
+        bi = i;
+      }
+    }
+    ss = wave_sum(ss);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      part[wv][0] = ss;
+      rd[wv] = best;
+      ri[wv] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < RJ_NW; ++w) {
+        s += part[w][0];
+        if (rd[w] > best || (rd[w] == best && ri[w] < bi)) {
+          best = rd[w];
+          bi = ri[w];
+        }
+      }
+      const double rmse = sqrt(s / active);
+      if (bi == INT_MAX || !(rmse == rmse)) {
+        done = 2;  // a non-finite residual: no point can be chosen
+      } else if (rmse < (double)thr || active <= RJ_T) {
+        done = 1;
+        out->rmse = rmse;
+      } else {
+        keep[bi] = 0;
+        --active;
+        ++removed;
+      }
+    }
+    __syncthreads();
+    if (done) break;
+  }
+  if (tid == 0) {
+    out->status = done == 1 ? 0 : 1;
+    out->removed = removed;
+    out->n_kept = active;
+    if (done != 1) out->rmse = NAN;
+    for (int a = 0; a < RJ_T; ++a) {
+      out->coef[a][0] = done == 1 ? coef[a][0] : NAN;
+      out->coef[a][1] = done == 1 ? coef[a][1] : NAN;
+    }
+    out->centre[0] = cx;
+    out->centre[1] = cy;
+    out->half_extent[0] = sx;
+    out->half_extent[1] = sy;
+  }
+}
+
+}  // namespace cfog
+
+extern "C" int cfog_reject_outliers(cfog_ctx* ctx, const float* d_src, const float* d_dst, int32_t n, float threshold,
+                                    unsigned char* d_keep, cfog_reject_result* d_result, void* stream) {
+  if (!ctx || !d_src || !d_dst || !d_keep || !d_result || n < 10 || n > (1 << 20) || !(threshold >= 0.f) ||
+      ((uintptr_t)d_src % 8) != 0 || ((uintptr_t)d_dst % 8) != 0 || ((uintptr_t)d_result % 8) != 0)
+    return CFOG_EINVAL;
+  hipLaunchKernelGGL(cfog::reject_kernel, dim3(1), dim3(cfog::RJ_NT), 0, (hipStream_t)stream,
+                     reinterpret_cast<const float2*>(d_src), reinterpret_cast<const float2*>(d_dst), n, threshold,
+                     d_keep, d_result);
+  return hipGetLastError() == hipSuccess ? CFOG_OK : CFOG_EHIP;
+}

@@ -96,6 +96,12 @@ def test_server_structs_match_header():
     assert ctypes.sizeof(cfog.cfog_server_stats) == 80
 
 
+def test_reject_result_layout():
+    from paper_1808_06194_amd import cfog
+    assert ctypes.sizeof(cfog.cfog_reject_result) == 216
+    assert cfog.cfog_reject_result.rmse.offset == 192 and cfog.cfog_reject_result.status.offset == 208
+
+
 def test_server_null_handles_are_rejected(lib):
     from paper_1808_06194_amd import cfog
     i32, i64 = ctypes.c_int32(), ctypes.c_int64()
