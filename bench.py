@@ -2,9 +2,9 @@
 """Benchmark of the CFOG + 3-D-FFT SSD matching hot path on one MI355X.
 
 One step = the whole hot path on one batch of synthetic input: CFOG extraction
-of every image (volume + FP64 summed-area table) and SSD matching of every
-control point (correlation, FP64 energies, argmin).  Inputs are resident in
-HBM before the timed region starts.
+of every image (volume + FP64 summed-area table; the images alternate between
+two streams) and SSD matching of every control point (correlation, FP64
+energies, argmin).  Inputs are resident in HBM before the timed region starts.
 
 Workloads (--workload):
   plain_2048 (default): one 2048^2 fp32 pair (800 blobs sigma 3-40, 300
@@ -205,17 +205,26 @@ def main():
         imgs.append((dA, vA, sA))
         imgs.append((dB, vB, sB))
         jobs.append(cfog.Job(vA, sA, vB, sB, torch.from_numpy(p["cps"]).to(dev), p["N"], p["r"]))
-    ws_ext = torch.empty(max(cfog.extract_workspace_size(*img[0].shape) for img in imgs),
-                         dtype=torch.uint8, device=dev)
+    # the images are extracted on two streams (every second image on the
+    # other one, each stream with its own workspace), joined before matching
+    ws_bytes = max(cfog.extract_workspace_size(*img[0].shape) for img in imgs)
+    ws_ext = [torch.empty(ws_bytes, dtype=torch.uint8, device=dev) for _ in range(2)]
     n_cps = sum(len(p["cps"]) for p in pairs)
     stream = torch.cuda.current_stream()
+    side = torch.cuda.Stream(device=dev)  # default priority
+    fork, join = torch.cuda.Event(), torch.cuda.Event()
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
     def step(evs=None):
         if evs:
             evs[0].record(stream)
-        for img, vol, sat in imgs:
-            cfog.cfog_extract(img, m=m, vol=vol, sat=sat, stream=stream, workspace=ws_ext)
+        fork.record(stream)
+        side.wait_event(fork)
+        for i, (img, vol, sat) in enumerate(imgs):
+            cfog.cfog_extract(img, m=m, vol=vol, sat=sat, stream=(stream if i % 2 == 0 else side),
+                              workspace=ws_ext[i % 2])
+        join.record(side)
+        stream.wait_event(join)
         if evs:
             evs[1].record(stream)
         cfog.match_batch(jobs, m=m, flags=flags, stream=stream)

@@ -9,7 +9,8 @@ What it computes (Ye et al., "Fast and Robust Matching for Multimodal Remote
 Sensing Image Registration"):
 
 * CFOG (Section III-F): oriented gradient channels from the horizontal and
-  vertical gradients of the image (Eq. 2, filters [-1, 0, 1]), convolved with a
+  vertical gradients of the image (Eq. 2, filters [-1, 0, 1]; scheme 1 of the
+  same section as an option), convolved with a
   3-D "Gaussian-like" kernel: a 2-D Gaussian of std sigma in X and Y and a
   [1, 2, 1] kernel along the orientation (Z) axis.  Defaults sigma = 0.8 and
   m = 9 (Section V-C, Table II).
@@ -100,6 +101,27 @@ def oriented_channels(gx: np.ndarray, gy: np.ndarray, m: int) -> np.ndarray:
     return np.abs(np.cos(th)[:, None, None] * gx[None] + np.sin(th)[:, None, None] * gy[None])
 
 
+def oriented_channels_scheme1(gx: np.ndarray, gy: np.ndarray, m: int) -> np.ndarray:
+    """Scheme 1 of Section III-F: the gradient orientation, taken modulo 180
+    degrees, falls between two of the m orientation bins (centres k pi / m);
+    the gradient magnitude is split between them with weights falling
+    linearly with the distance to each bin (reading of "inversely related to
+    the distance"), circularly over the m bins."""
+    mag = np.hypot(gx, gy)
+    phi = np.mod(np.arctan2(gy, gx), np.pi)
+    b = phi * (m / np.pi)
+    b = np.where(b >= m, b - m, b)
+    k0 = np.floor(b).astype(np.int64)
+    f = b - k0
+    k0 = np.mod(k0, m)
+    k1 = np.mod(k0 + 1, m)
+    G = np.zeros((m,) + gx.shape, np.float64)
+    rows, cols = np.indices(gx.shape)
+    np.add.at(G, (k0, rows, cols), mag * (1.0 - f))
+    np.add.at(G, (k1, rows, cols), mag * f)
+    return G
+
+
 def gaussian_weights(sigma: float, radius: int | None = None) -> np.ndarray:
     """Normalised 1-D Gaussian of std sigma on [-R, R], R = int(4 sigma + 0.5)."""
     R = int(4.0 * sigma + 0.5) if radius is None or radius < 0 else int(radius)
@@ -135,11 +157,13 @@ def smooth_z(G: np.ndarray) -> np.ndarray:
     return 0.25 * np.roll(G, 1, axis=0) + 0.5 * G + 0.25 * np.roll(G, -1, axis=0)
 
 
-def cfog(img: np.ndarray, m: int = 9, sigma: float = 0.8, radius: int | None = None) -> np.ndarray:
+def cfog(img: np.ndarray, m: int = 9, sigma: float = 0.8, radius: int | None = None,
+         scheme: int = 2) -> np.ndarray:
     """CFOG volume D, shape (m, H, W), fp64 (Section III-F, Fig. 9 chain:
-    gradients -> oriented channels -> 3-D Gaussian-like convolution)."""
+    gradients -> oriented channels (scheme 2: Eq. 2; scheme 1: binned
+    orientation) -> 3-D Gaussian-like convolution)."""
     gx, gy = gradients(img)
-    G = oriented_channels(gx, gy, m)
+    G = oriented_channels(gx, gy, m) if scheme == 2 else oriented_channels_scheme1(gx, gy, m)
     return smooth_z(smooth_xy(G, sigma, radius))
 
 

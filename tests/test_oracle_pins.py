@@ -558,3 +558,52 @@ def test_rejection_stops_at_ten_points_and_needs_ten():
     assert keep.sum() == 10 and removed == 2 and rmse < 1e-6  # ten points are interpolated
     with pytest.raises(ValueError):
         O.reject_outliers(P[:9], Q[:9])
+
+
+# ---------------------------------------------- CFOG scheme 1 (Section III-F)
+
+def test_scheme1_on_and_between_bins():
+    m = 9
+    th = np.arange(m) * np.pi / m
+    # a gradient exactly at bin 4's orientation goes entirely to bin 4
+    gx, gy = np.array([[2.0 * np.cos(th[4])]]), np.array([[2.0 * np.sin(th[4])]])
+    G = O.oriented_channels_scheme1(gx, gy, m)[:, 0, 0]
+    np.testing.assert_allclose(G, np.eye(m)[4] * 2.0, atol=1e-12)
+    # halfway between bins 8 and 0 (170 degrees): half to each, circularly
+    a = np.pi * (m - 0.5) / m
+    G = O.oriented_channels_scheme1(np.array([[np.cos(a)]]), np.array([[np.sin(a)]]), m)[:, 0, 0]
+    want = np.zeros(m)
+    want[8] = want[0] = 0.5
+    np.testing.assert_allclose(G, want, atol=1e-12)
+
+
+def test_scheme1_channels_sum_to_the_magnitude_and_ignore_sign():
+    rng = np.random.default_rng(12)
+    gx, gy = rng.normal(size=(2, 20, 20))
+    G = O.oriented_channels_scheme1(gx, gy, 7)
+    np.testing.assert_allclose(G.sum(axis=0), np.hypot(gx, gy), rtol=1e-12)
+    assert np.all(G >= 0) and np.all((G > 0).sum(axis=0) <= 2)
+    np.testing.assert_allclose(O.oriented_channels_scheme1(-gx, -gy, 7), G, rtol=1e-12, atol=1e-15)
+
+
+def test_scheme1_against_python_loops():
+    rng = np.random.default_rng(13)
+    gx, gy, m = rng.normal(size=(6, 5)), rng.normal(size=(6, 5)), 6
+    G = O.oriented_channels_scheme1(gx, gy, m)
+    for y in range(6):
+        for x in range(5):
+            phi = np.arctan2(gy[y, x], gx[y, x]) % np.pi
+            mag = (gx[y, x] ** 2 + gy[y, x] ** 2) ** 0.5
+            for k in range(m):
+                d = abs(phi - k * np.pi / m)
+                d = min(d, np.pi - d)  # circular distance over [0, pi)
+                assert G[k, y, x] == pytest.approx(mag * max(0.0, 1.0 - d * m / np.pi), abs=1e-12)
+
+
+def test_scheme1_mirror_invariant():
+    img = np.random.default_rng(14).random((24, 30))
+    m = 8
+    D = O.cfog(img, m=m, scheme=1)
+    Df = O.cfog(img[:, ::-1], m=m, scheme=1)
+    for k in range(m):
+        np.testing.assert_allclose(Df[(m - k) % m], D[k][:, ::-1], rtol=1e-12, atol=1e-13)
