@@ -102,6 +102,17 @@ int cfog_extract(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_
                  int32_t m, float sigma, int32_t gauss_radius, float* d_vol, double* d_sat,
                  void* d_ws, size_t ws_bytes, void* stream);
 
+/* cfog_extract with a choice of the oriented-gradient scheme of Section III-F:
+ * scheme 2 is Eq. 2 (what cfog_extract computes); scheme 1 bins the gradient
+ * orientation, taken modulo 180 degrees, between the two nearest of the m bin
+ * centres k*pi/m and splits the gradient magnitude between them with weights
+ * falling linearly with the distance to each bin (circularly over the bins).
+ * The smoothing, outputs and errors are those of cfog_extract; CFOG_EINVAL
+ * for a scheme other than 1 or 2. */
+int cfog_extract_scheme(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride,
+                        int32_t m, float sigma, int32_t gauss_radius, int32_t scheme, float* d_vol,
+                        double* d_sat, void* d_ws, size_t ws_bytes, void* stream);
+
 /* Device workspace (bytes) cfog_extract needs to build the SAT of an H x W
  * image: 8 * (H * ceil(W/64) + ceil(H/16) * W). */
 size_t cfog_extract_workspace_size(int32_t H, int32_t W);

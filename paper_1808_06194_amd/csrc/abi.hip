@@ -411,7 +411,14 @@ size_t cfog_extract_workspace_size(int32_t H, int32_t W) {
 int cfog_extract(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride, int32_t m,
                  float sigma, int32_t gauss_radius, float* d_vol, double* d_sat, void* d_ws, size_t ws_bytes,
                  void* stream) {
-  if (!ctx || !d_img || !d_vol) return CFOG_EINVAL;
+  return cfog_extract_scheme(ctx, d_img, H, W, row_stride, m, sigma, gauss_radius, 2, d_vol, d_sat, d_ws, ws_bytes,
+                             stream);
+}
+
+int cfog_extract_scheme(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride, int32_t m,
+                        float sigma, int32_t gauss_radius, int32_t scheme, float* d_vol, double* d_sat, void* d_ws,
+                        size_t ws_bytes, void* stream) {
+  if (!ctx || !d_img || !d_vol || (scheme != 1 && scheme != 2)) return CFOG_EINVAL;
   if (H < 1 || W < 1 || row_stride < W || m < 1 || m > cfog::kMaxOrient) return CFOG_EINVAL;
   if (!(sigma > 0.f) || !isfinite(sigma)) return CFOG_EINVAL;
   int R = gauss_radius < 0 ? (int)(4.0 * sigma + 0.5) : gauss_radius;
@@ -438,7 +445,8 @@ int cfog_extract(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_
     }
     d_ws = ctx->ext_ws;
   }
-  int rc = cfog::launch_extract(d_img, row_stride, H, W, m, sigma, R, d_vol, d_sat, d_ws, (hipStream_t)stream);
+  int rc = cfog::launch_extract(d_img, row_stride, H, W, m, sigma, R, d_vol, d_sat, d_ws, (hipStream_t)stream,
+                                scheme);
   if (rc == -1) return CFOG_EUNSUPPORTED;
   if (rc != 0) return record(ctx, hipGetLastError());
   return CFOG_OK;

@@ -51,6 +51,7 @@ struct ExtractArgs {
   double* rc;   // [H][ntx] right columns of the tile-local prefixes
   double* bt;   // [nty][W] bottom rows
   int ntx, nty;
+  int scheme;                     // 2: Eq. 2; 1: binned orientation (scheme 1)
   float cs[kMaxOrient];           // cos(theta_k)
   float sn[kMaxOrient];           // sin(theta_k)
   float w[kMaxGaussRadius + 1];   // w[|j|], j in [-R, R]
@@ -147,6 +148,19 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
       gxy[r * GWP + c] = make_float2(img[yl * IW + xp] - img[yl * IW + xm], img[yp * IW + xl] - img[ym * IW + xl]);
     }
   }
+  // scheme 1 keeps (|g|, orientation bin position in [0, m)) instead of (gx, gy)
+  if (a.scheme == 1) {
+    const float bscale = (float)m / 3.14159265358979f;
+    for (int i = tid; i < GH * GW; i += EX_NT) {
+      const int r = i / GW, c = i - r * GW;
+      const float2 g = gxy[r * GWP + c];
+      float phi = atan2f(g.y, g.x);
+      if (phi < 0.f) phi += 3.14159265358979f;
+      float b = phi * bscale;
+      if (b >= (float)m) b -= (float)m;
+      gxy[r * GWP + c] = make_float2(sqrtf(g.x * g.x + g.y * g.y), b);
+    }
+  }
   // the padding columns of gxy feed only channel values that no output reads
   __syncthreads();
 
@@ -178,12 +192,30 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
     const float ck = a.cs[k], sk = a.sn[k];
     float* hb = Hb + (k & 1) * GH * EX_TX;
     // oriented gradient of channel k at every pixel of the halo tile, two at a time
+    if (a.scheme == 1) {
+      // |g| times max(0, 1 - circular distance of the bin position to k)
+      const float kf = (float)k, mf = (float)m;
+      auto wgt = [&](float b) {
+        const float d = fabsf(b - kf);
+        return fmaxf(0.f, 1.f - fminf(d, mf - d));
+      };
 #pragma unroll
-    for (int it = 0; it < (T::NPAIR + EX_NT - 1) / EX_NT; ++it) {
-      const int i = tid + it * EX_NT;
-      if (T::NPAIR % EX_NT == 0 || i < T::NPAIR) {
-        const float4 g = lds4[(T::IMG / 4) + i];  // gxy[2i], gxy[2i+1]
-        reinterpret_cast<float2*>(G)[i] = make_float2(fabsf(fmaf(ck, g.x, sk * g.y)), fabsf(fmaf(ck, g.z, sk * g.w)));
+      for (int it = 0; it < (T::NPAIR + EX_NT - 1) / EX_NT; ++it) {
+        const int i = tid + it * EX_NT;
+        if (T::NPAIR % EX_NT == 0 || i < T::NPAIR) {
+          const float4 g = lds4[(T::IMG / 4) + i];  // (|g|, b) of two pixels
+          reinterpret_cast<float2*>(G)[i] = make_float2(g.x * wgt(g.y), g.z * wgt(g.w));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < (T::NPAIR + EX_NT - 1) / EX_NT; ++it) {
+        const int i = tid + it * EX_NT;
+        if (T::NPAIR % EX_NT == 0 || i < T::NPAIR) {
+          const float4 g = lds4[(T::IMG / 4) + i];  // gxy[2i], gxy[2i+1]
+          reinterpret_cast<float2*>(G)[i] =
+              make_float2(fabsf(fmaf(ck, g.x, sk * g.y)), fabsf(fmaf(ck, g.z, sk * g.w)));
+        }
       }
     }
     __syncthreads();
@@ -437,8 +469,9 @@ int init_extract_attributes() {
 }
 
 int launch_extract(const float* img, int64_t stride, int H, int W, int m, float sigma, int R, float* vol,
-                   double* sat, void* ws, hipStream_t st) {
+                   double* sat, void* ws, hipStream_t st, int scheme) {
   ExtractArgs a{};
+  a.scheme = scheme;
   a.img = img; a.stride = stride; a.H = H; a.W = W; a.m = m; a.vol = vol; a.sat = sat;
   a.ntx = (W + EX_TX - 1) / EX_TX;
   a.nty = (H + EX_TY - 1) / EX_TY;

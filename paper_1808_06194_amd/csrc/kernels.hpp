@@ -31,8 +31,9 @@ struct MatchJob {
 
 enum : int { kCpOk = 0, kCpOutOfBounds = 1, kCpNonFinite = 2 };
 
+// scheme 2: oriented channels of Eq. 2; scheme 1: binned orientation.
 int launch_extract(const float* img, int64_t stride, int H, int W, int m, float sigma, int R,
-                   float* vol, double* sat, void* ws, hipStream_t st);
+                   float* vol, double* sat, void* ws, hipStream_t st, int scheme = 2);
 size_t extract_lds_bytes(int m, int R);
 size_t extract_workspace_bytes(int H, int W);
 

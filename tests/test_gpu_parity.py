@@ -464,3 +464,40 @@ def test_batched_objective_and_subpixel_equal_plain(cf):
     assert np.array_equal(r1[1].view(np.int32), r2[1].view(np.int32))
     assert np.array_equal(r1[2].view(np.int32), r2[2].view(np.int32))
     assert int(r1[0]["status"][-1]) == cf.CP_OUT_OF_BOUNDS and np.all(np.isnan(r1[2][-1]))
+
+
+# ------------------------------------------------------------ CFOG scheme 1
+
+@pytest.mark.parametrize("H,W,m,seed", [(96, 130, 9, 91), (64, 64, 6, 92), (300, 257, 12, 93)])
+def test_extract_scheme1_matches_oracle(cf, H, W, m, seed):
+    _say(f"extract scheme 1 {H}x{W} m={m} seed={seed}")
+    A, _, _ = synth.make_pair(synth.PairSpec(H, W, max(4, H * W // 1500), (3.0, 15.0), max(2, H * W // 3000), 4),
+                              (seed, 0))
+    vol, sat = cf.cfog_extract(_dev(A), m=m, scheme=1)
+    torch.cuda.synchronize()
+    D = O.cfog(A.astype(np.float64), m=m, scheme=1)
+    parity.check_volume(vol.cpu().numpy(), D)
+    Q = np.sum(vol.cpu().numpy().astype(np.float64) ** 2, axis=0)
+    np.testing.assert_allclose(sat.cpu().numpy(), O.sat(Q), rtol=1e-12, atol=1e-9 * O.sat(Q)[-1, -1])
+
+
+def test_match_on_scheme1_volumes(cf):
+    """The matcher takes any volume: scheme-1 CFOG of a 256^2 pair, 16 CPs,
+    template 48, radius 10, against the oracle on its own scheme-1 volumes."""
+    A, B, cps, N, r = _opt_case(94)
+    _say("match on scheme-1 volumes, 256^2, 16 CPs, seed 94")
+    vA, sA = cf.cfog_extract(_dev(A), scheme=1)
+    vB, sB = cf.cfog_extract(_dev(B), scheme=1)
+    K = 2 * r + 1
+    surf = torch.empty((len(cps), K, K), device="cuda")
+    job = cf.Job(vA, sA, vB, sB, _dev(np.asarray(cps, np.int32)), N, r, surfaces=surf)
+    cf.match_batch([job])
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in cf.results(job.out).items()}
+    D1, D2 = O.cfog(A.astype(np.float64), scheme=1), O.cfog(B.astype(np.float64), scheme=1)
+    ora = O.match(D1, D2, cps, N, r, surfaces=True)
+    stats = {}
+    for k, cp in enumerate(cps):
+        E1, E2 = O.energies(D1, D2, cp, N, r)
+        parity.check_point(k, res, ora["surfaces"][k], E1, E2, r, surf_gpu=surf[k].cpu().numpy(), stats=stats)
+    _say("scheme-1 parity", stats)
