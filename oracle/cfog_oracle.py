@@ -63,6 +63,18 @@ Beyond the hot path (the first extension of the method):
     largest residual go to the smaller index; the loop also stops when ten
     points (the model's size) remain.
 
+  * pixel-wise HOG (FHOG, Section III-C): at every pixel, the histogram of a
+    block of 2 x 2 cells centred on it, 9 unsigned orientation bins, each
+    gradient spread over the neighbouring cells and bins by trilinear
+    interpolation, the 36 values normalised by their L2 norm.  Readings: the
+    orientation bins and their linear interpolation are those of scheme 1
+    (centres k pi / 9); cells of c = 4 pixels, the block spans offsets
+    [-c, c] around the pixel with cell centres at +-c/2; the spatial weight of
+    a gradient at offset d for the cell centred at o is max(0, 1 - |d - o| / c)
+    per axis (bilinear), zero outside the block; borders replicated; channel
+    index (2 a + b) 9 + k for cell column a, cell row b, bin k; normalisation
+    v / sqrt(|v|^2 + 1e-12).
+
 Parity pins live in tests/test_oracle_pins.py.  No CFOG value, surface or
 offset is printed in the paper, so agreement with the authors' own code is
 "parity unpinned"; every function here is pinned by closed forms, invariants,
@@ -469,3 +481,29 @@ def reject_outliers(src, dst, threshold: float = 3.5):
             return keep, coef, rmse, removed
         keep[idx[int(np.argmax(res))]] = False  # argmax: the first of equal maxima
         removed += 1
+
+
+# ------------------------------------------------- pixel-wise HOG (III-C)
+
+FHOG_EPS = 1e-12
+
+
+def fhog_cell_kernel(c: int, o: float) -> np.ndarray:
+    """Spatial weights of the cell centred at offset o for block offsets
+    d = -c .. c: max(0, 1 - |d - o| / c)."""
+    d = np.arange(-c, c + 1, dtype=np.float64)
+    return np.maximum(0.0, 1.0 - np.abs(d - o) / c)
+
+
+def fhog(img: np.ndarray, c: int = 4, bins: int = 9) -> np.ndarray:
+    """Pixel-wise HOG volume, shape (4 bins, H, W), fp64."""
+    gx, gy = gradients(img)
+    G = oriented_channels_scheme1(gx, gy, bins)
+    kern = [fhog_cell_kernel(c, -c / 2.0), fhog_cell_kernel(c, c / 2.0)]
+    out = np.empty((4 * bins,) + G.shape[1:], np.float64)
+    for a in range(2):          # cell column (x offset -c/2, +c/2)
+        Hx = np.stack([_conv1d_edge(G[k], kern[a], 1) for k in range(bins)])
+        for b in range(2):      # cell row (y offset -c/2, +c/2)
+            out[(2 * a + b) * bins:(2 * a + b + 1) * bins] = np.stack(
+                [_conv1d_edge(Hx[k], kern[b], 0) for k in range(bins)])
+    return out / np.sqrt(np.sum(out * out, axis=0) + FHOG_EPS)

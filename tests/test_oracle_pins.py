@@ -607,3 +607,64 @@ def test_scheme1_mirror_invariant():
     Df = O.cfog(img[:, ::-1], m=m, scheme=1)
     for k in range(m):
         np.testing.assert_allclose(Df[(m - k) % m], D[k][:, ::-1], rtol=1e-12, atol=1e-13)
+
+
+# ------------------------------------------------- pixel-wise HOG (III-C)
+
+def _python_loop_fhog(img, c=4, bins=9):
+    """The histogram of the definition, pixel by pixel: every gradient q of
+    the block around p adds |g| x (orientation weight) x (bilinear weight of
+    each cell); then the 36 values are L2-normalised."""
+    H, W = len(img), len(img[0])
+    cl = lambda v, n: min(max(v, 0), n - 1)  # noqa: E731
+    out = np.zeros((4 * bins, H, W))
+    for py in range(H):
+        for px in range(W):
+            v = np.zeros(4 * bins)
+            for dy in range(-c, c + 1):
+                for dx in range(-c, c + 1):
+                    y, x = cl(py + dy, H), cl(px + dx, W)
+                    gx = img[y][cl(x + 1, W)] - img[y][cl(x - 1, W)]
+                    gy = img[cl(y + 1, H)][x] - img[cl(y - 1, H)][x]
+                    mag = (gx * gx + gy * gy) ** 0.5
+                    phi = np.arctan2(gy, gx) % np.pi
+                    for a, ox in enumerate((-c / 2, c / 2)):
+                        wx = max(0.0, 1.0 - abs(dx - ox) / c)
+                        for b, oy in enumerate((-c / 2, c / 2)):
+                            wy = max(0.0, 1.0 - abs(dy - oy) / c)
+                            for k in range(bins):
+                                d = abs(phi - k * np.pi / bins)
+                                d = min(d, np.pi - d)
+                                wo = max(0.0, 1.0 - d * bins / np.pi)
+                                v[(2 * a + b) * bins + k] += mag * wo * wx * wy
+            out[:, py, px] = v / np.sqrt(np.sum(v * v) + O.FHOG_EPS)
+    return out
+
+
+def test_fhog_against_python_loops():
+    img = np.random.default_rng(15).random((7, 9))
+    np.testing.assert_allclose(O.fhog(img, c=2), _python_loop_fhog(img.tolist(), c=2), rtol=1e-10, atol=1e-12)
+
+
+def test_fhog_unit_norm_zero_on_flat_and_invariances():
+    img = np.random.default_rng(16).random((20, 24))
+    F = O.fhog(img)
+    np.testing.assert_allclose(np.sqrt(np.sum(F * F, axis=0)), 1.0, rtol=1e-9)
+    assert np.all(O.fhog(np.full((12, 12), 2.0)) == 0.0)
+    np.testing.assert_allclose(O.fhog(3.0 * img), F, rtol=1e-9, atol=1e-12)   # contrast
+    np.testing.assert_allclose(O.fhog(-img), F, rtol=1e-12, atol=1e-14)        # intensity inversion
+
+
+def test_fhog_vertical_edge_fills_bin_zero_only():
+    img = np.zeros((16, 16))
+    img[:, 8:] = 1.0                                  # horizontal gradient only: orientation 0
+    F = O.fhog(img)
+    mask = np.ones(36, bool)
+    mask[[0, 9, 18, 27]] = False                      # bin 0 of each cell
+    assert np.all(F[mask] == 0.0)
+    assert np.all(F[~mask][:, :, 4:12].sum(axis=0) > 0)
+
+
+def test_fhog_cell_kernels():
+    np.testing.assert_allclose(O.fhog_cell_kernel(4, -2.0), [0.5, 0.75, 1.0, 0.75, 0.5, 0.25, 0.0, 0.0, 0.0])
+    np.testing.assert_allclose(O.fhog_cell_kernel(4, 2.0), O.fhog_cell_kernel(4, -2.0)[::-1])
