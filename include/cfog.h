@@ -113,6 +113,25 @@ int cfog_extract_scheme(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W,
                         int32_t m, float sigma, int32_t gauss_radius, int32_t scheme, float* d_vol,
                         double* d_sat, void* d_ws, size_t ws_bytes, void* stream);
 
+/* Pixel-wise HOG (Section III-C, the FHOG descriptor built pixel by pixel):
+ * at every pixel the histogram of a block of 2 x 2 cells of `cell` pixels
+ * centred on it.  Gradients as in cfog_extract; the unsigned orientation
+ * (modulo 180 degrees) is split between the two nearest of 9 bins (centres
+ * k*pi/9) linearly in the distance, circularly; a gradient at block offset
+ * (dx, dy), |dx|, |dy| <= cell, adds to cell (a, b) with the weight
+ * wa(dx) wb(dy), w0(d) = max(0, 1 - |d + cell/2| / cell),
+ * w1(d) = max(0, 1 - |d - cell/2| / cell) (pixels beyond the image replicate
+ * the border); the 36 values of a pixel are divided by
+ * sqrt(sum of their squares + 1e-12).
+ *   d_vol   DEVICE out, planar [36][H][W] float: channel (2a + b) * 9 + k is
+ *           cell column a (0 left), cell row b (0 top), bin k.
+ *   d_sat, d_ws, ws_bytes, stream, H, W, row_stride: as for cfog_extract.
+ *   cell    1..8 (CFOG_EUNSUPPORTED above 8, CFOG_EINVAL below 1).
+ * The volume is matched by match_batch with m = 36. */
+int cfog_extract_fhog(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride,
+                      int32_t cell, float* d_vol, double* d_sat, void* d_ws, size_t ws_bytes,
+                      void* stream);
+
 /* Device workspace (bytes) cfog_extract needs to build the SAT of an H x W
  * image: 8 * (H * ceil(W/64) + ceil(H/16) * W). */
 size_t cfog_extract_workspace_size(int32_t H, int32_t W);
@@ -174,7 +193,8 @@ size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n
 
 /*
  * match_batch - SSD template matching of every control point of every job
- * (Eqs. 3-6, 8-9; Eq. 4 argmin).  Volumes have m channels (1..16).
+ * (Eqs. 3-6, 8-9; Eq. 4 argmin).  Volumes have m channels (1..64: a CFOG volume
+ * has 1..16, a pixel-wise HOG volume 36).
  *   jobs        host array of n_jobs jobs (n_jobs >= 0).
  *   flags       one CFOG_PATH_* value, optionally | CFOG_OBJ_CORR (Eq. 7
  *               objective) and | CFOG_AUTOTUNE (FFT paths:

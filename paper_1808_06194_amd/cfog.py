@@ -37,7 +37,7 @@ OBJ_CORR = 0x400
 # Exported symbols, as declared in include/cfog.h.
 EXPORTS = (
     "cfog_ctx_create", "cfog_ctx_destroy", "cfog_ctx_last_error", "cfog_status_str",
-    "cfog_extract", "cfog_extract_scheme", "cfog_extract_workspace_size", "match_batch_workspace_size", "match_batch",
+    "cfog_extract", "cfog_extract_scheme", "cfog_extract_fhog", "cfog_extract_workspace_size", "match_batch_workspace_size", "match_batch",
     "cfog_max_window", "cfog_fft_size", "cfog_set_plan", "cfog_plan_for", "cfog_harris_grid",
     "cfog_reject_outliers",
     "cfog_server_create", "cfog_server_destroy", "cfog_server_add_pair", "cfog_server_submit",
@@ -114,6 +114,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cfog_status_str.restype = ctypes.c_char_p
     lib.cfog_extract.argtypes = [vp, vp, i32, i32, i64, i32, ctypes.c_float, i32, vp, vp, vp, sz, vp]
     lib.cfog_extract_scheme.argtypes = [vp, vp, i32, i32, i64, i32, ctypes.c_float, i32, i32, vp, vp, vp, sz, vp]
+    lib.cfog_extract_fhog.argtypes = [vp, vp, i32, i32, i64, i32, vp, vp, vp, sz, vp]
     lib.cfog_extract_workspace_size.argtypes = [i32, i32]
     lib.cfog_extract_workspace_size.restype = sz
     lib.match_batch_workspace_size.argtypes = [vp, ctypes.POINTER(cfog_job), i32, i32, i32]
@@ -222,6 +223,28 @@ def cfog_extract(img: torch.Tensor, m: int = 9, sigma: float = 0.8, radius: int 
                                     int(scheme), vol.data_ptr(), _ptr(sat) if with_sat else None, _ptr(workspace),
                                     workspace.numel() if workspace is not None else 0, _stream_ptr(stream))
     _check(rc, "cfog_extract")
+    return vol, (sat if with_sat else None)
+
+
+FHOG_CHANNELS = 36
+
+
+def fhog_extract(img: torch.Tensor, cell: int = 4, with_sat: bool = True, vol: Optional[torch.Tensor] = None,
+                 sat: Optional[torch.Tensor] = None, stream=None, workspace: Optional[torch.Tensor] = None):
+    """Pixel-wise HOG volume (36, H, W) fp32 (2 x 2 cells of `cell` pixels,
+    9 unsigned bins) and its FP64 SAT; match it with match_batch(m=36)."""
+    if img.dim() != 2 or img.dtype != torch.float32 or not img.is_cuda or img.stride(1) != 1:
+        raise ValueError("img must be a 2-D row-contiguous cuda float32 tensor")
+    H, W = img.shape
+    if vol is None:
+        vol = torch.empty((FHOG_CHANNELS, H, W), dtype=torch.float32, device=img.device)
+    if with_sat and sat is None:
+        sat = torch.empty((H + 1, W + 1), dtype=torch.float64, device=img.device)
+    ctx = context(img.device.index)
+    rc = load().cfog_extract_fhog(ctx.handle, img.data_ptr(), H, W, img.stride(0), int(cell), vol.data_ptr(),
+                                  _ptr(sat) if with_sat else None, _ptr(workspace),
+                                  workspace.numel() if workspace is not None else 0, _stream_ptr(stream))
+    _check(rc, "cfog_extract_fhog")
     return vol, (sat if with_sat else None)
 
 

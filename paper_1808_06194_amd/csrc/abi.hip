@@ -61,7 +61,7 @@ struct cfog_ctx {
 namespace {
 
 long nr_key(int N, int r) { return (long)N * 4096 + r; }
-long nrm_key(int N, int r, int m) { return ((long)N * 4096 + r) * 32 + m; }
+long nrm_key(int N, int r, int m) { return ((long)N * 4096 + r) * 128 + m; }
 
 int record(cfog_ctx* ctx, hipError_t e) {
   if (e != hipSuccess) {
@@ -77,7 +77,7 @@ int validate_job(const cfog_job& j, int m) {
   if (!j.volA || !j.satA || !j.volB || !j.satB) return CFOG_EINVAL;
   if (j.n_cps < 0 || (j.n_cps > 0 && (!j.cps || !j.out))) return CFOG_EINVAL;
   if (j.hA < 1 || j.wA < 1 || j.hB < 1 || j.wB < 1) return CFOG_EINVAL;
-  if (j.N < 1 || j.r < 0 || m < 1 || m > cfog::kMaxOrient) return CFOG_EINVAL;
+  if (j.N < 1 || j.r < 0 || m < 1 || m > cfog::kMaxChannels) return CFOG_EINVAL;
   if (!aligned(j.cps, 16) || !aligned(j.out, 8) || !aligned(j.satA, 8) || !aligned(j.satB, 8) ||
       !aligned(j.volA, 4) || !aligned(j.volB, 4) || !aligned(j.surfaces, 4) || !aligned(j.subpix, 8))
     return CFOG_EINVAL;
@@ -231,7 +231,7 @@ void load_plan_cache(cfog_ctx* ctx) {
   int N, r, m, P;
   while (fscanf(f, "%d %d %d %d", &N, &r, &m, &P) == 4) {
     const cfog::FftPlan* p = plan_by_P(P);
-    if (p && N >= 1 && r >= 0 && cfog::plan_fits(p, N, r)) ctx->tuned[nrm_key(N, r, m)] = P;
+    if (p && N >= 1 && r >= 0 && m >= 1 && m <= cfog::kMaxChannels && cfog::plan_fits(p, N, r)) ctx->tuned[nrm_key(N, r, m)] = P;
   }
   fclose(f);
 }
@@ -243,7 +243,7 @@ void save_plan_cache(cfog_ctx* ctx) {
   if (!f) return;
   for (auto& kv : ctx->tuned) {
     const long nrm = kv.first;
-    const int m = (int)(nrm % 32), nr = (int)(nrm / 32);
+    const int m = (int)(nrm % 128), nr = (int)(nrm / 128);
     fprintf(f, "%d %d %d %d\n", nr / 4096, nr % 4096, m, kv.second);
   }
   fclose(f);
@@ -415,6 +415,26 @@ int cfog_extract(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_
                              stream);
 }
 
+// The context's extraction workspace, grown to `need` bytes.
+static int context_extract_ws(cfog_ctx* ctx, size_t need, void** ws) {
+  if (ctx->ext_ws_bytes < need) {
+    if (ctx->ext_ws) {
+      // the old workspace may still be in use by queued work on any stream
+      if (hipDeviceSynchronize() != hipSuccess) return record(ctx, hipGetLastError());
+      (void)hipFree(ctx->ext_ws);
+      ctx->ext_ws = nullptr;
+      ctx->ext_ws_bytes = 0;
+    }
+    if (hipMalloc(&ctx->ext_ws, need) != hipSuccess) {
+      ctx->ext_ws = nullptr;
+      return CFOG_ENOMEM;
+    }
+    ctx->ext_ws_bytes = need;
+  }
+  *ws = ctx->ext_ws;
+  return CFOG_OK;
+}
+
 int cfog_extract_scheme(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride, int32_t m,
                         float sigma, int32_t gauss_radius, int32_t scheme, float* d_vol, double* d_sat, void* d_ws,
                         size_t ws_bytes, void* stream) {
@@ -429,24 +449,28 @@ int cfog_extract_scheme(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W,
   if (need && d_ws && ws_bytes < need) return CFOG_ENOMEM;
   if (!aligned(d_ws, 8)) return CFOG_EINVAL;
   if (need && !d_ws) {
-    if (ctx->ext_ws_bytes < need) {
-      if (ctx->ext_ws) {
-        // the old workspace may still be in use by queued work on any stream
-        if (hipDeviceSynchronize() != hipSuccess) return record(ctx, hipGetLastError());
-        (void)hipFree(ctx->ext_ws);
-        ctx->ext_ws = nullptr;
-        ctx->ext_ws_bytes = 0;
-      }
-      if (hipMalloc(&ctx->ext_ws, need) != hipSuccess) {
-        ctx->ext_ws = nullptr;
-        return CFOG_ENOMEM;
-      }
-      ctx->ext_ws_bytes = need;
-    }
-    d_ws = ctx->ext_ws;
+    const int rc = context_extract_ws(ctx, need, &d_ws);
+    if (rc != CFOG_OK) return rc;
   }
   int rc = cfog::launch_extract(d_img, row_stride, H, W, m, sigma, R, d_vol, d_sat, d_ws, (hipStream_t)stream,
                                 scheme);
+  if (rc == -1) return CFOG_EUNSUPPORTED;
+  if (rc != 0) return record(ctx, hipGetLastError());
+  return CFOG_OK;
+}
+
+int cfog_extract_fhog(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride, int32_t cell,
+                      float* d_vol, double* d_sat, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !d_img || !d_vol || H < 1 || W < 1 || row_stride < W || cell < 1) return CFOG_EINVAL;
+  if (cell > 8) return CFOG_EUNSUPPORTED;
+  if (!aligned(d_sat, 8) || !aligned(d_ws, 8)) return CFOG_EINVAL;
+  const size_t need = d_sat ? cfog::extract_workspace_bytes(H, W) : 0;
+  if (need && d_ws && ws_bytes < need) return CFOG_ENOMEM;
+  if (need && !d_ws) {
+    const int rc = context_extract_ws(ctx, need, &d_ws);
+    if (rc != CFOG_OK) return rc;
+  }
+  const int rc = cfog::launch_fhog(d_img, row_stride, H, W, cell, d_vol, d_sat, d_ws, (hipStream_t)stream);
   if (rc == -1) return CFOG_EUNSUPPORTED;
   if (rc != 0) return record(ctx, hipGetLastError());
   return CFOG_OK;

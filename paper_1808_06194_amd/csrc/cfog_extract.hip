@@ -69,6 +69,33 @@ __device__ __forceinline__ double wave_incl_scan(double v) {
   return v;
 }
 
+// D. Tile-local 2-D inclusive prefix of the per-pixel energies q (rows
+// [orow, orow + EX_RUN) of column oc of the tile at row y0), written into the
+// SAT buffer, plus the tile's right column (rc) and bottom row (bt) for the
+// carry kernels.  qx: 4 x 64 doubles of LDS.
+__device__ __forceinline__ void tile_sat_prefix(double (&q)[EX_RUN], double* qx, double* sat, double* rc, double* bt,
+                                                int H, int W, int ntx, int y0, int orow, int oc, int gxx) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int o = 0; o < EX_RUN; ++o) q[o] = wave_incl_scan(q[o]);  // along x (lanes = columns)
+#pragma unroll
+  for (int o = 1; o < EX_RUN; ++o) q[o] += q[o - 1];              // along y within the thread
+  const int wv = tid >> 6;
+  qx[wv * 64 + oc] = q[EX_RUN - 1];
+  __syncthreads();
+  double up = 0.0;
+  for (int i = 0; i < wv; ++i) up += qx[i * 64 + oc];
+  const int W1 = W + 1;
+#pragma unroll
+  for (int o = 0; o < EX_RUN; ++o) {
+    q[o] += up;
+    const int gyy = y0 + orow + o;
+    if (gyy < H && gxx < W) sat[(size_t)(gyy + 1) * W1 + gxx + 1] = q[o];
+    if (oc == 63 && gyy < H) rc[(size_t)gyy * ntx + blockIdx.x] = q[o];
+  }
+  if (wv == EX_NT / 64 - 1 && gxx < W) bt[(size_t)blockIdx.y * W + gxx] = q[EX_RUN - 1];
+}
+
 // LDS geometry of the extraction tile for Gaussian radius R.
 template <int R>
 struct ExTile {
@@ -295,26 +322,165 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
     }
   }
   if (!a.sat) return;
+  tile_sat_prefix(q, qx, a.sat, a.rc, a.bt, H, W, a.ntx, y0, orow, oc, gxx);
+}
 
-  // D. tile-local 2-D prefix of Q
-#pragma unroll
-  for (int o = 0; o < EX_RUN; ++o) q[o] = wave_incl_scan(q[o]);  // along x (lanes = columns)
-#pragma unroll
-  for (int o = 1; o < EX_RUN; ++o) q[o] += q[o - 1];              // along y within the thread
-  const int wv = tid >> 6;
-  qx[wv * 64 + oc] = q[EX_RUN - 1];
+// ------------------------------------------------ pixel-wise HOG (FHOG)
+// Section III-C: at every pixel, the histogram of a block of 2 x 2 cells of
+// C pixels centred on it over 9 unsigned orientation bins (centres k pi / 9,
+// linear split between the two nearest bins), each gradient spread over the
+// cells with bilinear weights max(0, 1 - |d - o| / C) for cell centres
+// o = -C/2, +C/2 at block offsets d in [-C, C] (clamp-to-edge borders), the
+// 36 values normalised by sqrt(|v|^2 + 1e-12).  Channel (2 a + b) 9 + k is
+// cell column a, cell row b, bin k.  Same tiles as the CFOG kernel: per bin,
+// the bin's channel on the halo tile, both horizontal cell passes, both
+// vertical cell passes into registers (9 x 4 values for each of the 4 pixels
+// of a thread) until the norm is known; then the normalised values go out
+// and their energies feed the tile-local SAT prefix.
+constexpr int FH_BINS = 9;
+constexpr int FH_MAX_CELL = 8;
+
+struct FhogArgs {
+  const float* img;
+  int64_t stride;
+  int H, W;
+  float* vol;
+  double* sat;  // nullable
+  double* rc;
+  double* bt;
+  int ntx, nty;
+};
+
+template <int C>
+struct FhTile {
+  static constexpr int IW = EX_TX + 2 * C + 2, IH = EX_TY + 2 * C + 2;  // image tile (+1 for the gradient)
+  static constexpr int GW = EX_TX + 2 * C, GH = EX_TY + 2 * C;          // gradient / channel tile
+  static constexpr size_t IMG = ((size_t)IH * IW + 1) / 2 * 2;          // floats
+  static constexpr size_t MB = (size_t)GH * GW;                         // float2 (|g|, bin position)
+  static constexpr size_t G = (size_t)GH * GW;                          // floats
+  static constexpr size_t HX = 2 * (size_t)GH * EX_TX;                  // floats: both horizontal passes
+  static constexpr size_t BYTES = 4 * IMG + 8 * MB + 4 * G + 4 * HX + 8 * 4 * 64;
+};
+
+// Bilinear weight of block offset d for cell a (centre offset (a - 1/2) C).
+template <int C>
+__device__ __forceinline__ float fh_w(int d, int a) {
+  const float o = (a == 0 ? -0.5f : 0.5f) * (float)C;
+  return fmaxf(0.f, 1.f - fabsf((float)d - o) / (float)C);
+}
+
+template <int C>
+__global__ __launch_bounds__(EX_NT) void fhog_kernel(FhogArgs a) {
+  using T = FhTile<C>;
+  constexpr int IW = T::IW, IH = T::IH, GW = T::GW, GH = T::GH;
+  extern __shared__ float4 lds4[];
+  float* img = reinterpret_cast<float*>(lds4);
+  float2* mb = reinterpret_cast<float2*>(img + T::IMG);
+  float* G = reinterpret_cast<float*>(mb + T::MB);
+  float* hx = G + T::G;
+  double* qx = reinterpret_cast<double*>(hx + T::HX);
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * EX_TX, y0 = blockIdx.y * EX_TY;
+  const int H = a.H, W = a.W;
+
+  // A. image tile, rows y0-C-1 .. y0+TY+C, clamped
+  for (int i = tid; i < IH * IW; i += EX_NT) {
+    const int r = i / IW, c = i - r * IW;
+    const int gy = clampi(y0 - C - 1 + r, 0, H - 1), gx = clampi(x0 - C - 1 + c, 0, W - 1);
+    img[i] = a.img[(int64_t)gy * a.stride + gx];
+  }
   __syncthreads();
-  double up = 0.0;
-  for (int i = 0; i < wv; ++i) up += qx[i * 64 + oc];
-  const int W1 = W + 1;
+  // B. (|g|, orientation bin position) at the clamped positions of the halo tile
+  {
+    const int oy = y0 - C - 1, ox = x0 - C - 1;
+    const float bscale = (float)FH_BINS / 3.14159265358979f;
+    for (int i = tid; i < GH * GW; i += EX_NT) {
+      const int r = i / GW, c = i - r * GW;
+      const int Yc = clampi(y0 - C + r, 0, H - 1), Xc = clampi(x0 - C + c, 0, W - 1);
+      const int yl = Yc - oy, xl = Xc - ox;
+      const int xp = clampi(Xc + 1, 0, W - 1) - ox, xm = clampi(Xc - 1, 0, W - 1) - ox;
+      const int yp = clampi(Yc + 1, 0, H - 1) - oy, ym = clampi(Yc - 1, 0, H - 1) - oy;
+      const float gx = img[yl * IW + xp] - img[yl * IW + xm], gy = img[yp * IW + xl] - img[ym * IW + xl];
+      float phi = atan2f(gy, gx);
+      if (phi < 0.f) phi += 3.14159265358979f;
+      float b = phi * bscale;
+      if (b >= (float)FH_BINS) b -= (float)FH_BINS;
+      mb[i] = make_float2(sqrtf(gx * gx + gy * gy), b);
+    }
+  }
+  __syncthreads();
+
+  // C. per bin: channel, horizontal cell passes, vertical cell passes
+  const int oc = tid & 63, orow = (tid >> 6) * EX_RUN;
+  const int gxx = x0 + oc;
+  float v[FH_BINS][4][EX_RUN];
+  float n2[EX_RUN];
+#pragma unroll
+  for (int o = 0; o < EX_RUN; ++o) n2[o] = 0.f;
+#pragma unroll
+  for (int k = 0; k < FH_BINS; ++k) {
+    for (int i = tid; i < GH * GW; i += EX_NT) {
+      const float2 g = mb[i];
+      const float d = fabsf(g.y - (float)k);
+      G[i] = g.x * fmaxf(0.f, 1.f - fminf(d, (float)FH_BINS - d));
+    }
+    __syncthreads();
+    for (int i = tid; i < GH * EX_TX; i += EX_NT) {
+      const int r = i / EX_TX, c = i - r * EX_TX;
+      const float* row = G + r * GW + c + C;
+      float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+      for (int d = -C; d <= C; ++d) {
+        s0 = fmaf(fh_w<C>(d, 0), row[d], s0);
+        s1 = fmaf(fh_w<C>(d, 1), row[d], s1);
+      }
+      hx[i] = s0;
+      hx[GH * EX_TX + i] = s1;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ca = 0; ca < 2; ++ca) {
+      const float* col = hx + ca * GH * EX_TX + (orow + C) * EX_TX + oc;  // col[t * TX] = output row orow + t
+#pragma unroll
+      for (int o = 0; o < EX_RUN; ++o) {
+        float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+        for (int d = -C; d <= C; ++d) {
+          const float x = col[(o + d) * EX_TX];
+          s0 = fmaf(fh_w<C>(d, 0), x, s0);
+          s1 = fmaf(fh_w<C>(d, 1), x, s1);
+        }
+        v[k][2 * ca][o] = s0;
+        v[k][2 * ca + 1][o] = s1;
+        n2[o] = fmaf(s0, s0, fmaf(s1, s1, n2[o]));
+      }
+    }
+    // the next bin's channel pass writes G, which no thread still reads; its
+    // barrier precedes the next writes of hx
+  }
+
+  // D. normalise, write the 36 channels, energies -> tile-local SAT prefix
+  const size_t plane = (size_t)H * W;
+  float* const vout = a.vol + (size_t)min(y0 + orow, H - 1) * W + min(gxx, W - 1);
+  double q[EX_RUN];
 #pragma unroll
   for (int o = 0; o < EX_RUN; ++o) {
-    q[o] += up;
-    const int gyy = y0 + orow + o;
-    if (gyy < H && gxx < W) a.sat[(size_t)(gyy + 1) * W1 + gxx + 1] = q[o];
-    if (oc == 63 && gyy < H) a.rc[(size_t)gyy * a.ntx + blockIdx.x] = q[o];
+    q[o] = 0.0;
+    const bool ok = y0 + orow + o < H && gxx < W;
+    const float inv = 1.0f / sqrtf(n2[o] + 1e-12f);
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4)
+#pragma unroll
+      for (int k = 0; k < FH_BINS; ++k) {
+        const float val = v[k][c4][o] * inv;
+        if (ok) {
+          vout[(size_t)(c4 * FH_BINS + k) * plane + (size_t)o * W] = val;
+          q[o] = fma((double)val, (double)val, q[o]);
+        }
+      }
   }
-  if (wv == EX_NT / 64 - 1 && gxx < W) a.bt[(size_t)blockIdx.y * W + gxx] = q[EX_RUN - 1];
+  if (!a.sat) return;
+  tile_sat_prefix(q, qx, a.sat, a.rc, a.bt, H, W, a.ntx, y0, orow, oc, gxx);
 }
 
 // Kernel 2: exclusive prefixes of the right columns along each image row (one
@@ -461,7 +627,18 @@ static int set_attr() {
              : -2;
 }
 
+template <int C>
+static int set_fh_attr() {
+  return hipFuncSetAttribute((const void*)fhog_kernel<C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)FhTile<C>::BYTES) == hipSuccess
+             ? 0
+             : -2;
+}
+
 int init_extract_attributes() {
+  if (set_fh_attr<1>() || set_fh_attr<2>() || set_fh_attr<3>() || set_fh_attr<4>() || set_fh_attr<5>() ||
+      set_fh_attr<6>() || set_fh_attr<7>() || set_fh_attr<8>())
+    return -2;
   if (set_attr<0>() || set_attr<1>() || set_attr<2>() || set_attr<3>() || set_attr<4>() || set_attr<5>() ||
       set_attr<6>() || set_attr<7>() || set_attr<8>())
     return -2;
@@ -500,6 +677,43 @@ int launch_extract(const float* img, int64_t stride, int H, int W, int m, float 
     default: return -1;
   }
   if (rc != 0 || !sat) return rc;
+  const int row_blocks = (H + SAT_NT / 64 - 1) / (SAT_NT / 64);
+  hipLaunchKernelGGL(sat_carry_kernel, dim3(row_blocks + (W + 63) / 64), dim3(SAT_NT), 0, st, a.rc, a.bt, H, W,
+                     a.ntx, a.nty, row_blocks);
+  hipLaunchKernelGGL(sat_fix_kernel, dim3(a.ntx, a.nty), dim3(EX_NT), 0, st, sat, a.rc, a.bt, H, W, a.ntx);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace cfog
+
+namespace cfog {
+
+template <int C>
+static void launch_fh(const FhogArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(fhog_kernel<C>, dim3(a.ntx, a.nty), dim3(EX_NT), FhTile<C>::BYTES, st, a);
+}
+
+int launch_fhog(const float* img, int64_t stride, int H, int W, int cell, float* vol, double* sat, void* ws,
+                hipStream_t st) {
+  if (cell < 1 || cell > FH_MAX_CELL) return -1;
+  FhogArgs a{};
+  a.img = img; a.stride = stride; a.H = H; a.W = W; a.vol = vol; a.sat = sat;
+  a.ntx = (W + EX_TX - 1) / EX_TX;
+  a.nty = (H + EX_TY - 1) / EX_TY;
+  a.rc = (double*)ws;
+  a.bt = a.rc + (size_t)H * a.ntx;
+  switch (cell) {
+    case 1: launch_fh<1>(a, st); break;
+    case 2: launch_fh<2>(a, st); break;
+    case 3: launch_fh<3>(a, st); break;
+    case 4: launch_fh<4>(a, st); break;
+    case 5: launch_fh<5>(a, st); break;
+    case 6: launch_fh<6>(a, st); break;
+    case 7: launch_fh<7>(a, st); break;
+    default: launch_fh<8>(a, st); break;
+  }
+  if (hipGetLastError() != hipSuccess) return -2;
+  if (!sat) return 0;
   const int row_blocks = (H + SAT_NT / 64 - 1) / (SAT_NT / 64);
   hipLaunchKernelGGL(sat_carry_kernel, dim3(row_blocks + (W + 63) / 64), dim3(SAT_NT), 0, st, a.rc, a.bt, H, W,
                      a.ntx, a.nty, row_blocks);

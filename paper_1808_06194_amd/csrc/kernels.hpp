@@ -6,7 +6,8 @@
 
 namespace cfog {
 
-constexpr int kMaxOrient = 16;        // m <= 16 orientation channels
+constexpr int kMaxOrient = 16;        // m <= 16 orientation channels (CFOG extraction)
+constexpr int kMaxChannels = 64;      // channels of a volume the matcher takes (FHOG: 36)
 constexpr int kMaxGaussRadius = 8;    // Gaussian radius R <= 8 taps each side
 constexpr size_t kMaxLds = 160 * 1024;
 
@@ -34,6 +35,10 @@ enum : int { kCpOk = 0, kCpOutOfBounds = 1, kCpNonFinite = 2 };
 // scheme 2: oriented channels of Eq. 2; scheme 1: binned orientation.
 int launch_extract(const float* img, int64_t stride, int H, int W, int m, float sigma, int R,
                    float* vol, double* sat, void* ws, hipStream_t st, int scheme = 2);
+// Pixel-wise HOG (36 channels) with cells of `cell` pixels (1..8); the SAT as
+// for the CFOG volume.  0 ok, -1 unsupported cell, -2 HIP error.
+int launch_fhog(const float* img, int64_t stride, int H, int W, int cell, float* vol, double* sat, void* ws,
+                hipStream_t st);
 size_t extract_lds_bytes(int m, int R);
 size_t extract_workspace_bytes(int H, int W);
 
