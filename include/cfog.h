@@ -59,6 +59,9 @@ extern "C" {
 #define CFOG_OBJ_CORR 0x400  /* any path: the objective of Eq. 7 (maximise the correlation
                                 C(d) = sum D1 * D2 over the window, no energy terms); every
                                 similarity value (ssd_best, ssd_second, surfaces) is then -C(d) */
+#define CFOG_NO_SPLIT 0x800  /* FFT paths: match every point whole (no channel split, see
+                                match_batch), so that its result does not depend on the
+                                other points of the call */
 
 typedef struct cfog_ctx cfog_ctx;
 
@@ -186,8 +189,9 @@ typedef struct {
   float* subpix;
 } cfog_job;
 
-/* Device workspace (bytes) match_batch needs for these jobs and flags; 0 for
- * the plain path.  Returns (size_t)-1 for invalid jobs. */
+/* Device workspace (bytes) recommended for match_batch with these jobs and
+ * flags (it includes the channel-split partials described at match_batch);
+ * may be 0.  Returns (size_t)-1 for invalid jobs. */
 size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m,
                                   int32_t flags);
 
@@ -197,7 +201,7 @@ size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n
  * has 1..16, a pixel-wise HOG volume 36).
  *   jobs        host array of n_jobs jobs (n_jobs >= 0).
  *   flags       one CFOG_PATH_* value, optionally | CFOG_OBJ_CORR (Eq. 7
- *               objective) and | CFOG_AUTOTUNE (FFT paths:
+ *               objective), | CFOG_NO_SPLIT and | CFOG_AUTOTUNE (FFT paths:
  *               the first call for a given (N, r, m) times up to three FFT sizes
  *               on the job's own points and keeps the fastest; with the
  *               environment variable CFOG_PLAN_CACHE naming a file, choices
@@ -206,9 +210,19 @@ size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n
  *               hipGraph keyed by the exact jobs array, workspace pointer and size;
  *               identical later calls replay it).  Query the workspace size again
  *               after an autotuning call: a larger FFT size may need more.
- *   d_ws        device workspace of ws_bytes >= match_batch_workspace_size(); may be
- *               NULL when that size is 0.  It must stay untouched until the work
- *               completes on `stream`.
+ *   d_ws        device workspace of ws_bytes bytes, normally
+ *               match_batch_workspace_size(); may be NULL when that size is 0.
+ *               It must stay untouched until the work completes on `stream`.
+ *               FFT paths: when a launch's control points would leave
+ *               workgroup slots idle in its last round, the points of that
+ *               round are split by channel groups over several workgroups and
+ *               their partial correlations summed (in a fixed order) by a
+ *               second kernel; this needs the extra workspace, and a smaller
+ *               workspace (down to the minimum without splits) runs unsplit.
+ *               Results are deterministic for a given call and workspace
+ *               size; a split point differs from a whole one only by FP32
+ *               rounding.  CFOG_NO_SPLIT turns splitting off (the plain and
+ *               batched paths then return identical bits).
  *   Returns CFOG_EINVAL for invalid jobs, CFOG_EUNSUPPORTED when 2r+1 or
  *   N + 2r exceeds what the chosen path supports, CFOG_ENOMEM when the
  *   workspace is too small.  Per-point failures are reported in out[].status.

@@ -33,6 +33,7 @@ PATH_MFMA_BF16 = 0x4
 AUTOTUNE = 0x100
 USE_GRAPH = 0x200
 OBJ_CORR = 0x400
+NO_SPLIT = 0x800
 
 # Exported symbols, as declared in include/cfog.h.
 EXPORTS = (

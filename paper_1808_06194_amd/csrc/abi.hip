@@ -119,10 +119,71 @@ const cfog::FftPlan* select_plan(cfog_ctx* ctx, int N, int r, int m) {
 
 // ------------------------------------------------------------- batch plans
 
+// Channel split of the last round of a launch of n tasks on S workgroup
+// slots (see SplitArgs): the group count G minimising the modelled time,
+// G = 1 when splitting does not pay.  Costs are counted in 1-D FFTs of the
+// plan's size: per channel the row FFTs of template and window (two rows per
+// FFT) and the column FFTs of both half-spectra; per task the inverse and
+// the epilogue; a split pays its extra inverses and the reduce launch.
+// (Nmax, Wsmax, Kmax) bound the tasks' template, window and surface sides.
+cfog::SplitArgs plan_split(const cfog::FftPlan* p, int n, int S, int m, int Nmax, int Wsmax, int Kmax,
+                           size_t* bytes) {
+  cfog::SplitArgs sp{n, 1, 0, nullptr};
+  *bytes = 0;
+  if (m < 2 || n <= 0 || S <= 0) return sp;
+  const int q = n / S, rem = n % S;
+  if (rem == 0) return sp;
+  const int PH = p->P / 2 + 1;
+  const double cf = (Nmax + 1) / 2 + (Wsmax + 1) / 2 + 2.0 * PH;
+  const double ci = PH + (Kmax + 1) / 2;
+  auto cost = [&](int G) { return ((m + G - 1) / G) * cf + ci; };
+  double best = (q + 1) * cost(1);
+  int bestG = 1;
+  for (int G = 2; G <= std::min(m, 16) && (long)rem * G <= 2L * S; ++G) {
+    const double t = q * cost(1) + ((rem * G + S - 1) / S) * cost(G) + 0.05 * cost(1);
+    if (t < best) {
+      best = t;
+      bestG = G;
+    }
+  }
+  if (bestG == 1) return sp;
+  sp.n_whole = n - rem;
+  sp.G = bestG;
+  sp.slot = (int)align_up((size_t)Kmax * Kmax, 64);
+  *bytes = align_up(sizeof(float) * (size_t)rem * bestG * sp.slot, 256);
+  return sp;
+}
+
+// Workspace layout of a plain-path launch of job j: the template-spectrum
+// region of a TG plan, then the split partials (when split_ok).
+struct PlainLayout {
+  const cfog::FftPlan* p = nullptr;
+  cfog::SplitArgs sp{0, 1, 0, nullptr};
+  int blocks = 0;
+  size_t split_off = 0, total = 0;
+};
+
+PlainLayout plain_layout(cfog_ctx* ctx, const cfog_job& j, int m, bool split_ok) {
+  PlainLayout L;
+  L.p = select_plan(ctx, j.N, j.r, m);
+  if (!L.p) return L;
+  const int S = cfog::plan_slots(L.p, ctx->num_cus);
+  size_t sb = 0;
+  L.sp = split_ok ? plan_split(L.p, j.n_cps, S, m, j.N, j.N + 2 * j.r, 2 * j.r + 1, &sb)
+                  : cfog::SplitArgs{j.n_cps, 1, 0, nullptr};
+  const int items = cfog::split_items(j.n_cps, L.sp);
+  L.blocks = L.p->tg_bytes ? std::min(items, S) : items;
+  L.split_off = align_up((size_t)L.blocks * L.p->tg_bytes, 256);
+  L.total = L.split_off + sb;
+  return L;
+}
+
 struct Bucket {
   const cfog::FftPlan* plan;
   int begin, count, blocks;
   size_t tg_off;  // this bucket's template-spectrum region in the workspace
+  cfog::SplitArgs sp;
+  size_t split_off;  // its split partials (sp.G > 1)
 };
 
 struct BatchPlan {
@@ -132,7 +193,10 @@ struct BatchPlan {
   size_t jobs_off = 0, tasks_off = 0, table_bytes = 0, total = 0;
 };
 
-int build_batch(cfog_ctx* ctx, const cfog_job* jobs, int n_jobs, int m, int obj, BatchPlan& B) {
+// split_budget: workspace bytes the split partials may take (buckets are
+// split in order while they fit).
+int build_batch(cfog_ctx* ctx, const cfog_job* jobs, int n_jobs, int m, int obj, BatchPlan& B,
+                size_t split_budget) {
   std::vector<const cfog::FftPlan*> plans(n_jobs);
   for (int i = 0; i < n_jobs; ++i) {
     int rc = validate_job(jobs[i], m);
@@ -145,22 +209,42 @@ int build_batch(cfog_ctx* ctx, const cfog_job* jobs, int n_jobs, int m, int obj,
   int nplans = 0;
   const cfog::FftPlan* all = cfog::fft_plans(&nplans);
   size_t tg = 0;
+  std::vector<size_t> split_bytes;
   for (int p = 0; p < nplans; ++p) {
-    Bucket b{&all[p], (int)B.tasks.size(), 0, 0, 0};
+    Bucket b{&all[p], (int)B.tasks.size(), 0, 0, 0, cfog::SplitArgs{0, 1, 0, nullptr}, 0};
+    int Nmax = 0, Wmax = 0, Kmax = 0;
     for (int i = 0; i < n_jobs; ++i)
-      if (plans[i] == &all[p])
+      if (plans[i] == &all[p] && jobs[i].n_cps > 0) {
         for (int c = 0; c < jobs[i].n_cps; ++c) B.tasks.push_back(make_int2(i, c));
+        Nmax = std::max(Nmax, jobs[i].N);
+        Wmax = std::max(Wmax, jobs[i].N + 2 * jobs[i].r);
+        Kmax = std::max(Kmax, 2 * jobs[i].r + 1);
+      }
     b.count = (int)B.tasks.size() - b.begin;
     if (b.count == 0) continue;
-    b.blocks = std::min(b.count, cfog::plan_slots(b.plan, ctx->num_cus));
+    const int S = cfog::plan_slots(b.plan, ctx->num_cus);
+    size_t sb = 0;
+    b.sp = plan_split(b.plan, b.count, S, m, Nmax, Wmax, Kmax, &sb);
+    if (sb > split_budget) {
+      b.sp = cfog::SplitArgs{b.count, 1, 0, nullptr};
+      sb = 0;
+    }
+    split_budget -= sb;
+    split_bytes.push_back(sb);
+    b.blocks = std::min(cfog::split_items(b.count, b.sp), S);
     b.tg_off = tg;
     tg += align_up((size_t)b.blocks * b.plan->tg_bytes, 256);  // buckets run concurrently
     B.buckets.push_back(b);
   }
   B.jobs_off = tg;
   B.tasks_off = align_up(B.jobs_off + sizeof(cfog::MatchJob) * (size_t)n_jobs, 256);
-  B.total = B.tasks_off + sizeof(int2) * B.tasks.size();
-  B.table_bytes = B.total - B.jobs_off;
+  size_t end = align_up(B.tasks_off + sizeof(int2) * B.tasks.size(), 256);
+  B.table_bytes = B.tasks_off + sizeof(int2) * B.tasks.size() - B.jobs_off;
+  for (size_t k = 0; k < B.buckets.size(); ++k) {
+    B.buckets[k].split_off = end;
+    end += split_bytes[k];
+  }
+  B.total = end;
   return CFOG_OK;
 }
 
@@ -177,11 +261,15 @@ int enqueue_batch(cfog_ctx* ctx, const BatchPlan& B, char* ws, const void* host,
     return record(ctx, hipGetLastError());
   const cfog::MatchJob* d_jobs = (const cfog::MatchJob*)(ws + B.jobs_off);
   const int2* d_tasks = (const int2*)(ws + B.tasks_off);
+  auto launch_bucket = [&](const Bucket& b, hipStream_t s) {
+    cfog::SplitArgs sp = b.sp;
+    sp.part = sp.G > 1 ? (float*)(ws + b.split_off) : nullptr;
+    return cfog::launch_match_fft(b.plan, cfog::MatchJob{}, d_jobs, d_tasks + b.begin, b.count, b.blocks,
+                                  ws + b.tg_off, sp, s) == 0 &&
+           cfog::launch_split_reduce(cfog::MatchJob{}, d_jobs, d_tasks + b.begin, b.count, sp, s) == 0;
+  };
   if (B.buckets.size() == 1) {
-    const Bucket& b = B.buckets[0];
-    if (cfog::launch_match_fft(b.plan, cfog::MatchJob{}, d_jobs, d_tasks + b.begin, b.count, b.blocks, ws + b.tg_off,
-                               st) != 0)
-      return record(ctx, hipGetLastError());
+    if (!launch_bucket(B.buckets[0], st)) return record(ctx, hipGetLastError());
     return CFOG_OK;
   }
   if (hipEventRecord(ctx->fork, st) != hipSuccess) return record(ctx, hipGetLastError());
@@ -196,11 +284,7 @@ int enqueue_batch(cfog_ctx* ctx, const BatchPlan& B, char* ws, const void* host,
            (long)B.buckets[b].count * B.buckets[b].plan->P * B.buckets[b].plan->P;
   });
   for (size_t k = 0; k < order.size(); ++k) {
-    const Bucket& b = B.buckets[order[k]];
-    hipStream_t s = ctx->bucket[k % ns];
-    if (cfog::launch_match_fft(b.plan, cfog::MatchJob{}, d_jobs, d_tasks + b.begin, b.count, b.blocks, ws + b.tg_off,
-                               s) != 0)
-      return record(ctx, hipGetLastError());
+    if (!launch_bucket(B.buckets[order[k]], ctx->bucket[k % ns])) return record(ctx, hipGetLastError());
   }
   for (int s = 0; s < ns; ++s) {
     if (hipEventRecord(ctx->join[s], ctx->bucket[s]) != hipSuccess) return record(ctx, hipGetLastError());
@@ -287,7 +371,8 @@ int autotune(cfog_ctx* ctx, const cfog_job& j, int m, hipStream_t st, void* tg_w
     bool ok = true;
     for (int rep = 0; rep < 2 && ok; ++rep) {  // the first launch warms up
       ok = hipEventRecord(e0, st) == hipSuccess &&
-           cfog::launch_match_fft(p, dj, nullptr, nullptr, dj.n_cps, blocks, tg_ws, st) == 0 &&
+           cfog::launch_match_fft(p, dj, nullptr, nullptr, dj.n_cps, blocks, tg_ws,
+                                  cfog::SplitArgs{dj.n_cps, 1, 0, nullptr}, st) == 0 &&
            hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
            hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
     }
@@ -476,8 +561,9 @@ int cfog_extract_fhog(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, i
   return CFOG_OK;
 }
 
-size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m,
-                                  int32_t flags) {
+// Workspace bytes of a match_batch call, with the channel splits (the
+// recommended size) or without them (the minimum).
+static size_t ws_need(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags, bool split) {
   if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return (size_t)-1;
   const int path = flags & CFOG_PATH_MASK;
   for (int i = 0; i < n_jobs; ++i)
@@ -489,25 +575,31 @@ size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n
     for (int i = 0; i < n_jobs; ++i)
       tune = std::max(tune, cfog::max_tg_bytes(jobs[i].N, jobs[i].r) * (size_t)std::min(jobs[i].n_cps, 2 * ctx->num_cus));
   if (path == CFOG_PATH_PLAIN_FFT) {
-    size_t tg = 0;
+    size_t need = 0;  // the jobs run one after another on one stream
     for (int i = 0; i < n_jobs; ++i) {
-      const cfog::FftPlan* p = select_plan(ctx, jobs[i].N, jobs[i].r, m);
-      if (!p) return 0;  // match_batch reports CFOG_EUNSUPPORTED
-      if (p->tg_bytes && jobs[i].n_cps > 0)
-        tg = std::max(tg, (size_t)std::min(jobs[i].n_cps, cfog::plan_slots(p, ctx->num_cus)) * p->tg_bytes);
+      if (jobs[i].n_cps == 0) continue;
+      const PlainLayout L = plain_layout(ctx, jobs[i], m, split);
+      if (!L.p) return 0;  // match_batch reports CFOG_EUNSUPPORTED
+      need = std::max(need, L.total);
     }
-    return align_up(std::max(tg, tune), 256);
+    return align_up(std::max(need, tune), 256);
   }
   BatchPlan B;
-  if (build_batch(ctx, jobs, n_jobs, m, 0, B) != CFOG_OK) return 0;
+  if (build_batch(ctx, jobs, n_jobs, m, 0, B, split ? SIZE_MAX : 0) != CFOG_OK) return 0;
   return std::max(B.total, align_up(tune, 256));
+}
+
+size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m,
+                                  int32_t flags) {
+  return ws_need(ctx, jobs, n_jobs, m, flags, !(flags & CFOG_NO_SPLIT));
 }
 
 int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags, void* d_ws,
                 size_t ws_bytes, void* stream) {
   if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return CFOG_EINVAL;
   const int path = flags & CFOG_PATH_MASK;
-  if (flags & ~(CFOG_PATH_MASK | CFOG_AUTOTUNE | CFOG_USE_GRAPH | CFOG_OBJ_CORR)) return CFOG_EINVAL;
+  if (flags & ~(CFOG_PATH_MASK | CFOG_AUTOTUNE | CFOG_USE_GRAPH | CFOG_OBJ_CORR | CFOG_NO_SPLIT)) return CFOG_EINVAL;
+  const bool split_ok = !(flags & CFOG_NO_SPLIT);
   const int obj = (flags & CFOG_OBJ_CORR) ? 1 : 0;
   if (path != CFOG_PATH_PLAIN_FFT && path != CFOG_PATH_BATCHED_FFT && path != CFOG_PATH_MFMA_BF16)
     return CFOG_EINVAL;
@@ -531,7 +623,7 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
 
   for (int i = 0; i < n_jobs; ++i)
     if (!cfog::choose_fft_plan(jobs[i].N, jobs[i].r)) return CFOG_EUNSUPPORTED;
-  const size_t need = match_batch_workspace_size(ctx, jobs, n_jobs, m, flags);
+  const size_t need = ws_need(ctx, jobs, n_jobs, m, flags, false);  // the minimum
   if (need > 0 && (!d_ws || ws_bytes < need)) return CFOG_ENOMEM;
   if (flags & CFOG_AUTOTUNE) {
     // tune each distinct (N, r) on its first job, with the workspace's front as
@@ -548,10 +640,15 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
   if (path == CFOG_PATH_PLAIN_FFT) {
     for (int i = 0; i < n_jobs; ++i) {
       if (jobs[i].n_cps == 0) continue;
-      const cfog::FftPlan* p = select_plan(ctx, jobs[i].N, jobs[i].r, m);
-      const int blocks = p->tg_bytes ? std::min(jobs[i].n_cps, cfog::plan_slots(p, ctx->num_cus)) : jobs[i].n_cps;
-      if (p->tg_bytes && (size_t)blocks * p->tg_bytes > ws_bytes) return CFOG_ENOMEM;
-      if (cfog::launch_match_fft(p, to_device_job(jobs[i], m, obj), nullptr, nullptr, jobs[i].n_cps, blocks, ws, st) != 0)
+      // the channel split only where the workspace holds its partials
+      PlainLayout L = plain_layout(ctx, jobs[i], m, split_ok);
+      if (L.total > (d_ws ? ws_bytes : 0)) L = plain_layout(ctx, jobs[i], m, false);
+      if (L.total > (d_ws ? ws_bytes : 0)) return CFOG_ENOMEM;
+      cfog::SplitArgs sp = L.sp;
+      sp.part = sp.G > 1 ? (float*)(ws + L.split_off) : nullptr;
+      const cfog::MatchJob dj = to_device_job(jobs[i], m, obj);
+      if (cfog::launch_match_fft(L.p, dj, nullptr, nullptr, jobs[i].n_cps, L.blocks, ws, sp, st) != 0 ||
+          cfog::launch_split_reduce(dj, nullptr, nullptr, jobs[i].n_cps, sp, st) != 0)
         return record(ctx, hipGetLastError());
     }
     return CFOG_OK;
@@ -575,10 +672,16 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
     }
   }
   BatchPlan B;
-  int rc = build_batch(ctx, jobs, n_jobs, m, obj, B);
+  int rc = build_batch(ctx, jobs, n_jobs, m, obj, B, 0);
   if (rc != CFOG_OK) return rc;
   if (B.tasks.empty()) return CFOG_OK;
   if (!d_ws || ws_bytes < B.total) return CFOG_ENOMEM;
+  if (split_ok && ws_bytes > B.total) {  // room for channel splits
+    BatchPlan Bs;
+    rc = build_batch(ctx, jobs, n_jobs, m, obj, Bs, ws_bytes - B.total);
+    if (rc != CFOG_OK) return rc;
+    if (Bs.total <= ws_bytes) B = std::move(Bs);
+  }
 
   if (!(flags & CFOG_USE_GRAPH)) {
     rc = ensure_stage(ctx, B.table_bytes);

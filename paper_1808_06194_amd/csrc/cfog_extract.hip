@@ -5,7 +5,7 @@
 // contiguous H*W plane per orientation); SAT [(H+1)][(W+1)] fp64 with a zero
 // first row and column, SAT(y+1, x+1) = sum_{y'<=y, x'<=x} Q(y', x').
 //
-// Kernel 1 (cfog_extract_kernel<R>) produces a 64 x 16 output tile for all m
+// Kernel 1 (cfog_extract_kernel<R, M>) produces a 64 x 16 output tile for all m
 // channels:
 //   A. stage the image tile plus an (R+1)-pixel halo in LDS (clamp-to-edge);
 //   B. gx, gy by [-1,0,1] (the filters given after Eq. 2) at every pixel of
@@ -113,13 +113,16 @@ struct ExTile {
   static constexpr size_t BYTES = 4 * IMG + 8 * GXY + 4 * G + 4 * HB + 8 * 4 * 64;
 };
 
-template <int R>
+// M > 0: the channel count fixed at compile time (the channel loop unrolls
+// and the orientation smoothing's register rotation disappears); M = 0 reads
+// it from the arguments.
+template <int R, int M>
 __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   using T = ExTile<R>;
   constexpr int IW = T::IW, IH = T::IH, GW = T::GW, GH = T::GH, GWP = T::GWP;
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
-  const int m = a.m;
+  const int m = M > 0 ? M : a.m;
   float* img = lds;                                              // IH * IW
   float2* gxy = reinterpret_cast<float2*>(img + T::IMG);         // GH * GWP
   float* G = reinterpret_cast<float*>(gxy + T::GXY);             // GH * GWP
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
       }
     }
   };
-  for (int k = 0; k < m; ++k) {
+  auto channel = [&](int k) {
     const float ck = a.cs[k], sk = a.sn[k];
     float* hb = Hb + (k & 1) * GH * EX_TX;
     // oriented gradient of channel k at every pixel of the halo tile, two at a time
@@ -239,9 +242,10 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
       for (int it = 0; it < (T::NPAIR + EX_NT - 1) / EX_NT; ++it) {
         const int i = tid + it * EX_NT;
         if (T::NPAIR % EX_NT == 0 || i < T::NPAIR) {
+          // signed projections; the horizontal pass takes their magnitude
+          // (a free source modifier there)
           const float4 g = lds4[(T::IMG / 4) + i];  // gxy[2i], gxy[2i+1]
-          reinterpret_cast<float2*>(G)[i] =
-              make_float2(fabsf(fmaf(ck, g.x, sk * g.y)), fabsf(fmaf(ck, g.z, sk * g.w)));
+          reinterpret_cast<float2*>(G)[i] = make_float2(fmaf(ck, g.x, sk * g.y), fmaf(ck, g.z, sk * g.w));
         }
       }
     }
@@ -258,10 +262,10 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
 #pragma unroll
         for (int u = 0; u < T::NQ; ++u) {
           const float4 v = src[u];
-          x[4 * u] = v.x;
-          x[4 * u + 1] = v.y;
-          x[4 * u + 2] = v.z;
-          x[4 * u + 3] = v.w;
+          x[4 * u] = fabsf(v.x);
+          x[4 * u + 1] = fabsf(v.y);
+          x[4 * u + 2] = fabsf(v.z);
+          x[4 * u + 3] = fabsf(v.w);
         }
         float o4[4];
 #pragma unroll
@@ -306,6 +310,12 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
     for (int o = 0; o < EX_RUN; ++o) { pm2[o] = pm1[o]; pm1[o] = cur[o]; }
     // the next channel writes the other half of Hb; this half is overwritten
     // two channels later, after the next barrier
+  };
+  if constexpr (M > 0) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) channel(k);
+  } else {
+    for (int k = 0; k < m; ++k) channel(k);
   }
   {
     float d[EX_RUN];
@@ -615,16 +625,22 @@ template <int R>
 static int launch_r(const ExtractArgs& a, hipStream_t st) {
   const size_t lds = lds_bytes(a.m, R);
   dim3 grid(a.ntx, a.nty);
-  hipLaunchKernelGGL(cfog_extract_kernel<R>, grid, dim3(EX_NT), lds, st, a);
+  if (R == 3 && a.m == 9)  // the paper's parameters (sigma 0.8, nine orientations)
+    hipLaunchKernelGGL((cfog_extract_kernel<R, 9>), grid, dim3(EX_NT), lds, st, a);
+  else
+    hipLaunchKernelGGL((cfog_extract_kernel<R, 0>), grid, dim3(EX_NT), lds, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 template <int R>
 static int set_attr() {
-  return hipFuncSetAttribute((const void*)cfog_extract_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)kMaxLds) == hipSuccess
-             ? 0
-             : -2;
+  if (hipFuncSetAttribute((const void*)cfog_extract_kernel<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kMaxLds) != hipSuccess)
+    return -2;
+  if (R == 3 && hipFuncSetAttribute((const void*)cfog_extract_kernel<R, 9>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess)
+    return -2;
+  return 0;
 }
 
 template <int C>

@@ -63,8 +63,29 @@ int plan_slots(const FftPlan* p, int num_cus);
 // Launch the FFT matcher.  d_jobs == nullptr: n_tasks control points of job0
 // (plain path).  Otherwise n_tasks (job, cp) pairs from d_tasks over d_jobs.
 // tg_ws: n_blocks * tg_bytes bytes when tg_bytes > 0.
+// Channel split of a launch's last tasks: tasks [0, n_whole) run whole; every
+// later task runs as G work items, item g taking the channels
+// [g m / G, (g+1) m / G) and writing its correlation surface (K*K floats) to
+// part[(task - n_whole) * G + g][slot]; the split-reduce kernel then adds the
+// G surfaces in the order g = 0, 1, .. and finishes those tasks.  G = 1: no
+// split.  Used when a launch leaves workgroup slots idle in its last round.
+struct SplitArgs {
+  int n_whole;
+  int G;
+  int slot;
+  float* part;
+};
+
+// n_blocks: workgroups (a grid-stride loop covers the remaining items).
 int launch_match_fft(const FftPlan* plan, const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks,
-                     int n_tasks, int n_blocks, void* tg_ws, hipStream_t st);
+                     int n_tasks, int n_blocks, void* tg_ws, const SplitArgs& sp, hipStream_t st);
+// Finishes the split tasks [sp.n_whole, n_tasks) (no-op for G = 1).
+int launch_split_reduce(const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks, int n_tasks,
+                        const SplitArgs& sp, hipStream_t st);
+// Work items of a launch of n_tasks tasks under sp.
+__host__ __device__ inline int split_items(int n_tasks, const SplitArgs& sp) {
+  return sp.G > 1 ? sp.n_whole + (n_tasks - sp.n_whole) * sp.G : n_tasks;
+}
 int init_match_fft_attributes();
 int init_extract_attributes();
 

@@ -185,9 +185,14 @@ __device__ __forceinline__ void ypass_fwd(const Lane<C>& L, float2* X, const flo
   });
 }
 
+// Control point cpi of job jd over the channels [c0, c1).  part == nullptr:
+// the whole sum, finished by the epilogue; otherwise the partial correlation
+// surface goes to part (item g of a split task; item 0 reports an
+// out-of-bounds point).
 template <class C>
 __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, int cpi, float2* X, const float2* tw,
-                          ArgminState* red, float2* __restrict__ tg) {
+                          ArgminState* red, float2* __restrict__ tg, int c0, int c1,
+                          float* __restrict__ part, int g) {
   constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH, NT = C::NT, KF = C::KF;
   const int4 cp = jd.cps[cpi];
   const int N = jd.N, r = jd.r, K = 2 * r + 1, h = N / 2, Ws = N + 2 * r;
@@ -196,7 +201,7 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   const bool inA = tx0 >= 0 && ty0 >= 0 && tx0 + N <= jd.wA && ty0 + N <= jd.hA;
   const bool inB = sx0 >= 0 && sy0 >= 0 && sx0 + Ws <= jd.wB && sy0 + Ws <= jd.hB;
   if (!(inA && inB)) {
-    oob_result<NT>(jd, cpi);
+    if (g == 0) oob_result<NT>(jd, cpi);
     return;
   }
 
@@ -207,10 +212,12 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
     for (int k2 = 0; k2 < R2; ++k2) acc[k][k2] = make_float2(0.f, 0.f);
 
   const size_t planeA = (size_t)jd.hA * jd.wA, planeB = (size_t)jd.hB * jd.wB;
-  for (int c = 0; c < jd.m; ++c) {
+  const float* tA = jd.volA + (size_t)ty0 * jd.wA + tx0;
+  const float* sB = jd.volB + (size_t)sy0 * jd.wB + sx0;
+  for (int c = c0; c < c1; ++c) {
     float2 th[C::TG ? 1 : KF][R2];
     __syncthreads();  // previous readers of X are done
-    xpass_fwd<C>(L, jd.volA + c * planeA + (size_t)ty0 * jd.wA + tx0, jd.wA, N, N, X, tw);
+    xpass_fwd<C>(L, tA + c * planeA, jd.wA, N, N, X, tw);
     __syncthreads();
     ypass_fwd<C>(L, X, tw, [&](auto rndI, auto k2I, int kx, float2 v) {
       constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
@@ -218,7 +225,7 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
       else th[rnd][k2] = v;
     });
     __syncthreads();
-    xpass_fwd<C>(L, jd.volB + c * planeB + (size_t)sy0 * jd.wB + sx0, jd.wB, Ws, Ws, X, tw);
+    xpass_fwd<C>(L, sB + c * planeB, jd.wB, Ws, Ws, X, tw);
     __syncthreads();
     ypass_fwd<C>(L, X, tw, [&](auto rndI, auto k2I, int kx, float2 v) {
       constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
@@ -320,6 +327,10 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   }
   __syncthreads();
 
+  if (part) {
+    for (int i = threadIdx.x; i < K * K; i += NT) part[i] = Cs[i];
+    return;
+  }
   ssd_epilogue<NT>(jd, cpi, tx0, ty0, sx0, sy0, Cs, red);
 }
 
@@ -330,7 +341,7 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
 template <class C>
 __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const MatchJob* __restrict__ jobs,
                                                           const int2* __restrict__ tasks, int n_tasks,
-                                                          float2* __restrict__ tg_ws) {
+                                                          float2* __restrict__ tg_ws, SplitArgs sp) {
   extern __shared__ float2 smem[];
   float2* X = smem;
   float2* tw = X + C::P * C::PH;
@@ -344,8 +355,16 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
   }
   const Lane<C> L;
   float2* tg = C::TG ? tg_ws + (size_t)blockIdx.x * C::P * C::PH : nullptr;
-  for (int t = blockIdx.x; t < n_tasks; t += gridDim.x) {
+  const int n_items = split_items(n_tasks, sp);
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     __syncthreads();  // twiddles ready / previous task's reduction done
+    int t = it, g = 0, G = 1;
+    if (sp.G > 1 && it >= sp.n_whole) {  // an item of a split task
+      const int s = it - sp.n_whole;
+      t = sp.n_whole + s / sp.G;
+      g = s - (t - sp.n_whole) * sp.G;
+      G = sp.G;
+    }
     MatchJob jd = job0;
     int cpi = t;
     if (jobs) {
@@ -353,7 +372,8 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
       jd = jobs[tk.x];
       cpi = tk.y;
     }
-    match_one<C>(L, jd, cpi, X, tw, red, tg);
+    float* part = G > 1 ? sp.part + (size_t)(it - sp.n_whole) * sp.slot : nullptr;
+    match_one<C>(L, jd, cpi, X, tw, red, tg, g * jd.m / G, (g + 1) * jd.m / G, part, g);
   }
 }
 
@@ -437,10 +457,53 @@ int plan_slots(const FftPlan* p, int num_cus) {
 
 template <class C>
 static int launch_t(const MatchJob& job0, const MatchJob* jobs, const int2* tasks, int n_tasks, int n_blocks,
-                    void* tg_ws, hipStream_t st) {
+                    void* tg_ws, const SplitArgs& sp, hipStream_t st) {
   if (C::TG && !tg_ws) return -1;
   hipLaunchKernelGGL(match_fft_kernel<C>, dim3(n_blocks), dim3(C::NT), C::LDS, st, job0, jobs, tasks, n_tasks,
-                     (float2*)tg_ws);
+                     (float2*)tg_ws, sp);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// One workgroup per split task: the sum of its G partial surfaces (in item
+// order) into LDS, then the epilogue of the whole sum.
+constexpr int SR_NT = 1024;
+__global__ __launch_bounds__(SR_NT) void split_reduce_kernel(MatchJob job0, const MatchJob* __restrict__ jobs,
+                                                            const int2* __restrict__ tasks, SplitArgs sp) {
+  extern __shared__ float4 sr_lds[];
+  ArgminState* red = reinterpret_cast<ArgminState*>(sr_lds);
+  float* Cs = reinterpret_cast<float*>(red + SR_NT / 64);
+  const int t = sp.n_whole + blockIdx.x;
+  MatchJob jd = job0;
+  int cpi = t;
+  if (jobs) {
+    const int2 tk = tasks[t];
+    jd = jobs[tk.x];
+    cpi = tk.y;
+  }
+  const int4 cp = jd.cps[cpi];
+  const int N = jd.N, r = jd.r, K = 2 * r + 1, h = N / 2, Ws = N + 2 * r;
+  const int tx0 = cp.x - h, ty0 = cp.y - h;
+  const int sx0 = cp.z - h - r, sy0 = cp.w - h - r;
+  const bool inA = tx0 >= 0 && ty0 >= 0 && tx0 + N <= jd.wA && ty0 + N <= jd.hA;
+  const bool inB = sx0 >= 0 && sy0 >= 0 && sx0 + Ws <= jd.wB && sy0 + Ws <= jd.hB;
+  if (!(inA && inB)) return;  // reported by the task's first item
+  const float* p = sp.part + (size_t)blockIdx.x * sp.G * sp.slot;
+  for (int i = threadIdx.x; i < K * K; i += SR_NT) {
+    float s = p[i];
+    for (int g = 1; g < sp.G; ++g) s += p[(size_t)g * sp.slot + i];
+    Cs[i] = s;
+  }
+  __syncthreads();
+  ssd_epilogue<SR_NT>(jd, cpi, tx0, ty0, sx0, sy0, Cs, red);
+}
+
+int launch_split_reduce(const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks, int n_tasks,
+                        const SplitArgs& sp, hipStream_t st) {
+  if (sp.G <= 1 || n_tasks <= sp.n_whole) return 0;
+  const size_t lds = sizeof(ArgminState) * (SR_NT / 64) + sizeof(float) * (size_t)sp.slot;
+  if (lds > kMaxLds) return -1;
+  hipLaunchKernelGGL(split_reduce_kernel, dim3(n_tasks - sp.n_whole), dim3(SR_NT), lds, st, job0, d_jobs, d_tasks,
+                     sp);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -460,6 +523,9 @@ int init_match_fft_attributes() {
   }
   CFOG_PLANS(CFOG_PLAN_ATTR)
 #undef CFOG_PLAN_ATTR
+  if (hipFuncSetAttribute((const void*)split_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kMaxLds) != hipSuccess)
+    return -2;
   return 0;
 }
 
@@ -473,11 +539,11 @@ int init_kernel_attributes() {
 }
 
 int launch_match_fft(const FftPlan* plan, const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks,
-                     int n_tasks, int n_blocks, void* tg_ws, hipStream_t st) {
+                     int n_tasks, int n_blocks, void* tg_ws, const SplitArgs& sp, hipStream_t st) {
   if (n_tasks <= 0) return 0;
 #define CFOG_PLAN_CASE(P_, R1_, R2_, NT_, TG_) \
   if (plan->P == P_)                           \
-    return launch_t<CFOG_CFG(P_, R1_, R2_, NT_, TG_)>(job0, d_jobs, d_tasks, n_tasks, n_blocks, tg_ws, st);
+    return launch_t<CFOG_CFG(P_, R1_, R2_, NT_, TG_)>(job0, d_jobs, d_tasks, n_tasks, n_blocks, tg_ws, sp, st);
   CFOG_PLANS(CFOG_PLAN_CASE)
 #undef CFOG_PLAN_CASE
   return -1;

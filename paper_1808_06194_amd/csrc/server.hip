@@ -186,7 +186,9 @@ int launch(cfog_server* s, Slot& sl) {
   }
   if (hipMemcpyAsync(sl.d_cps, sl.h_cps, cp_off * sizeof(cfog_cp), hipMemcpyHostToDevice, sl.st) != hipSuccess)
     return CFOG_EHIP;
-  int rc = match_batch(sl.ctx, jobs.data(), (int32_t)jobs.size(), m, s->cfg.flags, sl.ws, sl.ws_bytes, sl.st);
+  // whole points: a request's results must not depend on its batch
+  int rc = match_batch(sl.ctx, jobs.data(), (int32_t)jobs.size(), m, s->cfg.flags | CFOG_NO_SPLIT, sl.ws,
+                       sl.ws_bytes, sl.st);
   if (rc != CFOG_OK) return rc;
   if (hipMemcpyAsync(sl.h_out, sl.d_out, cp_off * sizeof(cfog_result), hipMemcpyDeviceToHost, sl.st) != hipSuccess)
     return CFOG_EHIP;

@@ -202,7 +202,9 @@ def test_match_empty_job_and_unsupported_window(cf):
 
 
 def test_match_batched_equals_plain(cf):
-    """The fused task-table path returns bit-identical results to the plain path."""
+    """The fused task-table path returns bit-identical results to the plain
+    path when every point is matched whole (the two paths group the points
+    of a call differently, so their channel splits differ)."""
     _say("match batched vs plain")
     jobs_np = synth.batch_workload(n_pairs=4, sides=(256, 512), seed=7, max_cps=40, min_cps=5)
     outs = {}
@@ -214,11 +216,54 @@ def test_match_batched_equals_plain(cf):
             K = 2 * j["r"] + 1
             jobs.append(cf.Job(vA, sA, vB, sB, _dev(j["cps"]), j["N"], j["r"],
                                surfaces=torch.empty((len(j["cps"]), K, K), device="cuda")))
-        cf.match_batch(jobs, flags=flags)
+        cf.match_batch(jobs, flags=flags | cf.NO_SPLIT)
         torch.cuda.synchronize()
         outs[flags] = [(jb.out.cpu(), jb.surfaces.cpu()) for jb in jobs]
     for (o1, s1), (o2, s2) in zip(outs[cf.PATH_PLAIN_FFT], outs[cf.PATH_BATCHED_FFT]):
         assert torch.equal(o1, o2) and torch.equal(s1, s2)
+
+
+@pytest.mark.parametrize("N,r,H,n,seed", [(48, 10, 256, 16, 61), (128, 32, 256, 4, 62), (100, 20, 300, 7, 63)])
+def test_channel_split_matches_unsplit(cf, N, r, H, n, seed):
+    """A launch whose last round would leave workgroup slots idle splits those
+    points by channel groups over several workgroups (the recommended
+    workspace holds the partial surfaces); with no workspace the same points
+    run whole.  Both agree with the FP64 oracle, and with each other up to
+    FP32 rounding of the channel sum.  (128, 32) takes a plan that parks the
+    template spectrum in global memory."""
+    _say("channel split vs whole", N, r, H, n, seed)
+    spec = synth.PairSpec(H, H, max(6, H // 6), (2.0, 12.0), 6, 3)
+    A, B, _ = synth.make_pair(spec, (310, seed))
+    cps = synth.random_cps(np.random.default_rng(seed), H, H, N, r, n)
+    cps = np.concatenate([cps, [[2, 2, 2, 2]]]).astype(np.int32)  # an out-of-bounds point last
+    vA, sA = cf.cfog_extract(_dev(A))
+    vB, sB = cf.cfog_extract(_dev(B))
+    K = 2 * r + 1
+    dcps = _dev(cps)
+    probe = cf.Job(vA, sA, vB, sB, dcps, N, r, surfaces=torch.empty((len(cps), K, K), device="cuda"))
+    need = cf.load().match_batch_workspace_size(cf.context().handle, cf.make_jobs_array([probe]), 1, 9,
+                                                cf.PATH_PLAIN_FFT)
+    assert 0 < need < (1 << 40)
+    outs = []
+    # the recommended workspace (split), then one too small for the partials (whole)
+    for nbytes in (need, need - 256):
+        surf = torch.empty((len(cps), K, K), device="cuda")
+        job = cf.Job(vA, sA, vB, sB, dcps, N, r, surfaces=surf)
+        cf.match_batch([job], workspace=torch.empty(nbytes, dtype=torch.uint8, device="cuda"))
+        torch.cuda.synchronize()
+        outs.append(({k: v.cpu().numpy() for k, v in cf.results(job.out).items()}, surf.cpu().numpy()))
+    (rs, ss), (rw, sw) = outs
+    assert not np.array_equal(ss[:-1], sw[:-1]), "expected different channel summation orders"
+    for res in (rs, rw):
+        assert res["status"][-1] == cf.CP_OUT_OF_BOUNDS
+    assert np.all(np.isnan(ss[-1])) and np.all(np.isnan(sw[-1]))
+    stats = {}
+    for k, cp in enumerate(cps[:-1]):
+        S, E1, E2 = parity.oracle_point(A, B, cp, N, r)
+        for res, surf in ((rs, ss), (rw, sw)):
+            parity.check_point(k, res, S, E1, E2, r, surf[k], stats)
+        assert np.max(np.abs(ss[k].astype(np.float64) - sw[k]) / (E1 + E2)) <= 2e-5
+    _say("stats", stats)
 
 
 def test_match_plain_2048_full_size_sampled(cf):

@@ -76,7 +76,7 @@ def _direct(cf, pairs, reqs, flags):
         K = 2 * q["r"] + 1
         surf = torch.empty((len(q["cps"]), K, K), device="cuda") if q["surfaces"] else None
         job = cf.Job(vA, sA, vB, sB, torch.from_numpy(q["cps"]).cuda(), q["N"], q["r"], surfaces=surf)
-        cf.match_batch([job], flags=flags)
+        cf.match_batch([job], flags=flags | cf.NO_SPLIT)  # the server matches every point whole
         out.append((job, surf))
     torch.cuda.synchronize()
     return [(j.out.cpu().numpy(), None if s is None else s.cpu().numpy()) for j, s in out]
