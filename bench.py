@@ -21,6 +21,12 @@ Workloads (--workload):
   harris_8192: block-based Harris feature points (Section IV) of one 8192^2
       image: 128 x 128 cells, 60 x 60 chips, 4 points per chip; reports
       feature points/s (the control-point producer, not a CP-match rate).
+  reject_3000: iterative cubic outlier rejection (Section IV) of one set of
+      3000 matched points (5% gross outliers, threshold 1 px); reports point
+      sets/s.
+--descriptor (matching workloads): cfog (Eq. 2, default), scheme1 (CFOG
+  with binned orientations) or fhog (36-channel pixel-wise HOG, cell 4); the
+  matcher then takes that volume (m = 9, 9, 36).
   serve: the matching server with 32 resident pairs (8 each of 1024^2,
       2048^2, 4096^2, 8192^2) under open-loop Poisson arrivals of requests
       (1-500 control points, template 40-128, radius 5-32): latency
@@ -84,14 +90,16 @@ def extract_bytes_per_px(m: int = 9) -> int:
     return 4 + 4 * m + 8
 
 
-def cpu_baseline(pairs, budget_s: float = 20.0):
-    """The FP64 oracle (CFOG of the first pair's images + brute-force SSD) on a
-    bounded sample of its control points, scaled to CP matches/s of that pair."""
+def cpu_baseline(pairs, budget_s: float = 20.0, descriptor: str = "cfog"):
+    """The FP64 oracle (the descriptor volumes of the first pair's images +
+    brute-force SSD) on a bounded sample of its control points, scaled to CP
+    matches/s of that pair."""
     import oracle as O
+    desc = {"cfog": O.cfog, "scheme1": lambda I: O.cfog(I, scheme=1), "fhog": O.fhog}[descriptor]
     t0 = time.perf_counter()
     A, B, cps, N, r = pairs[0]["A"], pairs[0]["B"], pairs[0]["cps"], pairs[0]["N"], pairs[0]["r"]
-    D1 = O.cfog(A.astype(np.float64))
-    D2 = O.cfog(B.astype(np.float64))
+    D1 = desc(A.astype(np.float64))
+    D2 = desc(B.astype(np.float64))
     t_ext = time.perf_counter() - t0
     t1 = time.perf_counter()
     n = 0
@@ -103,7 +111,7 @@ def cpu_baseline(pairs, budget_s: float = 20.0):
     t_cp = (time.perf_counter() - t1) / n
     total = t_ext + len(cps) * t_cp
     return dict(value=round(len(cps) / total, 3), unit="CP matches/s", cores=1, kind="oracle",
-                sample=f"FP64 CFOG of both {A.shape[0]}x{A.shape[1]} images ({t_ext:.1f} s) + direct SSD of "
+                sample=f"FP64 {descriptor} of both {A.shape[0]}x{A.shape[1]} images ({t_ext:.1f} s) + direct SSD of "
                        f"{n} of {len(cps)} CPs ({t_cp:.3f} s/CP), extrapolated to all {len(cps)} CPs",
                 seconds=round(time.perf_counter() - t0, 2))
 
@@ -160,8 +168,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="plain_2048",
-                    choices=["plain_2048", "plain_256", "precision_4096", "batch_64", "serve", "harris_8192"])
+                    choices=["plain_2048", "plain_256", "precision_4096", "batch_64", "serve", "harris_8192",
+                             "reject_3000"])
     ap.add_argument("--path", choices=["plain", "batched", "fft", "mfma"], default=None)
+    ap.add_argument("--descriptor", choices=["cfog", "scheme1", "fhog"], default="cfog")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -183,6 +193,9 @@ def main():
     if args.workload == "harris_8192":
         run_harris(args)
         return
+    if args.workload == "reject_3000":
+        run_reject(args)
+        return
 
     pairs = make_workload(args.workload)  # before anything touches the GPU (worker processes fork)
     import torch
@@ -190,7 +203,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    m = 9
+    desc = args.descriptor
+    m = cfog.FHOG_CHANNELS if desc == "fhog" else 9
     path = args.path or {"batch_64": "batched", "precision_4096": "fft"}.get(args.workload, "plain")
     flags = {"plain": cfog.PATH_PLAIN_FFT, "fft": cfog.PATH_PLAIN_FFT, "mfma": cfog.PATH_MFMA_BF16,
              "batched": cfog.PATH_BATCHED_FFT | cfog.AUTOTUNE | cfog.USE_GRAPH}[path]
@@ -221,8 +235,12 @@ def main():
         fork.record(stream)
         side.wait_event(fork)
         for i, (img, vol, sat) in enumerate(imgs):
-            cfog.cfog_extract(img, m=m, vol=vol, sat=sat, stream=(stream if i % 2 == 0 else side),
-                              workspace=ws_ext[i % 2])
+            st = stream if i % 2 == 0 else side
+            if desc == "fhog":
+                cfog.fhog_extract(img, vol=vol, sat=sat, stream=st, workspace=ws_ext[i % 2])
+            else:
+                cfog.cfog_extract(img, m=m, vol=vol, sat=sat, stream=st, workspace=ws_ext[i % 2],
+                                  scheme=1 if desc == "scheme1" else 2)
         join.record(side)
         stream.wait_event(join)
         if evs:
@@ -267,7 +285,9 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16 x bf16 -> f32 (FP64 energies)" if path == "mfma" else "f32 (FP64 energies)",
         "data": "synthetic",
-        "config": {"workload": describe(args.workload, pairs), "path": path, "n_cps": n_cps},
+        "config": {"workload": describe(args.workload, pairs), "path": path, "n_cps": n_cps,
+                   "descriptor": {"cfog": "CFOG (Eq. 2)", "scheme1": "CFOG scheme 1 (binned orientations)",
+                                  "fhog": "pixel-wise HOG, 36 channels, cell 4"}[desc], "m": m},
         "latency_ms": {"step_p50": round(float(np.percentile(step_ms, 50)), 4),
                        "step_p99": round(float(np.percentile(step_ms, 99)), 4),
                        "match_p50": round(float(np.percentile(match_ms, 50)), 4),
@@ -302,9 +322,12 @@ def main():
         else:
             roof = dict(hbm)
             roof["bound"] = "hbm"
+        # the timed span is the whole match_batch call: the matcher launch and,
+        # where its last round is split by channel groups, the reduce kernel
         kernel = "match_fft_kernel" + (f"<P={cfog.plan_for(pairs[0]['N'], pairs[0]['r'], m)}>"
-                                       if len(pairs) == 1 else "<mixed P>")
-    traffic = traffic_record(f"{args.workload}:{path}") if path != "mfma" else None
+                                       if len(pairs) == 1 else "<mixed P>") + " + split_reduce_kernel"
+    key = f"{args.workload}:{path}" + ("" if desc == "cfog" else f":{desc}")
+    traffic = traffic_record(key) if path != "mfma" else None
     roof.update(kernel=kernel, traffic=traffic, bytes_per_launch=bytes_launch, flops_per_launch=flops,
                 hbm=hbm, alu=dict(achieved=round(tfs, 3), unit="TFLOP/s",
                                   peak=BF16_PEAK_TFS if path == "mfma" else FP32_PEAK_TFS))
@@ -324,7 +347,7 @@ def main():
         out["calib_copy_bytes"] = nb
         del junk
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pairs, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(pairs, args.cpu_budget, desc)
     print(json.dumps(out), flush=True)
 
 
@@ -377,6 +400,58 @@ def run_harris(args):
         "config": {"workload": "harris_8192: one 8192^2 image, 128 x 128 cells, 60 x 60 chips, 4 points per chip, "
                                "sigma 1, kappa 0.04", "chips": chips, "points": pts},
         "latency_ms": {"p50": round(float(np.percentile(kms, 50)), 4), "p99": round(float(np.percentile(kms, 99)), 4)},
+        "roofline": roof,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_reject(args):
+    from paper_1808_06194_amd import synth
+    P, Q = synth.reject_points(np.random.default_rng(np.random.SeedSequence([6, 0])), 3000, 150)
+    import torch
+    from paper_1808_06194_amd import cfog
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    dP, dQ = torch.from_numpy(P).to(dev), torch.from_numpy(Q).to(dev)
+    keep = torch.empty(len(P), dtype=torch.uint8, device=dev)
+    res = torch.empty(27, dtype=torch.float64, device=dev)  # one cfog_reject_result (216 bytes)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        cfog.reject_outliers(dP, dQ, 1.0, stream=stream, keep=keep, result=res, sync=False)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        cfog.reject_outliers(dP, dQ, 1.0, stream=stream, keep=keep, result=res, sync=False)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    kms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    t = float(np.mean(kms)) * 1e-3
+    info = cfog.reject_result_dict(res)
+    iters = info["removed"] + 1
+    # per iteration and kept point: 10 monomials (10 flops), the 55 + 20
+    # normal-equation products and sums (150), the model evaluation and the
+    # residual (45); the 10 x 10 Cholesky per iteration is negligible
+    n = len(P)
+    flops = sum((n - i) * 205.0 for i in range(iters))
+    tfs = flops / t / 1e12
+    FP64_PEAK_TFS = 78.6
+    roof = dict(bound="alu", achieved=round(tfs, 5), peak=FP64_PEAK_TFS, unit="TFLOP/s",
+                frac=round(tfs / FP64_PEAK_TFS, 6), kernel="reject_kernel (one workgroup per point set)",
+                traffic=None, flops_per_launch=flops, iterations=iters,
+                one_cu_peak_tfs=round(FP64_PEAK_TFS / 256, 4),
+                one_cu_frac=round(tfs / (FP64_PEAK_TFS / 256), 4))
+    out = {
+        "metric": "outlier-rejection point sets/s (cubic model, Section IV) on 1 MI355X",
+        "value": round(1.0 / t, 2), "unit": "point sets/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "reject_3000: 3000 matched points, 150 gross outliers, threshold 1 px",
+                   "points": n, "removed": info["removed"], "rmse": info["rmse"]},
+        "latency_ms": {"p50": round(float(np.percentile(kms, 50)), 4),
+                       "p99": round(float(np.percentile(kms, 99)), 4)},
         "roofline": roof,
     }
     print(json.dumps(out), flush=True)

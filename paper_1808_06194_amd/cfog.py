@@ -331,28 +331,42 @@ def harris_grid(img: torch.Tensor, n: int, k: int, chip: int = 60, sigma: float 
     return cps, resp
 
 
-def reject_outliers(src: torch.Tensor, dst: torch.Tensor, threshold: float = 3.5, stream=None):
+def reject_outliers(src: torch.Tensor, dst: torch.Tensor, threshold: float = 3.5, stream=None,
+                    keep: Optional[torch.Tensor] = None, result: Optional[torch.Tensor] = None, sync: bool = True):
     """Iterative cubic-polynomial outlier rejection (see cfog_reject_outliers
     in include/cfog.h).  src, dst: (n, 2) cuda fp32 point coordinates.
-    Returns (keep (n,) uint8 cuda tensor, result dict with coef (10, 2),
-    centre, half_extent, rmse, removed, n_kept, status); synchronises."""
+    keep / result: optional preallocated outputs ((n,) uint8; a cuda tensor of
+    at least 216 bytes, 8-byte aligned).  Returns (keep, result dict with coef
+    (10, 2), centre, half_extent, rmse, removed, n_kept, status) after
+    synchronising, or (keep, result tensor) with sync=False."""
     if src.shape != dst.shape or src.dim() != 2 or src.shape[1] != 2:
         raise ValueError("src and dst must be (n, 2)")
     src = src.to(torch.float32).contiguous()
     dst = dst.to(torch.float32).contiguous()
     n = src.shape[0]
-    keep = torch.empty((n,), dtype=torch.uint8, device=src.device)
-    res = torch.empty((ctypes.sizeof(cfog_reject_result),), dtype=torch.uint8, device=src.device)
+    if keep is None:
+        keep = torch.empty((n,), dtype=torch.uint8, device=src.device)
+    if result is None:
+        result = torch.empty((ctypes.sizeof(cfog_reject_result),), dtype=torch.uint8, device=src.device)
+    if keep.numel() < n or result.numel() * result.element_size() < ctypes.sizeof(cfog_reject_result):
+        raise ValueError("keep or result too small")
     rc = load().cfog_reject_outliers(context(src.device.index).handle, src.data_ptr(), dst.data_ptr(), n,
-                                     float(threshold), keep.data_ptr(), res.data_ptr(), _stream_ptr(stream))
+                                     float(threshold), keep.data_ptr(), result.data_ptr(), _stream_ptr(stream))
     _check(rc, "cfog_reject_outliers")
+    if not sync:
+        return keep, result
     torch.cuda.synchronize(src.device)
-    r = cfog_reject_result.from_buffer_copy(bytes(res.cpu().numpy()))
+    return keep, reject_result_dict(result)
+
+
+def reject_result_dict(result: torch.Tensor) -> dict:
+    """The fields of a cfog_reject_result held in a device or host tensor."""
+    raw = result.contiguous().view(torch.uint8).cpu().numpy().tobytes()[:ctypes.sizeof(cfog_reject_result)]
+    r = cfog_reject_result.from_buffer_copy(raw)
     import numpy as np
-    out = dict(coef=np.array([[r.coef[a][c] for c in range(2)] for a in range(10)]),
-               centre=np.array(list(r.centre)), half_extent=np.array(list(r.half_extent)), rmse=r.rmse,
-               removed=r.removed, n_kept=r.n_kept, status=r.status)
-    return keep, out
+    return dict(coef=np.array([[r.coef[a][c] for c in range(2)] for a in range(10)]),
+                centre=np.array(list(r.centre)), half_extent=np.array(list(r.half_extent)), rmse=r.rmse,
+                removed=r.removed, n_kept=r.n_kept, status=r.status)
 
 
 def set_plan(N: int, r: int, P: int, device: Optional[int] = None):

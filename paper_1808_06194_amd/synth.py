@@ -214,3 +214,16 @@ def serve_requests(n: int, rate: float, sides=SERVE_SIDES, seed: int = 999, max_
         cps = random_cps(rng, sides[p], sides[p], N, r, k)
         out.append(dict(t=float(t[i]), pair=p, cps=cps, N=N, r=r))
     return out
+
+
+def reject_points(rng: np.random.Generator, n: int, n_bad: int, side: float = 2048.0, noise: float = 0.4,
+                  curve: float = 3.0):
+    """n matched point pairs (src, dst), float32 (n, 2): dst = src + a smooth
+    quadratic warp (amplitude `curve` px) + a constant shift + Gaussian noise,
+    with n_bad of them displaced by up to 40 px (gross outliers)."""
+    P = rng.uniform(0, side, (n, 2))
+    u, v = (P[:, 0] - side / 2) / (side / 2), (P[:, 1] - side / 2) / (side / 2)
+    Q = P + np.stack([curve * u * v + 5.0, -curve * u * u * v + 2.0], 1) + rng.normal(0, noise, (n, 2))
+    bad = rng.choice(n, n_bad, replace=False)
+    Q[bad] += rng.uniform(-40, 40, (n_bad, 2))
+    return P.astype(np.float32), Q.astype(np.float32)
