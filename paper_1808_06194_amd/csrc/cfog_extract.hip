@@ -5,25 +5,27 @@
 // contiguous H*W plane per orientation); SAT [(H+1)][(W+1)] fp64 with a zero
 // first row and column, SAT(y+1, x+1) = sum_{y'<=y, x'<=x} Q(y', x').
 //
-// Kernel 1 (cfog_extract_kernel<R, M>) produces a 64 x 16 output tile for all m
-// channels:
+// Kernel 1 (cfog_extract_kernel<R, M>) produces a 64 x 16 output tile for all
+// m channels:
 //   A. stage the image tile plus an (R+1)-pixel halo in LDS (clamp-to-edge);
 //   B. gx, gy by [-1,0,1] (the filters given after Eq. 2) at every pixel of
 //      the tile + R halo, at the clamped pixel (which is what clamp-to-edge
-//      Gaussian borders read); (gx, gy) -> LDS;
-//   C. per channel k: g_k = |cos(theta_k) gx + sin(theta_k) gy| (Eq. 2,
-//      theta_k = k pi / m) into LDS, the horizontal Gaussian pass (consecutive
-//      lanes on consecutive columns, conflict-free), then the vertical pass
-//      (radius R, 4 outputs per thread from a sliding window down a column);
-//      the circular [1,2,1]/4 orientation smoothing is
-//      applied to the spatially smoothed channels with rolling registers, and
-//      each finished channel goes straight to HBM; Q accumulated in FP64 from
-//      the FP32 outputs;
+//      Gaussian borders read), into two LDS planes;
+//   C. per channel k: the horizontal Gaussian pass of
+//      g_k = |cos(theta_k) gx + sin(theta_k) gy| (Eq. 2, theta_k = k pi / m),
+//      the channel values formed on the fly from 16-byte reads of both
+//      planes (four outputs per thread, consecutive lanes on consecutive
+//      columns), then the vertical pass (radius R, 4 outputs per thread from
+//      a sliding window down a column); the circular [1,2,1]/4 orientation
+//      smoothing is applied to the spatially smoothed channels with rolling
+//      registers, and each finished channel goes straight to HBM; Q
+//      accumulated in FP64 from the FP32 outputs;
 //   D. the tile-local 2-D inclusive prefix L of Q (row scan across the 64 lanes
 //      of a wave, column scan down the tile), written into the SAT buffer,
 //      plus the tile's right column and bottom row into a small workspace.
-// LDS holds only the image tile, (gx, gy), one channel and two row-pass
-// buffers (~39 KB at R = 3), so four workgroups share a CU.
+// LDS holds the two gradient planes and two row-pass buffers (the image tile
+// shares their storage), about 26 KB at R = 3, so six workgroups share a CU;
+// one barrier per channel.
 
 // Global SAT from tile-local prefixes: for a tile (i, j) with origin (y0, x0),
 //   SAT(y, x) = L(y, x) + sum_{j'<j} Rc_{i,j'}(y) + sum_{i'<i} Bt_{i',j}(x)
@@ -102,15 +104,15 @@ struct ExTile {
   static constexpr int IW = EX_TX + 2 * R + 2, IH = EX_TY + 2 * R + 2;  // image tile (+1 for the gradient)
   static constexpr int GW = EX_TX + 2 * R, GH = EX_TY + 2 * R;          // gradient / channel tile
   static constexpr int NQ = (4 + 2 * R + 3) / 4;  // 16-byte reads per 4 horizontal outputs
-  // channel row stride: a multiple of 4 floats covering the last quad's reads
+  // gradient row stride: a multiple of 4 floats covering the last quad's reads
   static constexpr int GWP = ((GW + 3) / 4 * 4) > (EX_TX - 4 + 4 * NQ) ? ((GW + 3) / 4 * 4) : (EX_TX - 4 + 4 * NQ);
-  static constexpr int NPAIR = GH * GWP / 2;      // channel values computed two at a time
   static constexpr int NQUAD = GH * EX_TX / 4;    // horizontal outputs four at a time
   static constexpr size_t IMG = ((size_t)IH * IW + 3) / 4 * 4;   // floats
-  static constexpr size_t GXY = (size_t)GH * GWP;                // float2
-  static constexpr size_t G = (size_t)GH * GWP;                  // floats
+  static constexpr size_t GP = (size_t)GH * GWP;                 // floats per gradient plane
   static constexpr size_t HB = 2 * (size_t)GH * EX_TX;           // floats (two channels)
-  static constexpr size_t BYTES = 4 * IMG + 8 * GXY + 4 * G + 4 * HB + 8 * 4 * 64;
+  // the image tile is dead once the gradients exist: it shares HB's storage
+  static constexpr size_t HBI = HB > IMG ? HB : IMG;
+  static constexpr size_t BYTES = 4 * 2 * GP + 4 * HBI + 8 * 4 * 64;
 };
 
 // M > 0: the channel count fixed at compile time (the channel loop unrolls
@@ -123,11 +125,11 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   const int m = M > 0 ? M : a.m;
-  float* img = lds;                                              // IH * IW
-  float2* gxy = reinterpret_cast<float2*>(img + T::IMG);         // GH * GWP
-  float* G = reinterpret_cast<float*>(gxy + T::GXY);             // GH * GWP
-  float* Hb = G + T::G;                                          // 2 * GH * EX_TX
-  double* qx = reinterpret_cast<double*>(Hb + T::HB);            // 4 x 64 wave carries
+  float* gxp = lds;                                  // GH * GWP: gx (scheme 1: |g|)
+  float* gyp = gxp + T::GP;                          // GH * GWP: gy (scheme 1: bin position)
+  float* Hb = gyp + T::GP;                           // 2 * GH * EX_TX row-pass outputs
+  float* img = Hb;                                   // IH * IW, read only by the gradient pass
+  double* qx = reinterpret_cast<double*>(Hb + T::HBI);  // 4 x 64 wave carries
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * EX_TX, y0 = blockIdx.y * EX_TY;
   const int H = a.H, W = a.W;
@@ -161,42 +163,63 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   // directly; tiles at the border take them at clamped positions, which is
   // what clamp-to-edge gradient and Gaussian borders read.
   const bool interior = x0 - R - 1 >= 0 && y0 - R - 1 >= 0 && x0 + EX_TX + R <= W - 1 && y0 + EX_TY + R <= H - 1;
+  float2 gb[(GH * GW + EX_NT - 1) / EX_NT];  // held until the image tile is dead
   if (interior) {
-    for (int i = tid; i < GH * GW; i += EX_NT) {
-      const int r = i / GW, c = i - r * GW;
-      const float* p = img + (r + 1) * IW + c + 1;
-      gxy[r * GWP + c] = make_float2(p[1] - p[-1], p[IW] - p[-IW]);
+#pragma unroll
+    for (int it = 0; it < (GH * GW + EX_NT - 1) / EX_NT; ++it) {
+      const int i = tid + it * EX_NT;
+      if (i < GH * GW) {
+        const int r = i / GW, c = i - r * GW;
+        const float* p = img + (r + 1) * IW + c + 1;
+        gb[it] = make_float2(p[1] - p[-1], p[IW] - p[-IW]);
+      }
     }
   } else {
     const int oy = y0 - R - 1, ox = x0 - R - 1;  // global coords of img[0][0]
-    for (int i = tid; i < GH * GW; i += EX_NT) {
-      int r = i / GW, c = i - r * GW;
-      int Yc = clampi(y0 - R + r, 0, H - 1), Xc = clampi(x0 - R + c, 0, W - 1);
-      int yl = Yc - oy, xl = Xc - ox;
-      int xp = clampi(Xc + 1, 0, W - 1) - ox, xm = clampi(Xc - 1, 0, W - 1) - ox;
-      int yp = clampi(Yc + 1, 0, H - 1) - oy, ym = clampi(Yc - 1, 0, H - 1) - oy;
-      gxy[r * GWP + c] = make_float2(img[yl * IW + xp] - img[yl * IW + xm], img[yp * IW + xl] - img[ym * IW + xl]);
+#pragma unroll
+    for (int it = 0; it < (GH * GW + EX_NT - 1) / EX_NT; ++it) {
+      const int i = tid + it * EX_NT;
+      if (i < GH * GW) {
+        const int r = i / GW, c = i - r * GW;
+        const int Yc = clampi(y0 - R + r, 0, H - 1), Xc = clampi(x0 - R + c, 0, W - 1);
+        const int yl = Yc - oy, xl = Xc - ox;
+        const int xp = clampi(Xc + 1, 0, W - 1) - ox, xm = clampi(Xc - 1, 0, W - 1) - ox;
+        const int yp = clampi(Yc + 1, 0, H - 1) - oy, ym = clampi(Yc - 1, 0, H - 1) - oy;
+        gb[it] = make_float2(img[yl * IW + xp] - img[yl * IW + xm], img[yp * IW + xl] - img[ym * IW + xl]);
+      }
     }
   }
   // scheme 1 keeps (|g|, orientation bin position in [0, m)) instead of (gx, gy)
   if (a.scheme == 1) {
     const float bscale = (float)m / 3.14159265358979f;
-    for (int i = tid; i < GH * GW; i += EX_NT) {
-      const int r = i / GW, c = i - r * GW;
-      const float2 g = gxy[r * GWP + c];
+#pragma unroll
+    for (int it = 0; it < (GH * GW + EX_NT - 1) / EX_NT; ++it) {
+      const float2 g = gb[it];
       float phi = atan2f(g.y, g.x);
       if (phi < 0.f) phi += 3.14159265358979f;
       float b = phi * bscale;
       if (b >= (float)m) b -= (float)m;
-      gxy[r * GWP + c] = make_float2(sqrtf(g.x * g.x + g.y * g.y), b);
+      gb[it] = make_float2(sqrtf(g.x * g.x + g.y * g.y), b);
     }
   }
-  // the padding columns of gxy feed only channel values that no output reads
+#pragma unroll
+  for (int it = 0; it < (GH * GW + EX_NT - 1) / EX_NT; ++it) {
+    const int i = tid + it * EX_NT;
+    if (i < GH * GW) {
+      const int r = i / GW, c = i - r * GW;
+      gxp[r * GWP + c] = gb[it].x;
+      gyp[r * GWP + c] = gb[it].y;
+    }
+  }
+  // the padding columns of the gradient planes feed only channel values that
+  // no output reads
   __syncthreads();
 
-  // C. per channel: oriented gradient, horizontal then vertical Gaussian; the
-  // vertical pass leaves the spatially smoothed channel Gs_k for the rows
-  // [4 (tid/64), +4) of column tid % 64 in registers.
+  // C. per channel: the horizontal Gaussian of the oriented gradient (the
+  // channel values computed on the fly from the gradient planes), then the
+  // vertical pass, which leaves the spatially smoothed channel Gs_k for the
+  // rows [4 (tid/64), +4) of column tid % 64 in registers.  One barrier per
+  // channel: the row-pass buffer alternates between two halves.
   const int oc = tid & 63, orow = (tid >> 6) * EX_RUN;
   const int gxx = x0 + oc;
   double q[EX_RUN];
@@ -218,54 +241,38 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
       }
     }
   };
+  const bool s1 = a.scheme == 1;
   auto channel = [&](int k) {
     const float ck = a.cs[k], sk = a.sn[k];
+    const float kf = (float)k, mf = (float)m;
+    // oriented gradient g_k of one pixel from its two gradient-plane values:
+    // |cos(theta_k) gx + sin(theta_k) gy| (Eq. 2), or for scheme 1
+    // |g| max(0, 1 - circular distance of the bin position to k)
+    auto gk = [&](float u, float v) {
+      if (s1) {
+        const float d = fabsf(v - kf);
+        return u * fmaxf(0.f, 1.f - fminf(d, mf - d));
+      }
+      return fabsf(fmaf(ck, u, sk * v));
+    };
     float* hb = Hb + (k & 1) * GH * EX_TX;
-    // oriented gradient of channel k at every pixel of the halo tile, two at a time
-    if (a.scheme == 1) {
-      // |g| times max(0, 1 - circular distance of the bin position to k)
-      const float kf = (float)k, mf = (float)m;
-      auto wgt = [&](float b) {
-        const float d = fabsf(b - kf);
-        return fmaxf(0.f, 1.f - fminf(d, mf - d));
-      };
-#pragma unroll
-      for (int it = 0; it < (T::NPAIR + EX_NT - 1) / EX_NT; ++it) {
-        const int i = tid + it * EX_NT;
-        if (T::NPAIR % EX_NT == 0 || i < T::NPAIR) {
-          const float4 g = lds4[(T::IMG / 4) + i];  // (|g|, b) of two pixels
-          reinterpret_cast<float2*>(G)[i] = make_float2(g.x * wgt(g.y), g.z * wgt(g.w));
-        }
-      }
-    } else {
-#pragma unroll
-      for (int it = 0; it < (T::NPAIR + EX_NT - 1) / EX_NT; ++it) {
-        const int i = tid + it * EX_NT;
-        if (T::NPAIR % EX_NT == 0 || i < T::NPAIR) {
-          // signed projections; the horizontal pass takes their magnitude
-          // (a free source modifier there)
-          const float4 g = lds4[(T::IMG / 4) + i];  // gxy[2i], gxy[2i+1]
-          reinterpret_cast<float2*>(G)[i] = make_float2(fmaf(ck, g.x, sk * g.y), fmaf(ck, g.z, sk * g.w));
-        }
-      }
-    }
-    __syncthreads();
     // horizontal pass: each thread four consecutive outputs of one row from
-    // 16-byte reads (16 threads cover a row)
+    // 16-byte reads of both gradient planes (16 threads cover a row)
 #pragma unroll
     for (int it = 0; it < (T::NQUAD + EX_NT - 1) / EX_NT; ++it) {
       const int qd = tid + it * EX_NT;
       if (T::NQUAD % EX_NT == 0 || qd < T::NQUAD) {
         const int r = qd >> 4, c4 = (qd & 15) * 4;
-        const float4* src = reinterpret_cast<const float4*>(G + r * GWP + c4);
+        const float4* sx = reinterpret_cast<const float4*>(gxp + r * GWP + c4);
+        const float4* sy = reinterpret_cast<const float4*>(gyp + r * GWP + c4);
         float x[4 * T::NQ];
 #pragma unroll
         for (int u = 0; u < T::NQ; ++u) {
-          const float4 v = src[u];
-          x[4 * u] = fabsf(v.x);
-          x[4 * u + 1] = fabsf(v.y);
-          x[4 * u + 2] = fabsf(v.z);
-          x[4 * u + 3] = fabsf(v.w);
+          const float4 vx = sx[u], vy = sy[u];
+          x[4 * u] = gk(vx.x, vy.x);
+          x[4 * u + 1] = gk(vx.y, vy.y);
+          x[4 * u + 2] = gk(vx.z, vy.z);
+          x[4 * u + 3] = gk(vx.w, vy.w);
         }
         float o4[4];
 #pragma unroll
@@ -309,7 +316,8 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
 #pragma unroll
     for (int o = 0; o < EX_RUN; ++o) { pm2[o] = pm1[o]; pm1[o] = cur[o]; }
     // the next channel writes the other half of Hb; this half is overwritten
-    // two channels later, after the next barrier
+    // two channels later, after the next barrier (which every thread reaches
+    // only when its reads of this half are done)
   };
   if constexpr (M > 0) {
 #pragma unroll
@@ -625,10 +633,13 @@ template <int R>
 static int launch_r(const ExtractArgs& a, hipStream_t st) {
   const size_t lds = lds_bytes(a.m, R);
   dim3 grid(a.ntx, a.nty);
-  if (R == 3 && a.m == 9)  // the paper's parameters (sigma 0.8, nine orientations)
-    hipLaunchKernelGGL((cfog_extract_kernel<R, 9>), grid, dim3(EX_NT), lds, st, a);
-  else
-    hipLaunchKernelGGL((cfog_extract_kernel<R, 0>), grid, dim3(EX_NT), lds, st, a);
+  if constexpr (R == 3) {
+    if (a.m == 9) {  // the paper's parameters (sigma 0.8, nine orientations)
+      hipLaunchKernelGGL((cfog_extract_kernel<R, 9>), grid, dim3(EX_NT), lds, st, a);
+      return hipGetLastError() == hipSuccess ? 0 : -2;
+    }
+  }
+  hipLaunchKernelGGL((cfog_extract_kernel<R, 0>), grid, dim3(EX_NT), lds, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -637,9 +648,11 @@ static int set_attr() {
   if (hipFuncSetAttribute((const void*)cfog_extract_kernel<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)kMaxLds) != hipSuccess)
     return -2;
-  if (R == 3 && hipFuncSetAttribute((const void*)cfog_extract_kernel<R, 9>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess)
-    return -2;
+  if constexpr (R == 3) {
+    if (hipFuncSetAttribute((const void*)cfog_extract_kernel<R, 9>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kMaxLds) != hipSuccess)
+      return -2;
+  }
   return 0;
 }
 
