@@ -3,13 +3,18 @@
 // least squares, remove the point with the largest residual, and repeat until
 // the RMSE falls below a threshold (or ten points, the model's size, remain).
 //
-// One workgroup per point set.  Per iteration, in FP64:
-//   1. the 55 + 20 entries of the normal equations (ten monomials of the
-//      normalised source coordinates; both target coordinates) summed over
-//      the kept points (per-thread partials, wave shuffles, LDS);
+// One workgroup per point set; sets of up to 8192 points are held in LDS for
+// the whole loop (coordinates and keep flags), larger ones are read from
+// global memory.  In FP64:
+//   1. once, the 55 + 20 entries of the normal equations (ten monomials of
+//      the normalised source coordinates; both target coordinates) summed
+//      over all points (per-thread partials, wave shuffles, LDS);
+//   per iteration:
 //   2. a Cholesky solve of the 10 x 10 system for both right-hand sides;
 //   3. residuals |model(p) - q| of the kept points, their squared sum and the
-//      largest one (ties to the smaller index).
+//      largest one (ties to the smaller index);
+//   4. removal of that point, whose products are subtracted from the normal
+//      equations (a rank-one downdate, so the sums need not be formed again).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <limits.h>
@@ -17,11 +22,17 @@
 
 namespace cfog {
 
-constexpr int RJ_NT = 256;
+constexpr int RJ_NT = 512;
 constexpr int RJ_NW = RJ_NT / 64;
 constexpr int RJ_T = 10;                   // monomials of a bivariate cubic
 constexpr int RJ_G = RJ_T * (RJ_T + 1) / 2;  // unique entries of the normal matrix
 constexpr int RJ_V = RJ_G + 2 * RJ_T;      // plus the two right-hand sides
+constexpr int RJ_LDS_POINTS = 8192;        // sets up to this size live in LDS
+
+// Dynamic LDS of a set of n points: both coordinate arrays and the flags.
+static size_t reject_lds_bytes(int n) {
+  return n <= RJ_LDS_POINTS ? (size_t)n * (2 * sizeof(float2) + 1) : 0;
+}
 
 __device__ __forceinline__ void cubic_terms(double u, double v, double (&t)[RJ_T]) {
   t[0] = 1.0;
@@ -44,6 +55,7 @@ __device__ __forceinline__ double wave_sum(double x) {
 
 __global__ __launch_bounds__(RJ_NT) void reject_kernel(const float2* __restrict__ src, const float2* __restrict__ dst,
                                                        int n, float thr, unsigned char* keep, cfog_reject_result* out) {
+  extern __shared__ float2 rj_pts[];
   __shared__ double part[RJ_NW][RJ_V];
   __shared__ double sys[RJ_V];
   __shared__ double coef[RJ_T][2];
@@ -52,17 +64,25 @@ __global__ __launch_bounds__(RJ_NT) void reject_kernel(const float2* __restrict_
   __shared__ double ext[4];
   __shared__ int done, active, removed;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const bool resident = n <= RJ_LDS_POINTS;
+  const float2* ps = resident ? rj_pts : src;
+  const float2* pd = resident ? rj_pts + n : dst;
+  unsigned char* pk = resident ? reinterpret_cast<unsigned char*>(rj_pts + 2 * n) : keep;
 
-  // bounding box of all points -> centre and half-extent per axis
+  // points into LDS (resident sets); bounding box -> centre and half-extent per axis
   {
     double mn[2] = {INFINITY, INFINITY}, mx[2] = {-INFINITY, -INFINITY};
     for (int i = tid; i < n; i += RJ_NT) {
       const float2 p = src[i];
+      if (resident) {
+        rj_pts[i] = p;
+        rj_pts[n + i] = dst[i];
+      }
       mn[0] = fmin(mn[0], (double)p.x);
       mn[1] = fmin(mn[1], (double)p.y);
       mx[0] = fmax(mx[0], (double)p.x);
       mx[1] = fmax(mx[1], (double)p.y);
-      keep[i] = 1;
+      pk[i] = 1;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -98,14 +118,13 @@ __global__ __launch_bounds__(RJ_NT) void reject_kernel(const float2* __restrict_
   }
   const double cx = ext[0], cy = ext[1], sx = ext[2], sy = ext[3];
 
-  for (;;) {
-    // 1. normal equations over the kept points
+  // 1. normal equations over all points (every point starts kept)
+  {
     double acc[RJ_V];
 #pragma unroll
     for (int e = 0; e < RJ_V; ++e) acc[e] = 0.0;
     for (int i = tid; i < n; i += RJ_NT) {
-      if (!keep[i]) continue;
-      const float2 p = src[i], q = dst[i];
+      const float2 p = ps[i], q = pd[i];
       double t[RJ_T];
       cubic_terms(((double)p.x - cx) / sx, ((double)p.y - cy) / sy, t);
       int e = 0;
@@ -131,45 +150,52 @@ __global__ __launch_bounds__(RJ_NT) void reject_kernel(const float2* __restrict_
       sys[tid] = v;
     }
     __syncthreads();
-    // 2. Cholesky solve (one thread: 10 x 10)
+  }
+
+  for (;;) {
+    // 2. Cholesky solve (one thread: 10 x 10, every index fixed at compile
+    // time so that the factor stays in registers)
     if (tid == 0) {
+      // entry (a, b), a >= b, of the symmetric matrix held as the packed upper triangle
+      auto A = [&](int a, int b) { return sys[b * RJ_T - b * (b - 1) / 2 + (a - b)]; };
       double L[RJ_T][RJ_T];
-      int e = 0;
-      for (int a = 0; a < RJ_T; ++a)
-        for (int b = a; b < RJ_T; ++b) {
-          L[b][a] = sys[e];
-          L[a][b] = sys[e];
-          ++e;
-        }
       bool ok = true;
-      for (int j = 0; j < RJ_T && ok; ++j) {
-        double d = L[j][j];
+#pragma unroll
+      for (int j = 0; j < RJ_T; ++j) {
+        double d = A(j, j);
+#pragma unroll
         for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
-        if (!(d > 0.0)) {
-          ok = false;
-          break;
-        }
-        L[j][j] = sqrt(d);
+        ok = ok && d > 0.0;
+        const double ljj = sqrt(d > 0.0 ? d : 1.0);
+        L[j][j] = ljj;
+#pragma unroll
         for (int i = j + 1; i < RJ_T; ++i) {
-          double s = L[i][j];
-          for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
-          L[i][j] = s / L[j][j];
+          double t = A(i, j);
+#pragma unroll
+          for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+          L[i][j] = t / ljj;
         }
       }
       if (!ok) {
         done = 2;  // singular normal matrix (degenerate point layout)
       } else {
+#pragma unroll
         for (int c = 0; c < 2; ++c) {
-          double y[RJ_T];
+          double y[RJ_T], x[RJ_T];
+#pragma unroll
           for (int i = 0; i < RJ_T; ++i) {
-            double s = sys[RJ_G + 2 * i + c];
-            for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
-            y[i] = s / L[i][i];
+            double t = sys[RJ_G + 2 * i + c];
+#pragma unroll
+            for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
+            y[i] = t / L[i][i];
           }
+#pragma unroll
           for (int i = RJ_T - 1; i >= 0; --i) {
-            double s = y[i];
-            for (int k = i + 1; k < RJ_T; ++k) s -= L[k][i] * coef[k][c];
-            coef[i][c] = s / L[i][i];
+            double t = y[i];
+#pragma unroll
+            for (int k = i + 1; k < RJ_T; ++k) t -= L[k][i] * x[k];
+            x[i] = t / L[i][i];
+            coef[i][c] = x[i];
           }
         }
       }
@@ -180,8 +206,8 @@ __global__ __launch_bounds__(RJ_NT) void reject_kernel(const float2* __restrict_
     double ss = 0.0, best = -1.0;
     int bi = INT_MAX;
     for (int i = tid; i < n; i += RJ_NT) {
-      if (!keep[i]) continue;
-      const float2 p = src[i], q = dst[i];
+      if (!pk[i]) continue;
+      const float2 p = ps[i], q = pd[i];
       double t[RJ_T];
       cubic_terms(((double)p.x - cx) / sx, ((double)p.y - cy) / sy, t);
       double mxv = 0.0, myv = 0.0;
@@ -231,14 +257,27 @@ __global__ __launch_bounds__(RJ_NT) void reject_kernel(const float2* __restrict_
         done = 1;
         out->rmse = rmse;
       } else {
-        keep[bi] = 0;
+        // 4. remove the point and downdate the normal equations
+        pk[bi] = 0;
         --active;
         ++removed;
+        const float2 p = ps[bi], q = pd[bi];
+        double t[RJ_T];
+        cubic_terms(((double)p.x - cx) / sx, ((double)p.y - cy) / sy, t);
+        int e = 0;
+        for (int a = 0; a < RJ_T; ++a)
+          for (int b = a; b < RJ_T; ++b) sys[e++] -= t[a] * t[b];
+        for (int a = 0; a < RJ_T; ++a) {
+          sys[RJ_G + 2 * a] -= t[a] * (double)q.x;
+          sys[RJ_G + 2 * a + 1] -= t[a] * (double)q.y;
+        }
       }
     }
     __syncthreads();
     if (done) break;
   }
+  if (resident)
+    for (int i = tid; i < n; i += RJ_NT) keep[i] = pk[i];
   if (tid == 0) {
     out->status = done == 1 ? 0 : 1;
     out->removed = removed;
@@ -262,7 +301,14 @@ extern "C" int cfog_reject_outliers(cfog_ctx* ctx, const float* d_src, const flo
   if (!ctx || !d_src || !d_dst || !d_keep || !d_result || n < 10 || n > (1 << 20) || !(threshold >= 0.f) ||
       ((uintptr_t)d_src % 8) != 0 || ((uintptr_t)d_dst % 8) != 0 || ((uintptr_t)d_result % 8) != 0)
     return CFOG_EINVAL;
-  hipLaunchKernelGGL(cfog::reject_kernel, dim3(1), dim3(cfog::RJ_NT), 0, (hipStream_t)stream,
+  static int attr = 1;
+  if (attr == 1)
+    attr = hipFuncSetAttribute((const void*)cfog::reject_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)cfog::reject_lds_bytes(cfog::RJ_LDS_POINTS)) == hipSuccess
+               ? 0
+               : -1;
+  if (attr != 0) return CFOG_EHIP;
+  hipLaunchKernelGGL(cfog::reject_kernel, dim3(1), dim3(cfog::RJ_NT), cfog::reject_lds_bytes(n), (hipStream_t)stream,
                      reinterpret_cast<const float2*>(d_src), reinterpret_cast<const float2*>(d_dst), n, threshold,
                      d_keep, d_result);
   return hipGetLastError() == hipSuccess ? CFOG_OK : CFOG_EHIP;
