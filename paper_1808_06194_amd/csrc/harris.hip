@@ -3,12 +3,14 @@
 // on each cell is read and its k pixels with the largest Harris response
 // become feature points, which are the control points the matcher takes.
 //
-// One workgroup per chip, everything in LDS (two chips per CU):
+// One workgroup per chip, everything in LDS (two chips per CU); lanes map to
+// chip columns and the four waves take every fourth row, so no index is
+// divided; the Gaussian radius is a template parameter (unrolled taps):
 //   1. the chip (clipped to the image);
 //   2. gradients by [-1, 0, 1] with the chip's borders replicated;
-//   3. the structure tensor products gx^2, gx gy, gy^2 smoothed by a
-//      normalised Gaussian (horizontal then vertical pass, chip borders
-//      replicated) and the response R = det - kappa trace^2;
+//   3. the structure tensor products gx^2, gx gy, gy^2 (formed on the fly)
+//      smoothed by a normalised Gaussian (horizontal then vertical pass,
+//      chip borders replicated) and the response R = det - kappa trace^2;
 //   4. k rounds of a workgroup argmax (largest R, ties to the smallest
 //      row-major index), each marking its winner as taken.
 #include <hip/hip_runtime.h>
@@ -27,93 +29,131 @@ constexpr int HR_MAX_K = 64;
 struct HarrisArgs {
   const float* img;
   int64_t stride;
-  int H, W, n, k, chip, R;
+  int H, W, n, k, chip;
   float kappa;
   float w[kMaxGaussRadius + 1];  // w[|j|], j in [-R, R]
   cfog_cp* cps;
   float* resp;
 };
 
-__device__ __forceinline__ int hclamp(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
+constexpr int HR_LD = HR_MAX_CHIP;  // LDS row stride of every chip array
+constexpr int HR_NW = HR_NT / 64;
 
-// Dynamic LDS: five chip-sized arrays (at most 80 KB, so two chips share a
-// CU).  The chip is dead once the gradients exist and shares storage with the
-// first smoothed product; the response reuses gx.
-static size_t harris_lds_bytes(int chip) { return (size_t)5 * chip * chip * sizeof(float); }
+// Dynamic LDS: five 64 x 64 arrays (80 KB, so two chips share a CU).  The
+// chip is dead once the gradients exist and shares storage with the first
+// smoothed product; the response reuses gx.
+static size_t harris_lds_bytes() { return (size_t)5 * HR_LD * HR_LD * sizeof(float); }
 
+template <int R>
 __global__ __launch_bounds__(HR_NT) void harris_grid_kernel(HarrisArgs a) {
   extern __shared__ float hsm[];
-  const int cc = a.chip * a.chip;
+  constexpr int CC = HR_LD * HR_LD;
   float* gx = hsm;
-  float* gy = gx + cc;
-  float* ta = gy + cc;
-  float* tb = ta + cc;
-  float* tc = tb + cc;
+  float* gy = gx + CC;
+  float* ta = gy + CC;
+  float* tb = ta + CC;
+  float* tc = tb + CC;
   float* img = ta;  // read only by the gradient pass
   float* Rv = gx;   // written by the vertical pass, after the last gx read
-  __shared__ float bestv[HR_NT / 64];
-  __shared__ int besti[HR_NT / 64];
+  __shared__ float bestv[HR_NW];
+  __shared__ int besti[HR_NW];
   const int cell = blockIdx.x, ci = cell / a.n, cj = cell - ci * a.n;
   // chip of cell (ci, cj): centred at ((2 cj + 1) W / 2n, (2 ci + 1) H / 2n), clipped
   const int cy = (int)(((int64_t)(2 * ci + 1) * a.H) / (2 * a.n));
   const int cx = (int)(((int64_t)(2 * cj + 1) * a.W) / (2 * a.n));
   const int y0 = max(0, cy - a.chip / 2), x0 = max(0, cx - a.chip / 2);
   const int h = min(a.H, cy - a.chip / 2 + a.chip) - y0, w = min(a.W, cx - a.chip / 2 + a.chip) - x0;
-  const int np = h * w;
-  const int tid = threadIdx.x;
+  const int x = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const bool col = x < w;
+  float wt[R + 1];
+#pragma unroll
+  for (int j = 0; j <= R; ++j) wt[j] = a.w[j];
 
-  for (int i = tid; i < np; i += HR_NT) {
-    const int y = i / w, x = i - y * w;
-    img[i] = a.img[(int64_t)(y0 + y) * a.stride + x0 + x];
-  }
-  __syncthreads();
-  for (int i = tid; i < np; i += HR_NT) {
-    const int y = i / w, x = i - y * w;
-    const float* row = img + y * w;
-    gx[i] = row[hclamp(x + 1, w - 1)] - row[hclamp(x - 1, w - 1)];
-    gy[i] = img[hclamp(y + 1, h - 1) * w + x] - img[hclamp(y - 1, h - 1) * w + x];
-  }
-  __syncthreads();
-  const int R = a.R;
-  for (int i = tid; i < np; i += HR_NT) {
-    const int y = i / w, x = i - y * w;
-    float sa = 0.f, sb = 0.f, sc = 0.f;
-    for (int j = -R; j <= R; ++j) {
-      const int q = y * w + hclamp(x + j, w - 1);
-      const float wj = a.w[j < 0 ? -j : j];
-      sa = fmaf(wj, gx[q] * gx[q], sa);
-      sb = fmaf(wj, gx[q] * gy[q], sb);
-      sc = fmaf(wj, gy[q] * gy[q], sc);
+  constexpr int RPW = HR_LD / HR_NW;  // rows per wave (the row loops below are unrolled over them)
+  {
+    // all loads of the chip issued before the first LDS store
+    float v[RPW];
+    const float* src = a.img + (int64_t)y0 * a.stride + x0 + x;
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+      const int y = wv + HR_NW * t;
+      if (col && y < h) v[t] = src[(int64_t)y * a.stride];
     }
-    ta[i] = sa;
-    tb[i] = sb;
-    tc[i] = sc;
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+      const int y = wv + HR_NW * t;
+      if (col && y < h) img[y * HR_LD + x] = v[t];
+    }
   }
   __syncthreads();
-  for (int i = tid; i < np; i += HR_NT) {
-    const int y = i / w, x = i - y * w;
-    float sa = 0.f, sb = 0.f, sc = 0.f;
-    for (int j = -R; j <= R; ++j) {
-      const int q = hclamp(y + j, h - 1) * w + x;
-      const float wj = a.w[j < 0 ? -j : j];
-      sa = fmaf(wj, ta[q], sa);
-      sb = fmaf(wj, tb[q], sb);
-      sc = fmaf(wj, tc[q], sc);
+  const int xp = min(x + 1, w - 1), xm = max(x - 1, 0);
+#pragma unroll
+  for (int t = 0; t < RPW; ++t) {
+    const int y = wv + HR_NW * t;
+    if (col && y < h) {
+      const float* row = img + y * HR_LD;
+      gx[y * HR_LD + x] = row[xp] - row[xm];
+      gy[y * HR_LD + x] = img[min(y + 1, h - 1) * HR_LD + x] - img[max(y - 1, 0) * HR_LD + x];
     }
-    const float tr = sa + sc;
-    Rv[i] = sa * sc - sb * sb - a.kappa * tr * tr;
+  }
+  __syncthreads();
+  // horizontal pass of the three products (columns clamped to the chip)
+  int xs[2 * R + 1];
+#pragma unroll
+  for (int j = -R; j <= R; ++j) xs[j + R] = min(max(x + j, 0), w - 1);
+#pragma unroll
+  for (int t = 0; t < RPW; ++t) {
+    const int y = wv + HR_NW * t;
+    if (col && y < h) {
+      const float* rx = gx + y * HR_LD;
+      const float* ry = gy + y * HR_LD;
+      float sa = 0.f, sb = 0.f, sc = 0.f;
+#pragma unroll
+      for (int j = -R; j <= R; ++j) {
+        const float u = rx[xs[j + R]], v = ry[xs[j + R]], wj = wt[j < 0 ? -j : j];
+        sa = fmaf(wj, u * u, sa);
+        sb = fmaf(wj, u * v, sb);
+        sc = fmaf(wj, v * v, sc);
+      }
+      ta[y * HR_LD + x] = sa;
+      tb[y * HR_LD + x] = sb;
+      tc[y * HR_LD + x] = sc;
+    }
+  }
+  __syncthreads();
+  // vertical pass (rows clamped to the chip) and the response
+#pragma unroll
+  for (int t = 0; t < RPW; ++t) {
+    const int y = wv + HR_NW * t;
+    if (col && y < h) {
+      float sa = 0.f, sb = 0.f, sc = 0.f;
+#pragma unroll
+      for (int j = -R; j <= R; ++j) {
+        const int q = min(max(y + j, 0), h - 1) * HR_LD + x;
+        const float wj = wt[j < 0 ? -j : j];
+        sa = fmaf(wj, ta[q], sa);
+        sb = fmaf(wj, tb[q], sb);
+        sc = fmaf(wj, tc[q], sc);
+      }
+      const float tr = sa + sc;
+      Rv[y * HR_LD + x] = sa * sc - sb * sb - a.kappa * tr * tr;
+    }
   }
   __syncthreads();
 
-  const int lane = tid & 63, wv = tid >> 6;
+  const int lane = x;
   for (int q = 0; q < a.k; ++q) {
     float bv = -INFINITY;
     int bi = INT_MAX;
-    for (int i = tid; i < np; i += HR_NT) {
-      const float v = Rv[i];
-      if (v > bv || (v == bv && i < bi)) {  // taken pixels hold NaN and never win
-        bv = v;
-        bi = i;
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {  // increasing row-major index per thread
+      const int y = wv + HR_NW * t;
+      if (col && y < h) {
+        const float v = Rv[y * HR_LD + x];
+        if (v > bv) {  // taken pixels hold NaN and never win
+          bv = v;
+          bi = y * w + x;
+        }
       }
     }
 #pragma unroll
@@ -130,18 +170,18 @@ __global__ __launch_bounds__(HR_NT) void harris_grid_kernel(HarrisArgs a) {
       besti[wv] = bi;
     }
     __syncthreads();
-    if (tid == 0) {
-      for (int u = 1; u < HR_NT / 64; ++u)
+    if (threadIdx.x == 0) {
+      for (int u = 1; u < HR_NW; ++u)
         if (bestv[u] > bv || (bestv[u] == bv && besti[u] < bi)) {
           bv = bestv[u];
           bi = besti[u];
         }
       const int o = cell * a.k + q;
       if (bi != INT_MAX) {
-        const int y = bi / w, x = bi - y * w;
-        a.cps[o] = cfog_cp{x0 + x, y0 + y, x0 + x, y0 + y};
+        const int yy = bi / w, xx = bi - yy * w;
+        a.cps[o] = cfog_cp{x0 + xx, y0 + yy, x0 + xx, y0 + yy};
         if (a.resp) a.resp[o] = bv;
-        Rv[bi] = NAN;
+        Rv[yy * HR_LD + xx] = NAN;
       } else {  // no finite response left (a non-finite chip)
         a.cps[o] = cfog_cp{-1, -1, -1, -1};
         if (a.resp) a.resp[o] = NAN;
@@ -149,6 +189,19 @@ __global__ __launch_bounds__(HR_NT) void harris_grid_kernel(HarrisArgs a) {
     }
     __syncthreads();
   }
+}
+
+template <int R>
+static int launch_harris(const HarrisArgs& a, hipStream_t st) {
+  static int attr = 1;
+  if (attr == 1)
+    attr = hipFuncSetAttribute((const void*)harris_grid_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)harris_lds_bytes()) == hipSuccess
+               ? 0
+               : -1;
+  if (attr != 0) return -2;
+  hipLaunchKernelGGL(harris_grid_kernel<R>, dim3(a.n * a.n), dim3(HR_NT), harris_lds_bytes(), st, a);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 }  // namespace cfog
@@ -181,7 +234,6 @@ extern "C" int cfog_harris_grid(cfog_ctx* ctx, const float* d_img, int32_t H, in
   a.n = n;
   a.k = k;
   a.chip = chip;
-  a.R = R;
   a.kappa = kappa;
   double ws[cfog::kMaxGaussRadius + 1], tot = 0.0;
   for (int j = 0; j <= R; ++j) {
@@ -191,15 +243,19 @@ extern "C" int cfog_harris_grid(cfog_ctx* ctx, const float* d_img, int32_t H, in
   for (int j = 0; j <= R; ++j) a.w[j] = (float)(ws[j] / tot);
   a.cps = d_cps;
   a.resp = d_response;
-  static int attr = 1;
-  if (attr == 1)
-    attr = hipFuncSetAttribute((const void*)cfog::harris_grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)cfog::harris_lds_bytes(cfog::HR_MAX_CHIP)) == hipSuccess
-               ? 0
-               : -1;
-  if (attr != 0) return CFOG_EHIP;
-  hipLaunchKernelGGL(cfog::harris_grid_kernel, dim3(n * n), dim3(cfog::HR_NT), cfog::harris_lds_bytes(chip),
-                     (hipStream_t)stream, a);
-  if (hipGetLastError() != hipSuccess) return CFOG_EHIP;
-  return CFOG_OK;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = -2;
+  switch (R) {
+    case 0: rc = cfog::launch_harris<0>(a, st); break;
+    case 1: rc = cfog::launch_harris<1>(a, st); break;
+    case 2: rc = cfog::launch_harris<2>(a, st); break;
+    case 3: rc = cfog::launch_harris<3>(a, st); break;
+    case 4: rc = cfog::launch_harris<4>(a, st); break;
+    case 5: rc = cfog::launch_harris<5>(a, st); break;
+    case 6: rc = cfog::launch_harris<6>(a, st); break;
+    case 7: rc = cfog::launch_harris<7>(a, st); break;
+    case 8: rc = cfog::launch_harris<8>(a, st); break;
+    default: return CFOG_EUNSUPPORTED;
+  }
+  return rc == 0 ? CFOG_OK : CFOG_EHIP;
 }
