@@ -93,22 +93,39 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const float* __restr
                                           int ncols, float2* X, const float2* tw) {
   constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH;
   const int nrp = (nrows + 1) >> 1;
+  // the two rows of pair q, zero-padded, packed as one complex row
+  auto load = [&](int q, float2 (&v)[R1]) {
+    const int j = L.li;
+    const float* r0 = src + (int64_t)(2 * q) * ld;
+    const bool has1 = (2 * q + 1) < nrows;
+#pragma unroll
+    for (int a = 0; a < R1; ++a) {
+      const int xx = j + R2 * a;
+      float re = 0.f, im = 0.f;
+      if (xx < ncols) {
+        re = r0[xx];
+        if (has1) im = r0[ld + xx];
+      }
+      v[a] = make_float2(re, im);
+    }
+  };
+  // the large plans (one workgroup per CU) fetch the next pair while
+  // transforming this one (measured: 3% at P = 144, 1-2% at P = 120 and 192;
+  // the 768-thread P = 100 plan loses by it)
+  constexpr bool PF = P >= 120;
+  float2 vn[R1];
+  if (PF && L.g < nrp && L.li < R2) load(L.g, vn);
   for (int q = L.g; q < nrp; q += C::NG) {
     float2* base = X + 2 * opaque(q) * PH;
     if (L.li < R2) {
       const int j = L.li;
-      const float* r0 = src + (int64_t)(2 * q) * ld;
-      const bool has1 = (2 * q + 1) < nrows;
       float2 v[R1];
+      if constexpr (PF) {
 #pragma unroll
-      for (int a = 0; a < R1; ++a) {
-        const int xx = j + R2 * a;
-        float re = 0.f, im = 0.f;
-        if (xx < ncols) {
-          re = r0[xx];
-          if (has1) im = r0[ld + xx];
-        }
-        v[a] = make_float2(re, im);
+        for (int a = 0; a < R1; ++a) v[a] = vn[a];
+        if (q + C::NG < nrp) load(q + C::NG, vn);
+      } else {
+        load(q, v);
       }
       dft<R1, -1>(v);
 #pragma unroll
