@@ -45,7 +45,7 @@ size_t extract_workspace_bytes(int H, int W);
 // FFT matcher plans: FFT side P = R1 * R2, NT threads per workgroup; plans
 // with tg_bytes > 0 park the template spectrum of the current channel in a
 // per-workgroup global workspace of that size.
-struct FftPlan { int P, R1, R2, NT; size_t lds; size_t tg_bytes; };
+struct FftPlan { int P, R1, R2, NT; size_t lds; size_t tg_bytes; int t_rows; /* template rows it takes */ };
 const FftPlan* fft_plans(int* count);
 // Smallest supported plan with P >= Ws whose LDS scratch also fits the
 // inverse row pass for K = 2r + 1; nullptr if none.

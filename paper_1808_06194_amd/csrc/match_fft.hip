@@ -57,10 +57,15 @@ __device__ __forceinline__ int opaque(int v) {
   return v;
 }
 
-template <int P_, int R1_, int R2_, int NT_, bool TG_>
+// Channel layouts of a plan: T^ parked in registers between the template's
+// and the window's passes (LAY_REG), both row spectra side by side in LDS
+// (LAY_FUSED), or T^ parked in a global workspace (LAY_GLOBAL).
+enum : int { LAY_REG = 0, LAY_FUSED = 1, LAY_GLOBAL = 2 };
+
+template <int P_, int R1_, int R2_, int NT_, int LAY_>
 struct FftCfg {
   static constexpr int P = P_, R1 = R1_, R2 = R2_, NT = NT_;
-  static constexpr bool TG = TG_;  // T^ parked in a global workspace
+  static constexpr bool TG = LAY_ == LAY_GLOBAL;  // T^ parked in a global workspace
   static_assert(P == R1 * R2, "P must equal R1 * R2");
   static_assert(NT % 64 == 0 && NT <= 1024, "bad workgroup size");
   static constexpr int PH = P / 2 + 1;
@@ -69,7 +74,17 @@ struct FftCfg {
   static constexpr int NW = NT / 64;
   static constexpr int NG = NW * GPW;          // groups per workgroup
   static constexpr int KF = (PH + NG - 1) / NG;  // column rounds per group
-  static constexpr size_t LDS = sizeof(float2) * ((size_t)P * PH + P) + NW * 16;
+  static constexpr size_t BASE = sizeof(float2) * ((size_t)P * PH + P) + NW * 16;
+  // Fused layout (plans with one workgroup per CU): the row spectra of the
+  // template (XT, up to XT_ROWS rows) and of the window (X, P rows) side by
+  // side, so both x-passes share one phase and each y-pass column transforms
+  // S then T: two barriers per channel instead of four, no T^ registers.
+  // Templates of more rows than XT_ROWS take a larger plan.
+  static constexpr bool FUSE = LAY_ == LAY_FUSED;
+  static constexpr size_t XT_FIT = (kMaxLds - BASE) / (sizeof(float2) * PH) / 2 * 2;
+  static constexpr int XT_ROWS = FUSE ? (int)(XT_FIT < (size_t)P ? XT_FIT : (size_t)P) : 0;
+  static constexpr int T_ROWS = FUSE ? XT_ROWS : P;  // template rows the plan takes
+  static constexpr size_t LDS = BASE + sizeof(float2) * (size_t)XT_ROWS * PH;
   static constexpr size_t TG_BYTES = TG ? sizeof(float2) * (size_t)P * PH : 0;
 };
 
@@ -85,26 +100,45 @@ struct Lane {
   }
 };
 
-// x-pass: forward FFT of nrows x ncols real rows (src, leading dim ld),
-// zero-padded to P, two rows per complex FFT; leaves the half-spectra of the
-// rows in X as [row][kx], kx in [0, P/2], row stride PH.
-template <class C>
-__device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const float* __restrict__ src, int64_t ld, int nrows,
-                                          int ncols, float2* X, const float2* tw) {
+// One set of rows for the x-pass: nrows x ncols real values at src (leading
+// dim ld), transformed into X (row stride PH).  zero_tail: rows
+// [2 ceil(nrows/2), P) of X are zeroed (a y-pass that reads all P rows).
+struct XRows {
+  const float* src;
+  int64_t ld;
+  int nrows, ncols;
+  float2* X;
+  bool zero_tail;
+};
+
+// x-pass: forward FFTs of the rows of NS sets (the pairs of set 0, then those
+// of set 1), zero-padded to P, two rows per complex FFT; leaves the
+// half-spectra of the rows in each set's X as [row][kx], kx in [0, P/2].
+template <class C, int NS>
+__device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const XRows (&S)[NS], const float2* tw) {
   constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH;
-  const int nrp = (nrows + 1) >> 1;
-  // the two rows of pair q, zero-padded, packed as one complex row
-  auto load = [&](int q, float2 (&v)[R1]) {
+  const int nrp0 = (S[0].nrows + 1) >> 1;
+  const int total = NS > 1 ? nrp0 + ((S[NS - 1].nrows + 1) >> 1) : nrp0;
+  // item i -> (set, pair)
+  auto which = [&](int i, int& s, int& q) {
+    s = (NS > 1 && i >= nrp0) ? 1 : 0;
+    q = s ? i - nrp0 : i;
+  };
+  // the two rows of a pair, zero-padded, packed as one complex row
+  auto load = [&](int i, float2 (&v)[R1]) {
+    int s, q;
+    which(i, s, q);
+    const XRows& R = S[NS > 1 ? s : 0];
     const int j = L.li;
-    const float* r0 = src + (int64_t)(2 * q) * ld;
-    const bool has1 = (2 * q + 1) < nrows;
+    const float* r0 = R.src + (int64_t)(2 * q) * R.ld;
+    const bool has1 = (2 * q + 1) < R.nrows;
 #pragma unroll
     for (int a = 0; a < R1; ++a) {
       const int xx = j + R2 * a;
       float re = 0.f, im = 0.f;
-      if (xx < ncols) {
+      if (xx < R.ncols) {
         re = r0[xx];
-        if (has1) im = r0[ld + xx];
+        if (has1) im = r0[R.ld + xx];
       }
       v[a] = make_float2(re, im);
     }
@@ -114,18 +148,21 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const float* __restr
   // the 768-thread P = 100 plan loses by it)
   constexpr bool PF = P >= 120;
   float2 vn[R1];
-  if (PF && L.g < nrp && L.li < R2) load(L.g, vn);
-  for (int q = L.g; q < nrp; q += C::NG) {
-    float2* base = X + 2 * opaque(q) * PH;
+  if (PF && L.g < total && L.li < R2) load(L.g, vn);
+  for (int i = L.g; i < total; i += C::NG) {
+    int s, q;
+    which(i, s, q);
+    const XRows& R = S[NS > 1 ? s : 0];
+    float2* base = R.X + 2 * opaque(q) * PH;
     if (L.li < R2) {
       const int j = L.li;
       float2 v[R1];
       if constexpr (PF) {
 #pragma unroll
         for (int a = 0; a < R1; ++a) v[a] = vn[a];
-        if (q + C::NG < nrp) load(q + C::NG, vn);
+        if (i + C::NG < total) load(i + C::NG, vn);
       } else {
-        load(q, v);
+        load(i, v);
       }
       dft<R1, -1>(v);
 #pragma unroll
@@ -145,7 +182,7 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const float* __restr
     // lane R1-k1 of the group (k1 > 0), or this lane's register (R2-k2) mod R2 (k1 = 0).
     const int lane = threadIdx.x & 63;
     const int msrc = lane - L.li + (k1 == 0 ? 0 : R1 - k1);
-    const bool odd_pad = (2 * q + 1) >= nrows;  // second row of the pair is padding
+    const bool odd_pad = (2 * q + 1) >= R.nrows;  // second row of the pair is padding
     static_for<0, R2>([&](auto k2I) {
       constexpr int k2 = decltype(k2I)::value;
       const float2 far = make_float2(__shfl(v[R2 - 1 - k2].x, msrc, 64), __shfl(v[R2 - 1 - k2].y, msrc, 64));
@@ -160,8 +197,76 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const float* __restr
     wave_sync();
   }
   // rows [2 nrp, P) of the half-spectrum are zero padding (an odd last row is
-  // zeroed by its pair above): the y-pass reads all P rows unconditionally
-  for (int i = threadIdx.x; i < (P - 2 * nrp) * PH; i += C::NT) X[2 * nrp * PH + i] = make_float2(0.f, 0.f);
+  // zeroed by its pair above)
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (!S[s].zero_tail) continue;
+    const int r0 = 2 * ((S[s].nrows + 1) >> 1);
+    for (int t = threadIdx.x; t < (P - r0) * PH; t += C::NT) S[s].X[r0 * PH + t] = make_float2(0.f, 0.f);
+  }
+}
+
+// y-pass of the fused layout.  For each column kx of the group: the window's
+// column FFT in place in X (all P rows), then the template's, whose first
+// stage reads XT (rows < nT, zero beyond) and writes its intermediate into the
+// X column the window's transform has just left; conj(T^) S^ is accumulated
+// into acc[rnd][k2] for ky = k1 + R1 k2.
+template <class C>
+__device__ __forceinline__ void ypass_fused(const Lane<C>& L, const float2* XT, int nT, float2* X, const float2* tw,
+                                            float2 (&acc)[C::KF][C::R2]) {
+  constexpr int R1 = C::R1, R2 = C::R2, PH = C::PH;
+  static_for<0, C::KF>([&](auto rndI) {
+    constexpr int rnd = decltype(rndI)::value;
+    const int kx = L.g + rnd * C::NG;
+    if (kx < PH) {
+      float2* col = X + opaque(kx);
+      const float2* colT = XT + kx;
+      float2 sh[R2];
+      // window: stage 1 in place, stage 2 into registers
+      if (L.li < R2) {
+        const int j = L.li;
+        float2 v[R1];
+#pragma unroll
+        for (int a = 0; a < R1; ++a) v[a] = col[(j + R2 * a) * PH];
+        dft<R1, -1>(v);
+#pragma unroll
+        for (int k = 0; k < R1; ++k) col[(j * R1 + k) * PH] = v[k];
+      }
+      wave_sync();
+      if (L.li < R1) {
+        const int k1 = L.li;
+        sh[0] = col[k1 * PH];
+#pragma unroll
+        for (int b = 1; b < R2; ++b) sh[b] = cmul(col[(k1 + R1 * b) * PH], tw[b * R1 + k1]);
+        dft<R2, -1>(sh);
+      }
+      wave_sync();
+      // template: stage 1 from XT into the X column, stage 2 into registers
+      if (L.li < R2) {
+        const int j = L.li;
+        float2 v[R1];
+#pragma unroll
+        for (int a = 0; a < R1; ++a) {
+          const int row = j + R2 * a;
+          v[a] = row < nT ? colT[row * PH] : make_float2(0.f, 0.f);
+        }
+        dft<R1, -1>(v);
+#pragma unroll
+        for (int k = 0; k < R1; ++k) col[(j * R1 + k) * PH] = v[k];
+      }
+      wave_sync();
+      if (L.li < R1) {
+        const int k1 = L.li;
+        float2 w[R2];
+        w[0] = col[k1 * PH];
+#pragma unroll
+        for (int b = 1; b < R2; ++b) w[b] = cmul(col[(k1 + R1 * b) * PH], tw[b * R1 + k1]);
+        dft<R2, -1>(w);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) acc[rnd][k2] = cmac_conj(acc[rnd][k2], w[k2], sh[k2]);
+      }
+    }
+  });
 }
 
 // y-pass: forward column FFTs of the half-spectrum (rows >= nrows were zeroed
@@ -231,27 +336,47 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   const size_t planeA = (size_t)jd.hA * jd.wA, planeB = (size_t)jd.hB * jd.wB;
   const float* tA = jd.volA + (size_t)ty0 * jd.wA + tx0;
   const float* sB = jd.volB + (size_t)sy0 * jd.wB + sx0;
-  for (int c = c0; c < c1; ++c) {
-    float2 th[C::TG ? 1 : KF][R2];
-    __syncthreads();  // previous readers of X are done
-    xpass_fwd<C>(L, tA + c * planeA, jd.wA, N, N, X, tw);
-    __syncthreads();
-    ypass_fwd<C>(L, X, tw, [&](auto rndI, auto k2I, int kx, float2 v) {
-      constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
-      if constexpr (C::TG) tg[(size_t)kx * P + L.li + R1 * k2] = v;
-      else th[rnd][k2] = v;
-    });
-    __syncthreads();
-    xpass_fwd<C>(L, sB + c * planeB, jd.wB, Ws, Ws, X, tw);
-    __syncthreads();
-    ypass_fwd<C>(L, X, tw, [&](auto rndI, auto k2I, int kx, float2 v) {
-      constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
-      float2 t;
-      if constexpr (C::TG) t = tg[(size_t)kx * P + L.li + R1 * k2];
-      else t = th[rnd][k2];
-      acc[rnd][k2] = cmac_conj(acc[rnd][k2], t, v);
-    });
-  }
+  // fused layout: both x-passes in one phase (template rows into XT, window
+  // rows into X), then one y-pass phase; two barriers per channel
+  auto fused_channels = [&]() {
+    float2* XT = reinterpret_cast<float2*>(reinterpret_cast<char*>(X) + C::BASE);
+    for (int c = c0; c < c1; ++c) {
+      __syncthreads();  // previous readers of X and XT are done
+      const XRows rows[2] = {{tA + c * planeA, jd.wA, N, N, XT, false}, {sB + c * planeB, jd.wB, Ws, Ws, X, true}};
+      xpass_fwd<C, 2>(L, rows, tw);
+      __syncthreads();
+      ypass_fused<C>(L, XT, N, X, tw, acc);
+    }
+  };
+  // two-phase layout: T^ parked in registers (or global memory) between the
+  // template's and the window's passes; four barriers per channel
+  auto split_channels = [&]() {
+    for (int c = c0; c < c1; ++c) {
+      float2 th[C::TG ? 1 : KF][R2];
+      __syncthreads();  // previous readers of X are done
+      const XRows rt[1] = {{tA + c * planeA, jd.wA, N, N, X, true}};
+      xpass_fwd<C, 1>(L, rt, tw);
+      __syncthreads();
+      ypass_fwd<C>(L, X, tw, [&](auto rndI, auto k2I, int kx, float2 v) {
+        constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
+        if constexpr (C::TG) tg[(size_t)kx * P + L.li + R1 * k2] = v;
+        else th[rnd][k2] = v;
+      });
+      __syncthreads();
+      const XRows rs[1] = {{sB + c * planeB, jd.wB, Ws, Ws, X, true}};
+      xpass_fwd<C, 1>(L, rs, tw);
+      __syncthreads();
+      ypass_fwd<C>(L, X, tw, [&](auto rndI, auto k2I, int kx, float2 v) {
+        constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
+        float2 t;
+        if constexpr (C::TG) t = tg[(size_t)kx * P + L.li + R1 * k2];
+        else t = th[rnd][k2];
+        acc[rnd][k2] = cmac_conj(acc[rnd][k2], t, v);
+      });
+    }
+  };
+  if constexpr (C::FUSE) fused_channels();  // N <= XT_ROWS (plan_fits)
+  else split_channels();
 
   // ---- inverse along y: each group transforms its own columns in place and
   // keeps the rows u_y < K (no workgroup barrier: a column is group-private).
@@ -395,38 +520,41 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
 }
 
 // ------------------------------------------------------------------ plans
-//  P, R1, R2, NT, TG  (R1 >= R2 keeps the per-lane outputs of stage 2 small).
-//  NT is set per size from measurement: as many waves as the registers allow
-//  without starving the column rounds (P = 96..108 at 768 threads take every
-//  column in one round; P >= 128 at 512 threads beat 256-384 threads despite
-//  some register spilling at P >= 180); the largest sizes park T^ in global
-//  memory.
-#define CFOG_PLANS(X)            \
-  X(16, 4, 4, 64, false)         \
-  X(24, 6, 4, 128, false)        \
-  X(32, 8, 4, 192, false)        \
-  X(40, 8, 5, 192, false)        \
-  X(48, 8, 6, 256, false)        \
-  X(60, 10, 6, 384, false)       \
-  X(64, 8, 8, 320, false)        \
-  X(72, 9, 8, 384, false)        \
-  X(80, 10, 8, 448, false)       \
-  X(90, 10, 9, 512, false)       \
-  X(96, 12, 8, 768, false)       \
-  X(100, 10, 10, 768, false)     \
-  X(108, 12, 9, 768, false)      \
-  X(120, 12, 10, 512, false)     \
-  X(128, 16, 8, 512, false)      \
-  X(144, 12, 12, 512, false)     \
-  X(160, 16, 10, 512, true)      \
-  X(180, 15, 12, 512, true)      \
-  X(192, 16, 12, 512, true)
+//  P, R1, R2, NT, layout  (R1 >= R2 keeps the per-lane outputs of stage 2
+//  small).  NT is set per size from measurement: as many waves as the
+//  registers allow without starving the column rounds (P = 96..108 at 768
+//  threads take every column in one round; P >= 128 at 512 threads beat
+//  256-384 threads despite some register spilling at P >= 180).  The layout
+//  too: the fused one was 6-18% faster than parking T^ in registers for
+//  P = 80..144 except P = 128 (2.5% slower, more spills); the largest sizes
+//  park T^ in global memory.
+#define CFOG_PLANS(X)                  \
+  X(16, 4, 4, 64, LAY_REG)             \
+  X(24, 6, 4, 128, LAY_REG)            \
+  X(32, 8, 4, 192, LAY_REG)            \
+  X(40, 8, 5, 192, LAY_REG)            \
+  X(48, 8, 6, 256, LAY_REG)            \
+  X(60, 10, 6, 384, LAY_REG)           \
+  X(64, 8, 8, 320, LAY_REG)            \
+  X(72, 9, 8, 384, LAY_REG)            \
+  X(80, 10, 8, 448, LAY_FUSED)         \
+  X(90, 10, 9, 512, LAY_FUSED)         \
+  X(96, 12, 8, 768, LAY_FUSED)         \
+  X(100, 10, 10, 768, LAY_FUSED)       \
+  X(108, 12, 9, 768, LAY_FUSED)        \
+  X(120, 12, 10, 512, LAY_FUSED)       \
+  X(128, 16, 8, 512, LAY_REG)          \
+  X(144, 12, 12, 512, LAY_FUSED)       \
+  X(160, 16, 10, 512, LAY_GLOBAL)      \
+  X(180, 15, 12, 512, LAY_GLOBAL)      \
+  X(192, 16, 12, 512, LAY_GLOBAL)
 
 #define CFOG_CFG(P_, R1_, R2_, NT_, TG_) FftCfg<P_, R1_, R2_, NT_, TG_>
 
 static const FftPlan kPlans[] = {
-#define CFOG_PLAN_ENTRY(P_, R1_, R2_, NT_, TG_) \
-  {P_, R1_, R2_, NT_, CFOG_CFG(P_, R1_, R2_, NT_, TG_)::LDS, CFOG_CFG(P_, R1_, R2_, NT_, TG_)::TG_BYTES},
+#define CFOG_PLAN_ENTRY(P_, R1_, R2_, NT_, TG_)                                                  \
+  {P_, R1_, R2_, NT_, CFOG_CFG(P_, R1_, R2_, NT_, TG_)::LDS, CFOG_CFG(P_, R1_, R2_, NT_, TG_)::TG_BYTES, \
+   CFOG_CFG(P_, R1_, R2_, NT_, TG_)::T_ROWS},
     CFOG_PLANS(CFOG_PLAN_ENTRY)
 #undef CFOG_PLAN_ENTRY
 };
@@ -438,7 +566,7 @@ const FftPlan* fft_plans(int* count) {
 
 bool plan_fits(const FftPlan* p, int N, int r) {
   const int Ws = N + 2 * r, K = 2 * r + 1;
-  if (p->P < Ws) return false;
+  if (p->P < Ws || N > p->t_rows) return false;
   const int PH = p->P / 2 + 1;
   // inverse row scratch and the K x K correlation behind it must fit in LDS
   return 2L * ((long)(K + 1) / 2 * p->P) + (long)K * K <= 2L * (long)(p->P - K) * PH;
