@@ -18,9 +18,11 @@
 //   x-pass: rows of T_c (or S_c), two real rows packed per complex FFT, the
 //           two half-spectra separated via Z(k) and conj Z(-k);
 //   y-pass: complex column FFTs of the half-spectrum kx in [0, P/2];
-//   ACC(ky, kx) += conj(T^_c) * S^_c  in registers (T^_c is parked in
-//           registers, or for the largest P in a global workspace, between the
-//           T and S passes of the channel);
+//   ACC(ky, kx) += conj(T^_c) * S^_c  in registers.  Per plan layout: the
+//           row spectra of T_c and S_c side by side in LDS, both x-passes in
+//           one phase and each y-pass column transforming S then T (fused);
+//           or T^_c parked in registers (or, for the largest P, in a global
+//           workspace) between the T and S passes of the channel;
 // then one inverse: column IFFTs (kept rows u_y < K) and a C2R row IFFT with
 // two output rows packed per complex FFT (kept columns u_x < K), the SSD
 // assembly in FP64, and a lexicographic argmin + second-best over (SSD, index).
@@ -31,7 +33,8 @@
 //   stage 2 (lane k1 < R1): X[k1 + R1 k2] = sum_j W_P^{k1 j} t[j R1 + k1] W_R2^{j k2}
 // with the small DFTs as unrolled register codelets (dft.hpp) and the
 // exchange between stages through the FFT's own LDS rows or column.  Only the
-// x -> y transposes need workgroup barriers (4 per channel).
+// x -> y transposes need workgroup barriers (2 per channel in the fused
+// layout, 4 otherwise).
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <algorithm>
