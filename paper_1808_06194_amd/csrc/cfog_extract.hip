@@ -373,9 +373,13 @@ template <int C>
 struct FhTile {
   static constexpr int IW = EX_TX + 2 * C + 2, IH = EX_TY + 2 * C + 2;  // image tile (+1 for the gradient)
   static constexpr int GW = EX_TX + 2 * C, GH = EX_TY + 2 * C;          // gradient / channel tile
-  static constexpr size_t IMG = ((size_t)IH * IW + 1) / 2 * 2;          // floats
+  static constexpr size_t IMG = ((size_t)IH * IW + 3) / 4 * 4;          // floats (keeps G 16-byte aligned)
   static constexpr size_t MB = (size_t)GH * GW;                         // float2 (|g|, bin position)
-  static constexpr size_t G = (size_t)GH * GW;                          // floats
+  static constexpr int NQ = (4 + 2 * C + 3) / 4;  // 16-byte reads per 4 horizontal outputs
+  // channel row stride: a multiple of 4 floats covering the last quad's reads
+  static constexpr int GWP = ((GW + 3) / 4 * 4) > (EX_TX - 4 + 4 * NQ) ? ((GW + 3) / 4 * 4) : (EX_TX - 4 + 4 * NQ);
+  static constexpr int NQUAD = GH * EX_TX / 4;  // horizontal outputs four at a time
+  static constexpr size_t G = (size_t)GH * GWP;                         // floats
   static constexpr size_t HX = 2 * (size_t)GH * EX_TX;                  // floats: both horizontal passes
   static constexpr size_t BYTES = 4 * IMG + 8 * MB + 4 * G + 4 * HX + 8 * 4 * 64;
 };
@@ -438,22 +442,45 @@ __global__ __launch_bounds__(EX_NT) void fhog_kernel(FhogArgs a) {
 #pragma unroll
   for (int k = 0; k < FH_BINS; ++k) {
     for (int i = tid; i < GH * GW; i += EX_NT) {
+      const int r = i / GW, c = i - r * GW;
       const float2 g = mb[i];
       const float d = fabsf(g.y - (float)k);
-      G[i] = g.x * fmaxf(0.f, 1.f - fminf(d, (float)FH_BINS - d));
+      G[r * T::GWP + c] = g.x * fmaxf(0.f, 1.f - fminf(d, (float)FH_BINS - d));
     }
     __syncthreads();
-    for (int i = tid; i < GH * EX_TX; i += EX_NT) {
-      const int r = i / EX_TX, c = i - r * EX_TX;
-      const float* row = G + r * GW + c + C;
-      float s0 = 0.f, s1 = 0.f;
+    // both horizontal cell passes, four consecutive outputs per thread from
+    // 16-byte reads (16 threads cover a row); the padding columns of G feed
+    // no output
 #pragma unroll
-      for (int d = -C; d <= C; ++d) {
-        s0 = fmaf(fh_w<C>(d, 0), row[d], s0);
-        s1 = fmaf(fh_w<C>(d, 1), row[d], s1);
+    for (int it = 0; it < (T::NQUAD + EX_NT - 1) / EX_NT; ++it) {
+      const int qd = tid + it * EX_NT;
+      if (T::NQUAD % EX_NT == 0 || qd < T::NQUAD) {
+        const int r = qd >> 4, c4 = (qd & 15) * 4;
+        const float4* src = reinterpret_cast<const float4*>(G + r * T::GWP + c4);
+        float x[4 * T::NQ];
+#pragma unroll
+        for (int u = 0; u < T::NQ; ++u) {
+          const float4 t = src[u];
+          x[4 * u] = t.x;
+          x[4 * u + 1] = t.y;
+          x[4 * u + 2] = t.z;
+          x[4 * u + 3] = t.w;
+        }
+        float o0[4], o1[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+          for (int d = -C; d <= C; ++d) {
+            s0 = fmaf(fh_w<C>(d, 0), x[j + C + d], s0);
+            s1 = fmaf(fh_w<C>(d, 1), x[j + C + d], s1);
+          }
+          o0[j] = s0;
+          o1[j] = s1;
+        }
+        *reinterpret_cast<float4*>(hx + r * EX_TX + c4) = make_float4(o0[0], o0[1], o0[2], o0[3]);
+        *reinterpret_cast<float4*>(hx + GH * EX_TX + r * EX_TX + c4) = make_float4(o1[0], o1[1], o1[2], o1[3]);
       }
-      hx[i] = s0;
-      hx[GH * EX_TX + i] = s1;
     }
     __syncthreads();
 #pragma unroll
