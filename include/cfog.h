@@ -286,7 +286,8 @@ int cfog_harris_grid(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, in
  * coordinates normalised by the centre and half-extent of their bounding box;
  * residual = Euclidean distance between the mapped source point and its match;
  * RMSE = sqrt(mean residual^2) over the kept points; ties in the largest
- * residual go to the smaller index.  FP64 normal equations, Cholesky solve.
+ * residual go to the smaller index.  FP64 normal equations (formed once,
+ * then downdated by each removed point), Cholesky solve.
  *   d_src, d_dst  DEVICE [n][2] fp32 (x, y): points in A and their matches in
  *                 B (e.g. (x + fdx, y + fdy) from match results), 8-byte aligned.
  *   n             10 .. 2^20 points; the work grows as n * (points removed).
