@@ -172,6 +172,18 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const XRows (&S)[NS]
       for (int k = 0; k < R1; ++k) base[j * R1 + k] = v[k];
     }
     wave_sync();
+    xpass_stage2<C>(L, base, q, R.nrows, tw);
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) xpass_zero_tail<C>(S[s]);
+}
+
+// Stage 2 of the row FFT of pair q at base (stage 1 done), then the
+// separation of the two packed rows into their half-spectra.
+template <class C>
+__device__ __forceinline__ void xpass_stage2(const Lane<C>& L, float2* base, int q, int nrows, const float2* tw) {
+  constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH;
+  {
     // stage 2 on every lane of the group (idle lanes duplicate lane R1-1 so the
     // cross-lane fetch below runs with the whole wave active)
     const int k1 = L.li < R1 ? L.li : R1 - 1;
@@ -185,7 +197,7 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const XRows (&S)[NS]
     // lane R1-k1 of the group (k1 > 0), or this lane's register (R2-k2) mod R2 (k1 = 0).
     const int lane = threadIdx.x & 63;
     const int msrc = lane - L.li + (k1 == 0 ? 0 : R1 - k1);
-    const bool odd_pad = (2 * q + 1) >= R.nrows;  // second row of the pair is padding
+    const bool odd_pad = (2 * q + 1) >= nrows;  // second row of the pair is padding
     static_for<0, R2>([&](auto k2I) {
       constexpr int k2 = decltype(k2I)::value;
       const float2 far = make_float2(__shfl(v[R2 - 1 - k2].x, msrc, 64), __shfl(v[R2 - 1 - k2].y, msrc, 64));
@@ -199,13 +211,85 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const XRows (&S)[NS]
     });
     wave_sync();
   }
-  // rows [2 nrp, P) of the half-spectrum are zero padding (an odd last row is
-  // zeroed by its pair above)
+}
+
+// Rows [2 ceil(nrows/2), P) of a set's half-spectra are zero padding (an odd
+// last row is zeroed by its pair); needed where a y-pass reads all P rows.
+template <class C>
+__device__ __forceinline__ void xpass_zero_tail(const XRows& R) {
+  if (!R.zero_tail) return;
+  const int r0 = 2 * ((R.nrows + 1) >> 1);
+  for (int t = threadIdx.x; t < (C::P - r0) * C::PH; t += C::NT) R.X[r0 * C::PH + t] = make_float2(0.f, 0.f);
+}
+
+// The x-pass of the fused layout: as xpass_fwd over the template's rows then
+// the window's, except that the first pair of this group (template pair L.g)
+// was loaded into vn by the caller during the previous channel's y-pass,
+// which hides its global-memory latency; vn then prefetches the next pair.
+template <class C>
+__device__ __forceinline__ void xpass_fused(const Lane<C>& L, const XRows (&S)[2], const float2* tw,
+                                            float2 (&vn)[C::R1]) {
+  constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH;
+  const int nrp0 = (S[0].nrows + 1) >> 1;
+  const int total = nrp0 + ((S[1].nrows + 1) >> 1);
+  auto load = [&](int i, float2 (&v)[R1]) {
+    const bool s1 = i >= nrp0;
+    const XRows& R = s1 ? S[1] : S[0];
+    const int q = s1 ? i - nrp0 : i;
+    const int j = L.li;
+    const float* r0 = R.src + (int64_t)(2 * q) * R.ld;
+    const bool has1 = (2 * q + 1) < R.nrows;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    if (!S[s].zero_tail) continue;
-    const int r0 = 2 * ((S[s].nrows + 1) >> 1);
-    for (int t = threadIdx.x; t < (P - r0) * PH; t += C::NT) S[s].X[r0 * PH + t] = make_float2(0.f, 0.f);
+    for (int a = 0; a < R1; ++a) {
+      const int xx = j + R2 * a;
+      float re = 0.f, im = 0.f;
+      if (xx < R.ncols) {
+        re = r0[xx];
+        if (has1) im = r0[R.ld + xx];
+      }
+      v[a] = make_float2(re, im);
+    }
+  };
+  if (L.g >= nrp0 && L.g < total && L.li < R2) load(L.g, vn);  // not covered by the preload
+  for (int i = L.g; i < total; i += C::NG) {
+    const bool s1 = i >= nrp0;
+    const XRows& R = s1 ? S[1] : S[0];
+    const int q = s1 ? i - nrp0 : i;
+    float2* base = R.X + 2 * opaque(q) * PH;
+    if (L.li < R2) {
+      const int j = L.li;
+      float2 v[R1];
+#pragma unroll
+      for (int a = 0; a < R1; ++a) v[a] = vn[a];
+      if (i + C::NG < total) load(i + C::NG, vn);
+      dft<R1, -1>(v);
+#pragma unroll
+      for (int k = 0; k < R1; ++k) base[j * R1 + k] = v[k];
+    }
+    wave_sync();
+    xpass_stage2<C>(L, base, q, R.nrows, tw);
+  }
+  xpass_zero_tail<C>(S[1]);
+}
+
+// Issues the loads of this group's first pair of the fused x-pass (template
+// pair L.g) into vn.
+template <class C>
+__device__ __forceinline__ void xpass_fused_preload(const Lane<C>& L, const XRows& T, float2 (&vn)[C::R1]) {
+  if (L.g < ((T.nrows + 1) >> 1) && L.li < C::R2) {
+    const int j = L.li, q = L.g;
+    const float* r0 = T.src + (int64_t)(2 * q) * T.ld;
+    const bool has1 = (2 * q + 1) < T.nrows;
+#pragma unroll
+    for (int a = 0; a < C::R1; ++a) {
+      const int xx = j + C::R2 * a;
+      float re = 0.f, im = 0.f;
+      if (xx < T.ncols) {
+        re = r0[xx];
+        if (has1) im = r0[T.ld + xx];
+      }
+      vn[a] = make_float2(re, im);
+    }
   }
 }
 
@@ -343,12 +427,27 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   // rows into X), then one y-pass phase; two barriers per channel
   auto fused_channels = [&]() {
     float2* XT = reinterpret_cast<float2*>(reinterpret_cast<char*>(X) + C::BASE);
-    for (int c = c0; c < c1; ++c) {
-      __syncthreads();  // previous readers of X and XT are done
-      const XRows rows[2] = {{tA + c * planeA, jd.wA, N, N, XT, false}, {sB + c * planeB, jd.wB, Ws, Ws, X, true}};
-      xpass_fwd<C, 2>(L, rows, tw);
-      __syncthreads();
-      ypass_fused<C>(L, XT, N, X, tw, acc);
+    if constexpr (C::P >= 120) {
+      // the large plans load the next channel's first template pair during
+      // this channel's y-pass (measured: 1.4% at P = 144, 3.6% at P = 120)
+      float2 vn[R1];
+      xpass_fused_preload<C>(L, XRows{tA + c0 * planeA, jd.wA, N, N, XT, false}, vn);
+      for (int c = c0; c < c1; ++c) {
+        __syncthreads();  // previous readers of X and XT are done
+        const XRows rows[2] = {{tA + c * planeA, jd.wA, N, N, XT, false}, {sB + c * planeB, jd.wB, Ws, Ws, X, true}};
+        xpass_fused<C>(L, rows, tw, vn);
+        __syncthreads();
+        if (c + 1 < c1) xpass_fused_preload<C>(L, XRows{tA + (c + 1) * planeA, jd.wA, N, N, XT, false}, vn);
+        ypass_fused<C>(L, XT, N, X, tw, acc);
+      }
+    } else {
+      for (int c = c0; c < c1; ++c) {
+        __syncthreads();  // previous readers of X and XT are done
+        const XRows rows[2] = {{tA + c * planeA, jd.wA, N, N, XT, false}, {sB + c * planeB, jd.wB, Ws, Ws, X, true}};
+        xpass_fwd<C, 2>(L, rows, tw);
+        __syncthreads();
+        ypass_fused<C>(L, XT, N, X, tw, acc);
+      }
     }
   };
   // two-phase layout: T^ parked in registers (or global memory) between the
