@@ -34,7 +34,7 @@ Workloads (--workload):
       CP matches/s sustained in the sweep.  Also checks that a seeded sample
       of requests gives bit-identical results alone and in the mix.
 
-Prints ONE JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+Prints ONE JSON line.  `--gpus N` with N > 1 is refused: the benchmark runs on
 one GPU.
 """
 from __future__ import annotations
@@ -184,7 +184,7 @@ def main():
                     help="serve: device memory budget (0: 80%% of free memory)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the benchmark runs on exactly one GPU (asked for --gpus {args.gpus}); "
               "the matching path shards by control point and needs no collectives", file=sys.stderr)
         sys.exit(2)
     if args.workload == "serve":

@@ -1,8 +1,8 @@
 """FP64 CPU oracle for CFOG extraction and SSD template matching.
 
-TEST INFRASTRUCTURE ONLY.  This module is the independent judge of the HIP
-path: only the test suite, the smoke entry point and the benchmark's CPU
-baseline may import it.  It shares no code with the GPU library and must never
+TEST INFRASTRUCTURE ONLY.  This module is the independent reference the HIP
+path is checked against: only the test suite, the smoke entry point and the
+benchmark's CPU baseline may import it.  It shares no code with the GPU library and must never
 be used to produce a product result.
 
 What it computes (Ye et al., "Fast and Robust Matching for Multimodal Remote
