@@ -625,8 +625,9 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
 //  P, R1, R2, NT, layout  (R1 >= R2 keeps the per-lane outputs of stage 2
 //  small).  NT is set per size from measurement: as many waves as the
 //  registers allow without starving the column rounds (P = 96..108 at 768
-//  threads take every column in one round; P >= 128 at 512 threads beat
-//  256-384 threads despite some register spilling at P >= 180).  The layout
+//  threads take every column in one round; P = 120..144 at 512 threads beat
+//  256-384 threads; the global-layout sizes P >= 160 gain 4-5% from 768
+//  threads over 512 despite their register spilling).  The layout
 //  too: the fused one was 6-18% faster than parking T^ in registers for
 //  P = 80..144 except P = 128 (2.5% slower, more spills); the largest sizes
 //  park T^ in global memory.
@@ -647,9 +648,9 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
   X(120, 12, 10, 512, LAY_FUSED)       \
   X(128, 16, 8, 512, LAY_REG)          \
   X(144, 12, 12, 512, LAY_FUSED)       \
-  X(160, 16, 10, 512, LAY_GLOBAL)      \
-  X(180, 15, 12, 512, LAY_GLOBAL)      \
-  X(192, 16, 12, 512, LAY_GLOBAL)
+  X(160, 16, 10, 768, LAY_GLOBAL)      \
+  X(180, 15, 12, 768, LAY_GLOBAL)      \
+  X(192, 16, 12, 768, LAY_GLOBAL)
 
 #define CFOG_CFG(P_, R1_, R2_, NT_, TG_) FftCfg<P_, R1_, R2_, NT_, TG_>
 
