@@ -625,12 +625,12 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
 //  P, R1, R2, NT, layout  (R1 >= R2 keeps the per-lane outputs of stage 2
 //  small).  NT is set per size from measurement: as many waves as the
 //  registers allow without starving the column rounds (P = 96..108 at 768
-//  threads take every column in one round; P = 120..144 at 512 threads beat
-//  256-384 threads; the global-layout sizes P >= 160 gain 4-5% from 768
-//  threads over 512 despite their register spilling).  The layout
-//  too: the fused one was 6-18% faster than parking T^ in registers for
-//  P = 80..144 except P = 128 (2.5% slower, more spills); the largest sizes
-//  park T^ in global memory.
+//  threads take every column in one round; P = 128 and 144 at 512 threads
+//  beat 256-384 threads; P = 120 and the global-layout sizes P >= 160 gain
+//  3-5% from 768 threads over 512 despite their register spilling).  The
+//  layout too: the fused one was 6-18% faster than parking T^ in registers
+//  for P = 80..144 except P = 128 (2.5% slower, more spills); the largest
+//  sizes park T^ in global memory.
 #define CFOG_PLANS(X)                  \
   X(16, 4, 4, 64, LAY_REG)             \
   X(24, 6, 4, 128, LAY_REG)            \
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
   X(96, 12, 8, 768, LAY_FUSED)         \
   X(100, 10, 10, 768, LAY_FUSED)       \
   X(108, 12, 9, 768, LAY_FUSED)        \
-  X(120, 12, 10, 512, LAY_FUSED)       \
+  X(120, 12, 10, 768, LAY_FUSED)       \
   X(128, 16, 8, 512, LAY_REG)          \
   X(144, 12, 12, 512, LAY_FUSED)       \
   X(160, 16, 10, 768, LAY_GLOBAL)      \
