@@ -15,6 +15,7 @@
 #include <vector>
 #include "cfog.h"
 #include "kernels.hpp"
+#include "split_plan.hpp"
 
 namespace {
 
@@ -119,39 +120,12 @@ const cfog::FftPlan* select_plan(cfog_ctx* ctx, int N, int r, int m) {
 
 // ------------------------------------------------------------- batch plans
 
-// Channel split of the last round of a launch of n tasks on S workgroup
-// slots (see SplitArgs): the group count G minimising the modelled time,
-// G = 1 when splitting does not pay.  Costs are counted in 1-D FFTs of the
-// plan's size: per channel the row FFTs of template and window (two rows per
-// FFT) and the column FFTs of both half-spectra; per task the inverse and
-// the epilogue; a split pays its extra inverses and the reduce launch.
-// (Nmax, Wsmax, Kmax) bound the tasks' template, window and surface sides.
+// Channel split of the last round of a launch (split_plan.hpp).
 cfog::SplitArgs plan_split(const cfog::FftPlan* p, int n, int S, int m, int Nmax, int Wsmax, int Kmax,
                            size_t* bytes) {
-  cfog::SplitArgs sp{n, 1, 0, nullptr};
-  *bytes = 0;
-  if (m < 2 || n <= 0 || S <= 0) return sp;
-  const int q = n / S, rem = n % S;
-  if (rem == 0) return sp;
-  const int PH = p->P / 2 + 1;
-  const double cf = (Nmax + 1) / 2 + (Wsmax + 1) / 2 + 2.0 * PH;
-  const double ci = PH + (Kmax + 1) / 2;
-  auto cost = [&](int G) { return ((m + G - 1) / G) * cf + ci; };
-  double best = (q + 1) * cost(1);
-  int bestG = 1;
-  for (int G = 2; G <= std::min(m, 16) && (long)rem * G <= 2L * S; ++G) {
-    const double t = q * cost(1) + ((rem * G + S - 1) / S) * cost(G) + 0.05 * cost(1);
-    if (t < best) {
-      best = t;
-      bestG = G;
-    }
-  }
-  if (bestG == 1) return sp;
-  sp.n_whole = n - rem;
-  sp.G = bestG;
-  sp.slot = (int)align_up((size_t)Kmax * Kmax, 64);
-  *bytes = align_up(sizeof(float) * (size_t)rem * bestG * sp.slot, 256);
-  return sp;
+  const cfog::SplitChoice c = cfog::plan_split_choice(p->P, n, S, m, Nmax, Wsmax, Kmax);
+  *bytes = c.bytes;
+  return cfog::SplitArgs{c.n_whole, c.G, c.slot, nullptr};
 }
 
 // Workspace layout of a plain-path launch of job j: the template-spectrum

@@ -125,3 +125,17 @@ def test_server_scheduler_simulation(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
     assert "ALL OK" in r.stdout
+
+
+def test_channel_split_planner(tmp_path):
+    """The host-side choice of the matcher's last-round channel split
+    (split_plan.hpp), built for the host with the sanitizers."""
+    src = os.path.join(ROOT, "tests", "cpp", "split_plan_test.cpp")
+    exe = tmp_path / "split_plan_test"
+    inc = os.path.join(ROOT, "paper_1808_06194_amd", "csrc")
+    r = subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-I", inc, src,
+                        "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
+    assert "ALL OK" in r.stdout
