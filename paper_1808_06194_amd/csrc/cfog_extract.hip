@@ -531,10 +531,14 @@ __global__ __launch_bounds__(EX_NT) void fhog_kernel(FhogArgs a) {
 // Kernel 2: exclusive prefixes of the right columns along each image row (one
 // wave per row, lanes across tiles) and of the bottom rows along each image
 // column (64 columns per workgroup, lanes across columns, the tile rows split
-// between the 4 waves: each wave sums its rows, the partial sums are
-// exchanged in LDS, then each wave writes its exclusive prefixes; no load
-// waits on another).
-constexpr int SAT_NT = 256;
+// between the 16 waves: each wave sums its rows, the partial sums are
+// exchanged in LDS, then each wave writes its exclusive prefixes).  A wave's
+// first 8 tile rows stay in registers between the two steps, which at up to
+// 128 tile rows (2048 image rows) is all of them: one round of loads, one of
+// stores.
+constexpr int SAT_NT = 1024;
+constexpr int SAT_WAVES = SAT_NT / 64;
+constexpr int SAT_CH = 8;
 
 __device__ __forceinline__ double wave_excl_scan(double v, double& total) {
   const double inc = wave_incl_scan(v);
@@ -545,7 +549,7 @@ __device__ __forceinline__ double wave_excl_scan(double v, double& total) {
 __global__ __launch_bounds__(SAT_NT) void sat_carry_kernel(double* rc, double* bt, int H, int W, int ntx, int nty,
                                                            int row_blocks) {
   if ((int)blockIdx.x < row_blocks) {
-    const int y = blockIdx.x * (SAT_NT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int y = blockIdx.x * SAT_WAVES + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (y >= H) return;
     double* p = rc + (size_t)y * ntx;
     double carry = 0.0;
@@ -559,34 +563,43 @@ __global__ __launch_bounds__(SAT_NT) void sat_carry_kernel(double* rc, double* b
     }
     return;
   }
-  __shared__ double part[SAT_NT / 64][64];
+  __shared__ double part[SAT_WAVES][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x = (blockIdx.x - row_blocks) * 64 + lane;
-  const int per = (nty + SAT_NT / 64 - 1) / (SAT_NT / 64);
+  const int per = (nty + SAT_WAVES - 1) / SAT_WAVES;
   const int i0 = wv * per, i1 = min(nty, i0 + per);
+  const bool xok = x < W;
+  double first[SAT_CH];
+#pragma unroll
+  for (int u = 0; u < SAT_CH; ++u) first[u] = (xok && i0 + u < i1) ? bt[(size_t)(i0 + u) * W + x] : 0.0;
   double sum = 0.0;
-  if (x < W) {
-    constexpr int CH = 8;
-    for (int i = i0; i < i1; i += CH) {
-      double v[CH];
 #pragma unroll
-      for (int u = 0; u < CH; ++u) v[u] = (i + u < i1) ? bt[(size_t)(i + u) * W + x] : 0.0;
+  for (int u = 0; u < SAT_CH; ++u) sum += first[u];
+  if (xok) {
+    for (int i = i0 + SAT_CH; i < i1; i += SAT_CH) {
+      double v[SAT_CH];
 #pragma unroll
-      for (int u = 0; u < CH; ++u) sum += v[u];
+      for (int u = 0; u < SAT_CH; ++u) v[u] = (i + u < i1) ? bt[(size_t)(i + u) * W + x] : 0.0;
+#pragma unroll
+      for (int u = 0; u < SAT_CH; ++u) sum += v[u];
     }
   }
   part[wv][lane] = sum;
   __syncthreads();
-  if (x >= W) return;
+  if (!xok) return;
   double run = 0.0;
   for (int k = 0; k < wv; ++k) run += part[k][lane];
-  constexpr int CH = 8;
-  for (int i = i0; i < i1; i += CH) {
-    double v[CH];
 #pragma unroll
-    for (int u = 0; u < CH; ++u) v[u] = (i + u < i1) ? bt[(size_t)(i + u) * W + x] : 0.0;
+  for (int u = 0; u < SAT_CH; ++u) {
+    if (i0 + u < i1) bt[(size_t)(i0 + u) * W + x] = run;
+    run += first[u];
+  }
+  for (int i = i0 + SAT_CH; i < i1; i += SAT_CH) {
+    double v[SAT_CH];
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
+    for (int u = 0; u < SAT_CH; ++u) v[u] = (i + u < i1) ? bt[(size_t)(i + u) * W + x] : 0.0;
+#pragma unroll
+    for (int u = 0; u < SAT_CH; ++u) {
       if (i + u < i1) bt[(size_t)(i + u) * W + x] = run;
       run += v[u];
     }
@@ -595,12 +608,27 @@ __global__ __launch_bounds__(SAT_NT) void sat_carry_kernel(double* rc, double* b
 
 // Kernel 3: SAT = L + row carry + column carry + corner, in place; zero row 0
 // and column 0.  One thread per pixel column of a 64 x 16 tile, 4 rows each.
+// The tile's values and carries are loaded first, so their latency overlaps
+// the corner's reduction.
 __global__ __launch_bounds__(EX_NT) void sat_fix_kernel(double* sat, const double* rc, const double* bt, int H,
                                                         int W, int ntx) {
   __shared__ double corner_part[EX_NT / 64];
   const int tid = threadIdx.x, oc = tid & 63, wv = tid >> 6;
   const int tx = blockIdx.x, ty = blockIdx.y;
   const int x0 = tx * EX_TX, y0 = ty * EX_TY;
+  const int W1 = W + 1;
+  const int gxx = x0 + oc;
+  double* const p0 = sat + (size_t)(y0 + wv * EX_RUN + 1) * W1 + gxx + 1;
+  bool ok[EX_RUN];
+  double l[EX_RUN], r[EX_RUN];
+  const double colc = gxx < W ? bt[(size_t)ty * W + gxx] : 0.0;
+#pragma unroll
+  for (int o = 0; o < EX_RUN; ++o) {
+    const int gyy = y0 + wv * EX_RUN + o;
+    ok[o] = gxx < W && gyy < H;
+    l[o] = ok[o] ? p0[(size_t)o * W1] : 0.0;
+    r[o] = ok[o] ? rc[(size_t)gyy * ntx + tx] : 0.0;
+  }
   // corner = sum_{j' < tx} (column prefix of bottom rows at the last column of tile j')
   double cpart = 0.0;
   for (int j = tid; j < tx; j += EX_NT) {
@@ -612,19 +640,9 @@ __global__ __launch_bounds__(EX_NT) void sat_fix_kernel(double* sat, const doubl
   if ((tid & 63) == 0) corner_part[wv] = cpart;
   __syncthreads();
   const double corner = corner_part[0] + corner_part[1] + corner_part[2] + corner_part[3];
-  const int W1 = W + 1;
-  const int gxx = x0 + oc;
-  if (gxx < W) {
-    const double colc = bt[(size_t)ty * W + gxx];
 #pragma unroll
-    for (int o = 0; o < EX_RUN; ++o) {
-      const int gyy = y0 + wv * EX_RUN + o;
-      if (gyy < H) {
-        double* p = sat + (size_t)(gyy + 1) * W1 + gxx + 1;
-        *p = *p + rc[(size_t)gyy * ntx + tx] + colc + corner;
-      }
-    }
-  }
+  for (int o = 0; o < EX_RUN; ++o)
+    if (ok[o]) p0[(size_t)o * W1] = l[o] + r[o] + colc + corner;
   if (ty == 0) {
     for (int x = x0 + tid; x < min(W + 1, x0 + EX_TX + 1); x += EX_NT) sat[x] = 0.0;
   }
