@@ -23,9 +23,11 @@
 //   D. the tile-local 2-D inclusive prefix L of Q (row scan across the 64 lanes
 //      of a wave, column scan down the tile), written into the SAT buffer,
 //      plus the tile's right column and bottom row into a small workspace.
-// LDS holds the two gradient planes and two row-pass buffers (the image tile
-// shares their storage), about 26 KB at R = 3, so six workgroups share a CU;
-// one barrier per channel.
+// LDS holds the two gradient planes and one row-pass buffer (the image tile
+// shares its storage; the wave carries of D reuse the dead gradient planes),
+// about 19 KB at R = 3, so eight workgroups (32 waves) share a CU; two
+// barriers per channel.  (Two row-pass buffers, one barrier per channel and
+// six workgroups per CU measured 3-4% slower.)
 
 // Global SAT from tile-local prefixes: for a tile (i, j) with origin (y0, x0),
 //   SAT(y, x) = L(y, x) + sum_{j'<j} Rc_{i,j'}(y) + sum_{i'<i} Bt_{i',j}(x)
@@ -109,10 +111,10 @@ struct ExTile {
   static constexpr int NQUAD = GH * EX_TX / 4;    // horizontal outputs four at a time
   static constexpr size_t IMG = ((size_t)IH * IW + 3) / 4 * 4;   // floats
   static constexpr size_t GP = (size_t)GH * GWP;                 // floats per gradient plane
-  static constexpr size_t HB = 2 * (size_t)GH * EX_TX;           // floats (two channels)
+  static constexpr size_t HB = (size_t)GH * EX_TX;                // floats: one channel's row pass
   // the image tile is dead once the gradients exist: it shares HB's storage
   static constexpr size_t HBI = HB > IMG ? HB : IMG;
-  static constexpr size_t BYTES = 4 * 2 * GP + 4 * HBI + 8 * 4 * 64;
+  static constexpr size_t BYTES = 4 * 2 * GP + 4 * HBI;
 };
 
 // M > 0: the channel count fixed at compile time (the channel loop unrolls
@@ -127,9 +129,9 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   const int m = M > 0 ? M : a.m;
   float* gxp = lds;                                  // GH * GWP: gx (scheme 1: |g|)
   float* gyp = gxp + T::GP;                          // GH * GWP: gy (scheme 1: bin position)
-  float* Hb = gyp + T::GP;                           // 2 * GH * EX_TX row-pass outputs
+  float* Hb = gyp + T::GP;                           // GH * EX_TX row-pass outputs
   float* img = Hb;                                   // IH * IW, read only by the gradient pass
-  double* qx = reinterpret_cast<double*>(Hb + T::HBI);  // 4 x 64 wave carries
+  double* qx = reinterpret_cast<double*>(gxp);       // 4 x 64 wave carries, after the last channel
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * EX_TX, y0 = blockIdx.y * EX_TY;
   const int H = a.H, W = a.W;
@@ -218,8 +220,8 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   // C. per channel: the horizontal Gaussian of the oriented gradient (the
   // channel values computed on the fly from the gradient planes), then the
   // vertical pass, which leaves the spatially smoothed channel Gs_k for the
-  // rows [4 (tid/64), +4) of column tid % 64 in registers.  One barrier per
-  // channel: the row-pass buffer alternates between two halves.
+  // rows [4 (tid/64), +4) of column tid % 64 in registers.  A barrier after
+  // each pass: the next channel's row pass rewrites the buffer.
   const int oc = tid & 63, orow = (tid >> 6) * EX_RUN;
   const int gxx = x0 + oc;
   double q[EX_RUN];
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
       }
       return fabsf(fmaf(ck, u, sk * v));
     };
-    float* hb = Hb + (k & 1) * GH * EX_TX;
+    float* hb = Hb;
     // horizontal pass: each thread four consecutive outputs of one row from
     // 16-byte reads of both gradient planes (16 threads cover a row)
 #pragma unroll
@@ -315,9 +317,7 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
     }
 #pragma unroll
     for (int o = 0; o < EX_RUN; ++o) { pm2[o] = pm1[o]; pm1[o] = cur[o]; }
-    // the next channel writes the other half of Hb; this half is overwritten
-    // two channels later, after the next barrier (which every thread reaches
-    // only when its reads of this half are done)
+    __syncthreads();  // every read of Hb is done before the next row pass
   };
   if constexpr (M > 0) {
 #pragma unroll
