@@ -136,7 +136,7 @@ int cfog_extract_fhog(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, i
                       void* stream);
 
 /* Device workspace (bytes) cfog_extract needs to build the SAT of an H x W
- * image: 8 * (H * ceil(W/64) + ceil(H/16) * W). */
+ * image: 8 * (H * ceil(W/64) + ceil(H/32) * W). */
 size_t cfog_extract_workspace_size(int32_t H, int32_t W);
 
 /* One control point: template centre (x, y) in A; search centre (bx, by) in B

@@ -5,7 +5,7 @@
 // contiguous H*W plane per orientation); SAT [(H+1)][(W+1)] fp64 with a zero
 // first row and column, SAT(y+1, x+1) = sum_{y'<=y, x'<=x} Q(y', x').
 //
-// Kernel 1 (cfog_extract_kernel<R, M>) produces a 64 x 16 output tile for all
+// Kernel 1 (cfog_extract_kernel<R, M>) produces a 64 x 32 output tile for all
 // m channels:
 //   A. stage the image tile plus an (R+1)-pixel halo in LDS (clamp-to-edge);
 //   B. gx, gy by [-1,0,1] (the filters given after Eq. 2) at every pixel of
@@ -25,9 +25,10 @@
 //      plus the tile's right column and bottom row into a small workspace.
 // LDS holds the two gradient planes and one row-pass buffer (the image tile
 // shares its storage; the wave carries of D reuse the dead gradient planes),
-// about 19 KB at R = 3, so eight workgroups (32 waves) share a CU; two
-// barriers per channel.  (Two row-pass buffers, one barrier per channel and
-// six workgroups per CU measured 3-4% slower.)
+// about 33 KB at R = 3; four 512-thread workgroups (32 waves) share a CU; two
+// barriers per channel.  (Measured on 2048^2 images: 64 x 16 tiles of 256
+// threads, eight per CU, 4% slower; with two row-pass buffers, one barrier per
+// channel and six per CU, 7-8% slower.)
 
 // Global SAT from tile-local prefixes: for a tile (i, j) with origin (y0, x0),
 //   SAT(y, x) = L(y, x) + sum_{j'<j} Rc_{i,j'}(y) + sum_{i'<i} Bt_{i',j}(x)
@@ -42,8 +43,8 @@
 namespace cfog {
 
 constexpr int EX_TX = 64;
-constexpr int EX_TY = 16;
-constexpr int EX_NT = 256;
+constexpr int EX_TY = 32;
+constexpr int EX_NT = 512;
 constexpr int EX_RUN = 4;  // outputs per thread in the sliding Gaussian passes
 
 struct ExtractArgs {
@@ -131,7 +132,8 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   float* gyp = gxp + T::GP;                          // GH * GWP: gy (scheme 1: bin position)
   float* Hb = gyp + T::GP;                           // GH * EX_TX row-pass outputs
   float* img = Hb;                                   // IH * IW, read only by the gradient pass
-  double* qx = reinterpret_cast<double*>(gxp);       // 4 x 64 wave carries, after the last channel
+  double* qx = reinterpret_cast<double*>(gxp);       // 64 wave carries per wave, after the last channel
+  static_assert(2 * T::GP * sizeof(float) >= (EX_NT / 64) * 64 * sizeof(double), "wave carries");
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * EX_TX, y0 = blockIdx.y * EX_TY;
   const int H = a.H, W = a.W;
@@ -381,7 +383,7 @@ struct FhTile {
   static constexpr int NQUAD = GH * EX_TX / 4;  // horizontal outputs four at a time
   static constexpr size_t G = (size_t)GH * GWP;                         // floats
   static constexpr size_t HX = 2 * (size_t)GH * EX_TX;                  // floats: both horizontal passes
-  static constexpr size_t BYTES = 4 * IMG + 8 * MB + 4 * G + 4 * HX + 8 * 4 * 64;
+  static constexpr size_t BYTES = 4 * IMG + 8 * MB + 4 * G + 4 * HX + 8 * (EX_NT / 64) * 64;
 };
 
 // Bilinear weight of block offset d for cell a (centre offset (a - 1/2) C).
@@ -607,7 +609,7 @@ __global__ __launch_bounds__(SAT_NT) void sat_carry_kernel(double* rc, double* b
 }
 
 // Kernel 3: SAT = L + row carry + column carry + corner, in place; zero row 0
-// and column 0.  One thread per pixel column of a 64 x 16 tile, 4 rows each.
+// and column 0.  One thread per pixel column of an extraction tile, 4 rows each.
 // The tile's values and carries are loaded first, so their latency overlaps
 // the corner's reduction.
 __global__ __launch_bounds__(EX_NT) void sat_fix_kernel(double* sat, const double* rc, const double* bt, int H,
@@ -639,7 +641,9 @@ __global__ __launch_bounds__(EX_NT) void sat_fix_kernel(double* sat, const doubl
   for (int o = 32; o > 0; o >>= 1) cpart += __shfl_xor(cpart, o, 64);
   if ((tid & 63) == 0) corner_part[wv] = cpart;
   __syncthreads();
-  const double corner = corner_part[0] + corner_part[1] + corner_part[2] + corner_part[3];
+  double corner = 0.0;
+#pragma unroll
+  for (int k = 0; k < EX_NT / 64; ++k) corner += corner_part[k];
 #pragma unroll
   for (int o = 0; o < EX_RUN; ++o)
     if (ok[o]) p0[(size_t)o * W1] = l[o] + r[o] + colc + corner;
