@@ -82,6 +82,22 @@ def test_extract_row_stride(cf):
     assert torch.equal(vol, ref)
 
 
+@pytest.mark.parametrize("H,W", [(24, 8300), (8300, 24), (97, 4160)])
+def test_extract_sat_of_wide_and_tall_images(cf, H, W):
+    """The SAT carry scans in several pieces: more than 64 tiles along a row
+    (W > 4096) and more than 8 tile rows per wave of the column scan
+    (H > 4096).  Property at any size: the SAT is the 2-D prefix of the
+    returned volume's energies, with zero first row and column."""
+    _say("extract SAT", H, W)
+    img = np.random.default_rng(H + W).random((H, W)).astype(np.float32)
+    vol, sat = _extract(cf, img)
+    q = (vol.astype(np.float64) ** 2).sum(0)
+    ref = np.zeros((H + 1, W + 1))
+    ref[1:, 1:] = q.cumsum(0).cumsum(1)
+    assert np.all(sat[0] == 0) and np.all(sat[:, 0] == 0)
+    assert np.max(np.abs(sat - ref)) <= 1e-11 * ref[-1, -1]
+
+
 def test_extract_rejects_bad_arguments(cf):
     _say("extract invalid args")
     img = torch.rand(8, 8, device="cuda")
