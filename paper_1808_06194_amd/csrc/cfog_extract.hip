@@ -548,8 +548,7 @@ __global__ __launch_bounds__(EX_NT) void fhog_kernel(FhogArgs a) {
 // between the 16 waves: each wave sums its rows, the partial sums are
 // exchanged in LDS, then each wave writes its exclusive prefixes).  A wave's
 // first 8 tile rows stay in registers between the two steps, which at up to
-// 128 tile rows (2048 image rows) is all of them: one round of loads, one of
-// stores.
+// 128 tile rows is all of them: one round of loads, one of stores.
 constexpr int SAT_NT = 1024;
 constexpr int SAT_WAVES = SAT_NT / 64;
 constexpr int SAT_CH = 8;
