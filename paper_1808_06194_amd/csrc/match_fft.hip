@@ -103,6 +103,23 @@ struct Lane {
   }
 };
 
+// The inputs of a stage-2 DFT of lane k1: w[b] = get(b) W_P^{-k1 b} (INV:
+// W_P^{+k1 b}).  The twiddles come by recurrence from W_P^{k1}: one LDS read
+// instead of R2 - 1 (measured 3% faster at P = 144, 15% at P = 192), at most
+// R2 - 2 more FP32 roundings in each.
+template <class C, bool INV, class Get>
+__device__ __forceinline__ void stage2_inputs(float2 (&w)[C::R2], const float2* tw, int k1, Get&& get) {
+  float2 t1 = tw[C::R1 + k1];
+  if (INV) t1.y = -t1.y;
+  float2 t = t1;
+  w[0] = get(0);
+#pragma unroll
+  for (int b = 1; b < C::R2; ++b) {
+    if (b > 1) t = cmul(t, t1);
+    w[b] = cmul(get(b), t);
+  }
+}
+
 // One set of rows for the x-pass: nrows x ncols real values at src (leading
 // dim ld), transformed into X (row stride PH).  zero_tail: rows
 // [2 ceil(nrows/2), P) of X are zeroed (a y-pass that reads all P rows).
@@ -188,9 +205,7 @@ __device__ __forceinline__ void xpass_stage2(const Lane<C>& L, float2* base, int
     // cross-lane fetch below runs with the whole wave active)
     const int k1 = L.li < R1 ? L.li : R1 - 1;
     float2 v[R2];
-    v[0] = base[k1];
-#pragma unroll
-    for (int b = 1; b < R2; ++b) v[b] = cmul(base[k1 + R1 * b], tw[b * R1 + k1]);
+    stage2_inputs<C, false>(v, tw, k1, [&](int b) { return base[k1 + R1 * b]; });
     dft<R2, -1>(v);
     // separate the packed rows: A(k) = (Z(k) + conj Z(-k)) / 2, B(k) = (Z(k) - conj Z(-k)) / 2i.
     // Z(-k) for k = k1 + R1 k2 is Z((R1-k1) + R1 (R2-1-k2)), i.e. register R2-1-k2 of
@@ -322,9 +337,7 @@ __device__ __forceinline__ void ypass_fused(const Lane<C>& L, const float2* XT, 
       wave_sync();
       if (L.li < R1) {
         const int k1 = L.li;
-        sh[0] = col[k1 * PH];
-#pragma unroll
-        for (int b = 1; b < R2; ++b) sh[b] = cmul(col[(k1 + R1 * b) * PH], tw[b * R1 + k1]);
+        stage2_inputs<C, false>(sh, tw, k1, [&](int b) { return col[(k1 + R1 * b) * PH]; });
         dft<R2, -1>(sh);
       }
       wave_sync();
@@ -345,9 +358,7 @@ __device__ __forceinline__ void ypass_fused(const Lane<C>& L, const float2* XT, 
       if (L.li < R1) {
         const int k1 = L.li;
         float2 w[R2];
-        w[0] = col[k1 * PH];
-#pragma unroll
-        for (int b = 1; b < R2; ++b) w[b] = cmul(col[(k1 + R1 * b) * PH], tw[b * R1 + k1]);
+        stage2_inputs<C, false>(w, tw, k1, [&](int b) { return col[(k1 + R1 * b) * PH]; });
         dft<R2, -1>(w);
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) acc[rnd][k2] = cmac_conj(acc[rnd][k2], w[k2], sh[k2]);
@@ -381,9 +392,7 @@ __device__ __forceinline__ void ypass_fwd(const Lane<C>& L, float2* X, const flo
       if (L.li < R1) {
         const int k1 = L.li;
         float2 w[R2];
-        w[0] = col[k1 * PH];
-#pragma unroll
-        for (int b = 1; b < R2; ++b) w[b] = cmul(col[(k1 + R1 * b) * PH], tw[b * R1 + k1]);
+        stage2_inputs<C, false>(w, tw, k1, [&](int b) { return col[(k1 + R1 * b) * PH]; });
         dft<R2, -1>(w);
         static_for<0, R2>([&](auto k2I) {
           constexpr int k2 = decltype(k2I)::value;
@@ -505,12 +514,7 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
       if (L.li < R1) {
         const int k1 = L.li;
         float2 w[R2];
-        w[0] = col[k1 * PH];
-#pragma unroll
-        for (int b = 1; b < R2; ++b) {
-          const float2 t = tw[b * R1 + k1];
-          w[b] = cmul(col[(k1 + R1 * b) * PH], make_float2(t.x, -t.y));
-        }
+        stage2_inputs<C, true>(w, tw, k1, [&](int b) { return col[(k1 + R1 * b) * PH]; });
         dft<R2, +1>(w);
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) {
@@ -552,12 +556,7 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
     if (L.li < R1) {
       const int k1 = L.li;
       float2 w[R2];
-      w[0] = sc[k1];
-#pragma unroll
-      for (int b = 1; b < R2; ++b) {
-        const float2 t = tw[b * R1 + k1];
-        w[b] = cmul(sc[k1 + R1 * b], make_float2(t.x, -t.y));
-      }
+      stage2_inputs<C, true>(w, tw, k1, [&](int b) { return sc[k1 + R1 * b]; });
       dft<R2, +1>(w);
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) {
@@ -590,7 +589,8 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
   float2* X = smem;
   float2* tw = X + C::P * C::PH;
   ArgminState* red = reinterpret_cast<ArgminState*>(tw + C::P);
-  // stage-2 twiddles W_P^{k1 b} stored lane-major: tw[b * R1 + k1]
+  // stage-2 twiddles W_P^{k1 b} stored lane-major, tw[b * R1 + k1] (stage 2
+  // reads row b = 1 and forms the other powers)
   for (int i = threadIdx.x; i < C::P; i += C::NT) {
     const int b = i / C::R1, k1 = i - b * C::R1;
     double s, c;
