@@ -11,6 +11,19 @@
 
 namespace cfog {
 
+// Loads and stores through global-address-space pointers.  Device pointers
+// that reach a kernel inside job records have no known address space, so the
+// compiler would issue flat accesses, which also count as LDS operations:
+// every wait on LDS traffic would then wait for them too (the matchers'
+// prefetched volume rows, the energies, the surface stores).
+__device__ __forceinline__ float ldg(const float* p) {
+  return *(const __attribute__((address_space(1))) float*)p;
+}
+__device__ __forceinline__ double ldg(const double* p) {
+  return *(const __attribute__((address_space(1))) double*)p;
+}
+__device__ __forceinline__ void stg(float* p, float v) { *(__attribute__((address_space(1))) float*)p = v; }
+
 struct ArgminState {
   float bv;  // best value
   int bi;    // its row-major index (u_y * K + u_x)
@@ -44,7 +57,7 @@ __device__ __forceinline__ void am_merge(ArgminState& s, const ArgminState& o) {
 __device__ __forceinline__ double box_sum(const double* sat, int ld, int y0, int x0, int n) {
   const double* a = sat + (size_t)y0 * ld + x0;
   const double* b = a + (size_t)n * ld;
-  return (b[n] - a[n]) - (b[0] - a[0]);
+  return (ldg(b + n) - ldg(a + n)) - (ldg(b) - ldg(a));
 }
 
 // Abscissa, relative to the middle sample, of the vertex of the parabola
@@ -81,7 +94,7 @@ __device__ __forceinline__ void ssd_epilogue(const MatchJob& jd, int cpi, int tx
   for (int idx = threadIdx.x; idx < K * K; idx += NT) {
     const float s = value(idx);
     am_push(st, s, idx);
-    if (surf) surf[idx] = s;
+    if (surf) stg(surf + idx, s);
   }
   // wave reduction then across waves
 #pragma unroll

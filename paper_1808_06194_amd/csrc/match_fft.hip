@@ -157,8 +157,8 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const XRows (&S)[NS]
       const int xx = j + R2 * a;
       float re = 0.f, im = 0.f;
       if (xx < R.ncols) {
-        re = r0[xx];
-        if (has1) im = r0[R.ld + xx];
+        re = ldg(r0 + xx);
+        if (has1) im = ldg(r0 + R.ld + xx);
       }
       v[a] = make_float2(re, im);
     }
@@ -259,8 +259,8 @@ __device__ __forceinline__ void xpass_fused(const Lane<C>& L, const XRows (&S)[2
       const int xx = j + R2 * a;
       float re = 0.f, im = 0.f;
       if (xx < R.ncols) {
-        re = r0[xx];
-        if (has1) im = r0[R.ld + xx];
+        re = ldg(r0 + xx);
+        if (has1) im = ldg(r0 + R.ld + xx);
       }
       v[a] = make_float2(re, im);
     }
@@ -300,8 +300,8 @@ __device__ __forceinline__ void xpass_fused_preload(const Lane<C>& L, const XRow
       const int xx = j + C::R2 * a;
       float re = 0.f, im = 0.f;
       if (xx < T.ncols) {
-        re = r0[xx];
-        if (has1) im = r0[T.ld + xx];
+        re = ldg(r0 + xx);
+        if (has1) im = ldg(r0 + T.ld + xx);
       }
       vn[a] = make_float2(re, im);
     }
@@ -571,7 +571,7 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   __syncthreads();
 
   if (part) {
-    for (int i = threadIdx.x; i < K * K; i += NT) part[i] = Cs[i];
+    for (int i = threadIdx.x; i < K * K; i += NT) stg(part + i, Cs[i]);
     return;
   }
   ssd_epilogue<NT>(jd, cpi, tx0, ty0, sx0, sy0, Cs, red);
@@ -737,8 +737,8 @@ __global__ __launch_bounds__(SR_NT) void split_reduce_kernel(MatchJob job0, cons
   if (!(inA && inB)) return;  // reported by the task's first item
   const float* p = sp.part + (size_t)blockIdx.x * sp.G * sp.slot;
   for (int i = threadIdx.x; i < K * K; i += SR_NT) {
-    float s = p[i];
-    for (int g = 1; g < sp.G; ++g) s += p[(size_t)g * sp.slot + i];
+    float s = ldg(p + i);
+    for (int g = 1; g < sp.G; ++g) s += ldg(p + (size_t)g * sp.slot + i);
     Cs[i] = s;
   }
   __syncthreads();
