@@ -53,6 +53,10 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// RES: the set lives in LDS (n <= RJ_LDS_POINTS).  A compile-time choice, so
+// that every point access has a known address space (LDS or global) instead
+// of going through flat instructions.
+template <bool RES>
 __global__ __launch_bounds__(RJ_NT) void reject_kernel(const float2* __restrict__ src, const float2* __restrict__ dst,
                                                        int n, float thr, unsigned char* keep, cfog_reject_result* out) {
   extern __shared__ float2 rj_pts[];
@@ -64,17 +68,16 @@ __global__ __launch_bounds__(RJ_NT) void reject_kernel(const float2* __restrict_
   __shared__ double ext[4];
   __shared__ int done, active, removed;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const bool resident = n <= RJ_LDS_POINTS;
-  const float2* ps = resident ? rj_pts : src;
-  const float2* pd = resident ? rj_pts + n : dst;
-  unsigned char* pk = resident ? reinterpret_cast<unsigned char*>(rj_pts + 2 * n) : keep;
+  const float2* ps = RES ? rj_pts : src;
+  const float2* pd = RES ? rj_pts + n : dst;
+  unsigned char* pk = RES ? reinterpret_cast<unsigned char*>(rj_pts + 2 * n) : keep;
 
   // points into LDS (resident sets); bounding box -> centre and half-extent per axis
   {
     double mn[2] = {INFINITY, INFINITY}, mx[2] = {-INFINITY, -INFINITY};
     for (int i = tid; i < n; i += RJ_NT) {
       const float2 p = src[i];
-      if (resident) {
+      if (RES) {
         rj_pts[i] = p;
         rj_pts[n + i] = dst[i];
       }
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(RJ_NT) void reject_kernel(const float2* __restrict_
     __syncthreads();
     if (done) break;
   }
-  if (resident)
+  if (RES)
     for (int i = tid; i < n; i += RJ_NT) keep[i] = pk[i];
   if (tid == 0) {
     out->status = done == 1 ? 0 : 1;
@@ -303,13 +306,18 @@ extern "C" int cfog_reject_outliers(cfog_ctx* ctx, const float* d_src, const flo
     return CFOG_EINVAL;
   static int attr = 1;
   if (attr == 1)
-    attr = hipFuncSetAttribute((const void*)cfog::reject_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+    attr = hipFuncSetAttribute((const void*)cfog::reject_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)cfog::reject_lds_bytes(cfog::RJ_LDS_POINTS)) == hipSuccess
                ? 0
                : -1;
   if (attr != 0) return CFOG_EHIP;
-  hipLaunchKernelGGL(cfog::reject_kernel, dim3(1), dim3(cfog::RJ_NT), cfog::reject_lds_bytes(n), (hipStream_t)stream,
-                     reinterpret_cast<const float2*>(d_src), reinterpret_cast<const float2*>(d_dst), n, threshold,
-                     d_keep, d_result);
+  const float2* src = reinterpret_cast<const float2*>(d_src);
+  const float2* dst = reinterpret_cast<const float2*>(d_dst);
+  if (n <= cfog::RJ_LDS_POINTS)
+    hipLaunchKernelGGL(cfog::reject_kernel<true>, dim3(1), dim3(cfog::RJ_NT), cfog::reject_lds_bytes(n),
+                       (hipStream_t)stream, src, dst, n, threshold, d_keep, d_result);
+  else
+    hipLaunchKernelGGL(cfog::reject_kernel<false>, dim3(1), dim3(cfog::RJ_NT), 0, (hipStream_t)stream, src, dst, n,
+                       threshold, d_keep, d_result);
   return hipGetLastError() == hipSuccess ? CFOG_OK : CFOG_EHIP;
 }
