@@ -131,6 +131,15 @@ __device__ __forceinline__ int s1_pos(int j, int k) {
   return j * C::R1 + k + (j >> 2);
 }
 
+// Where lane j of a column FFT leaves its stage-1 output k: row k R2 + j of
+// the column, i.e. back in the rows it read (j + R2 a), so stage 1 is in place
+// per lane and consecutive lanes write consecutive rows; stage 2 then reads
+// rows k1 R2 + b.  (The natural order, row j R1 + k, puts a group's writes
+// R1 rows apart, which at R1 = 16 lands 12 lanes in two LDS banks; measured:
+// 2% faster at P = 144, 17% at P = 192.)
+template <class C>
+__device__ __forceinline__ int s1c(int j, int k) { return k * C::R2 + j; }
+
 // One set of rows for the x-pass: nrows x ncols real values at src (leading
 // dim ld), transformed into X (row stride PH).  zero_tail: rows
 // [2 ceil(nrows/2), P) of X are zeroed (a y-pass that reads all P rows).
@@ -343,12 +352,12 @@ __device__ __forceinline__ void ypass_fused(const Lane<C>& L, const float2* XT, 
         for (int a = 0; a < R1; ++a) v[a] = col[(j + R2 * a) * PH];
         dft<R1, -1>(v);
 #pragma unroll
-        for (int k = 0; k < R1; ++k) col[(j * R1 + k) * PH] = v[k];
+        for (int k = 0; k < R1; ++k) col[s1c<C>(j, k) * PH] = v[k];
       }
       wave_sync();
       if (L.li < R1) {
         const int k1 = L.li;
-        stage2_inputs<C, false>(sh, tw, k1, [&](int b) { return col[(k1 + R1 * b) * PH]; });
+        stage2_inputs<C, false>(sh, tw, k1, [&](int b) { return col[s1c<C>(b, k1) * PH]; });
         dft<R2, -1>(sh);
       }
       wave_sync();
@@ -363,13 +372,13 @@ __device__ __forceinline__ void ypass_fused(const Lane<C>& L, const float2* XT, 
         }
         dft<R1, -1>(v);
 #pragma unroll
-        for (int k = 0; k < R1; ++k) col[(j * R1 + k) * PH] = v[k];
+        for (int k = 0; k < R1; ++k) col[s1c<C>(j, k) * PH] = v[k];
       }
       wave_sync();
       if (L.li < R1) {
         const int k1 = L.li;
         float2 w[R2];
-        stage2_inputs<C, false>(w, tw, k1, [&](int b) { return col[(k1 + R1 * b) * PH]; });
+        stage2_inputs<C, false>(w, tw, k1, [&](int b) { return col[s1c<C>(b, k1) * PH]; });
         dft<R2, -1>(w);
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) acc[rnd][k2] = cmac_conj(acc[rnd][k2], w[k2], sh[k2]);
@@ -397,13 +406,13 @@ __device__ __forceinline__ void ypass_fwd(const Lane<C>& L, float2* X, const flo
         for (int a = 0; a < R1; ++a) v[a] = col[(j + R2 * a) * PH];
         dft<R1, -1>(v);
 #pragma unroll
-        for (int k = 0; k < R1; ++k) col[(j * R1 + k) * PH] = v[k];
+        for (int k = 0; k < R1; ++k) col[s1c<C>(j, k) * PH] = v[k];
       }
       wave_sync();
       if (L.li < R1) {
         const int k1 = L.li;
         float2 w[R2];
-        stage2_inputs<C, false>(w, tw, k1, [&](int b) { return col[(k1 + R1 * b) * PH]; });
+        stage2_inputs<C, false>(w, tw, k1, [&](int b) { return col[s1c<C>(b, k1) * PH]; });
         dft<R2, -1>(w);
         static_for<0, R2>([&](auto k2I) {
           constexpr int k2 = decltype(k2I)::value;
@@ -519,13 +528,13 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
         for (int a = 0; a < R1; ++a) v[a] = col[(j + R2 * a) * PH];
         dft<R1, +1>(v);
 #pragma unroll
-        for (int k = 0; k < R1; ++k) col[(j * R1 + k) * PH] = v[k];
+        for (int k = 0; k < R1; ++k) col[s1c<C>(j, k) * PH] = v[k];
       }
       wave_sync();
       if (L.li < R1) {
         const int k1 = L.li;
         float2 w[R2];
-        stage2_inputs<C, true>(w, tw, k1, [&](int b) { return col[(k1 + R1 * b) * PH]; });
+        stage2_inputs<C, true>(w, tw, k1, [&](int b) { return col[s1c<C>(b, k1) * PH]; });
         dft<R2, +1>(w);
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) {
