@@ -121,13 +121,15 @@ __device__ __forceinline__ void stage2_inputs(float2 (&w)[C::R2], const float2* 
 }
 
 // Where lane j of an x-pass group leaves stage-1 output k in its pair's row
-// buffer (2 PH = P + 2 slots): j R1 + k plus j / 4, which spreads the lanes'
-// writes over more LDS banks (unpadded, the stride R1 puts lanes j and j + 8
-// in one bank at R1 = 12 and every lane in two banks at R1 = 16; measured 1%
-// faster at P = 144, 12% at P = 192).
+// buffer (2 PH = P + 2 slots), chosen so that neither the group's writes
+// (fixed k) nor its stage-2 reads (fixed j) share LDS banks: j R1 + k plus
+// j / 4 (unpadded, the stride R1 puts lanes j and j + 8 in one bank at
+// R1 = 12: 1% at P = 144, 12% at P = 192), and for R1 = 16 with R2 >= 10,
+// where that still pairs lanes, k R2 + j plus k / 8 (a further 5% at P = 192).
 template <class C>
 __device__ __forceinline__ int s1_pos(int j, int k) {
-  static_assert((C::R2 - 1) / 4 <= 2, "the padded stage-1 outputs must fit the pair's two rows");
+  static_assert((C::R2 - 1) / 4 <= 2 && (C::R1 - 1) / 8 <= 1, "the stage-1 outputs must fit the pair's two rows");
+  if constexpr (C::R1 == 16 && C::R2 >= 10) return k * C::R2 + j + (k >> 3);
   return j * C::R1 + k + (j >> 2);
 }
 
