@@ -150,7 +150,7 @@ def test_match_plain_256_workload_full(cf):
 @pytest.mark.parametrize("N,r,H,seed", [
     (8, 3, 40, 11), (9, 0, 30, 12), (16, 4, 48, 13), (21, 5, 64, 14), (30, 9, 80, 15),
     (40, 20, 100, 16), (47, 12, 100, 17), (60, 20, 120, 18), (80, 10, 128, 19), (77, 21, 160, 20),
-    (100, 20, 160, 21), (110, 17, 180, 22), (126, 15, 200, 23), (130, 15, 200, 24),
+    (100, 20, 160, 21), (110, 17, 180, 22), (126, 15, 200, 23), (130, 15, 200, 24), (33, 3, 60, 25),
 ])
 def test_match_plans_and_ragged_sizes(cf, N, r, H, seed):
     """Template/radius combinations that select every FFT size and leave
@@ -344,7 +344,7 @@ def test_fft_size_independence(cf):
     cps = synth.random_cps(np.random.default_rng(5), H, H, N, r, 6)
     oracle_pts = [parity.oracle_point(A, B, cp, N, r) for cp in cps]
     sizes = []
-    for P in (60, 64, 72, 80, 96, 128, 160, 192):
+    for P in (60, 64, 72, 80, 90, 96, 100, 108, 120, 128, 144, 160, 180, 192):
         cf.set_plan(N, r, P)
         assert cf.plan_for(N, r) == P
         res, surf = _run_match(cf, A, B, cps, N, r)
