@@ -192,14 +192,23 @@ __global__ __launch_bounds__(HR_NT) void harris_grid_kernel(HarrisArgs a) {
 }
 
 template <int R>
+static int set_harris_attr() {
+  return hipFuncSetAttribute((const void*)harris_grid_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)harris_lds_bytes()) == hipSuccess
+             ? 0
+             : -2;
+}
+
+int init_harris_attributes() {
+  if (set_harris_attr<0>() || set_harris_attr<1>() || set_harris_attr<2>() || set_harris_attr<3>() ||
+      set_harris_attr<4>() || set_harris_attr<5>() || set_harris_attr<6>() || set_harris_attr<7>() ||
+      set_harris_attr<8>())
+    return -2;
+  return 0;
+}
+
+template <int R>
 static int launch_harris(const HarrisArgs& a, hipStream_t st) {
-  static int attr = 1;
-  if (attr == 1)
-    attr = hipFuncSetAttribute((const void*)harris_grid_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)harris_lds_bytes()) == hipSuccess
-               ? 0
-               : -1;
-  if (attr != 0) return -2;
   hipLaunchKernelGGL(harris_grid_kernel<R>, dim3(a.n * a.n), dim3(HR_NT), harris_lds_bytes(), st, a);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }

@@ -55,9 +55,13 @@ bool plan_fits(const FftPlan* p, int N, int r);
 // Largest per-workgroup template-spectrum workspace among the sizes the
 // autotuner considers for (N, r).
 size_t max_tg_bytes(int N, int r);
-// Set the dynamic-LDS limits of every matcher and extraction kernel (once per
-// process; must precede any stream capture).  0 on success.
+// Set the dynamic-LDS limits of every kernel of the library on the current
+// device (once per device, from context creation, before any stream capture;
+// safe to call from several host threads).  0 on success.
 int init_kernel_attributes();
+int init_direct_attributes();
+int init_harris_attributes();
+int init_outlier_attributes();
 // Workgroups of this plan that fit the device at once.
 int plan_slots(const FftPlan* p, int num_cus);
 // Launch the FFT matcher.  d_jobs == nullptr: n_tasks control points of job0

@@ -209,8 +209,6 @@ __global__ __launch_bounds__(D_NT) void match_direct_kernel(MatchJob jd, DirectG
   }
 }
 
-static int g_direct_attr = 1;
-
 size_t direct_workspace_bytes(const cfog_job*, int, int, int) { return 0; }
 
 template <int NB>
@@ -218,17 +216,16 @@ static void launch_nb(const MatchJob& d, const DirectGeom& g, int blocks, hipStr
   hipLaunchKernelGGL(match_direct_kernel<NB>, dim3(blocks), dim3(D_NT), g.lds, st, d, g);
 }
 
+int init_direct_attributes() {
+  const void* k[D_NB] = {(const void*)match_direct_kernel<1>, (const void*)match_direct_kernel<2>,
+                         (const void*)match_direct_kernel<3>, (const void*)match_direct_kernel<4>,
+                         (const void*)match_direct_kernel<5>};
+  for (int i = 0; i < D_NB; ++i)
+    if (hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess) return -2;
+  return 0;
+}
+
 int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, int obj, void*, int num_cus, hipStream_t st) {
-  if (g_direct_attr == 1) {
-    const void* k[D_NB] = {(const void*)match_direct_kernel<1>, (const void*)match_direct_kernel<2>,
-                           (const void*)match_direct_kernel<3>, (const void*)match_direct_kernel<4>,
-                           (const void*)match_direct_kernel<5>};
-    g_direct_attr = 0;
-    for (int i = 0; i < D_NB; ++i)
-      if (hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) != hipSuccess)
-        g_direct_attr = -2;
-  }
-  if (g_direct_attr != 0) return -2;
   for (int i = 0; i < n_jobs; ++i) {
     const cfog_job& j = jobs[i];
     const DirectGeom g = direct_geom(j.N, j.r);

@@ -38,6 +38,8 @@
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <algorithm>
+#include <mutex>
+#include <vector>
 #include "dft.hpp"
 #include "epilogue.hpp"
 #include "kernels.hpp"
@@ -800,11 +802,18 @@ int init_match_fft_attributes() {
 }
 
 int init_kernel_attributes() {
-  static int rc = 1;
-  if (rc == 1) {
-    rc = init_match_fft_attributes();
-    if (rc == 0) rc = init_extract_attributes();
-  }
+  static std::mutex mu;
+  static std::vector<int> done;  // devices already set up
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -2;
+  std::lock_guard<std::mutex> lock(mu);
+  if (std::find(done.begin(), done.end(), dev) != done.end()) return 0;
+  int rc = init_match_fft_attributes();
+  if (rc == 0) rc = init_extract_attributes();
+  if (rc == 0) rc = init_direct_attributes();
+  if (rc == 0) rc = init_harris_attributes();
+  if (rc == 0) rc = init_outlier_attributes();
+  if (rc == 0) done.push_back(dev);
   return rc;
 }
 

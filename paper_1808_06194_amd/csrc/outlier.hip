@@ -297,6 +297,13 @@ __global__ __launch_bounds__(RJ_NT) void reject_kernel(const float2* __restrict_
   }
 }
 
+int init_outlier_attributes() {
+  return hipFuncSetAttribute((const void*)reject_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)reject_lds_bytes(RJ_LDS_POINTS)) == hipSuccess
+             ? 0
+             : -2;
+}
+
 }  // namespace cfog
 
 extern "C" int cfog_reject_outliers(cfog_ctx* ctx, const float* d_src, const float* d_dst, int32_t n, float threshold,
@@ -304,13 +311,6 @@ extern "C" int cfog_reject_outliers(cfog_ctx* ctx, const float* d_src, const flo
   if (!ctx || !d_src || !d_dst || !d_keep || !d_result || n < 10 || n > (1 << 20) || !(threshold >= 0.f) ||
       ((uintptr_t)d_src % 8) != 0 || ((uintptr_t)d_dst % 8) != 0 || ((uintptr_t)d_result % 8) != 0)
     return CFOG_EINVAL;
-  static int attr = 1;
-  if (attr == 1)
-    attr = hipFuncSetAttribute((const void*)cfog::reject_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)cfog::reject_lds_bytes(cfog::RJ_LDS_POINTS)) == hipSuccess
-               ? 0
-               : -1;
-  if (attr != 0) return CFOG_EHIP;
   const float2* src = reinterpret_cast<const float2*>(d_src);
   const float2* dst = reinterpret_cast<const float2*>(d_dst);
   if (n <= cfog::RJ_LDS_POINTS)
