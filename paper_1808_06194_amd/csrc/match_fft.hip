@@ -31,10 +31,12 @@
 // G = max(R1, R2) lanes of one wave:
 //   stage 1 (lane j < R2):  t[j R1 + k1] = sum_a x[j + R2 a] W_R1^{a k1}
 //   stage 2 (lane k1 < R1): X[k1 + R1 k2] = sum_j W_P^{k1 j} t[j R1 + k1] W_R2^{j k2}
-// with the small DFTs as unrolled register codelets (dft.hpp) and the
-// exchange between stages through the FFT's own LDS rows or column.  Only the
-// x -> y transposes need workgroup barriers (2 per channel in the fused
-// layout, 4 otherwise).
+// with the small DFTs as unrolled register codelets (dft.hpp), the twiddles
+// W_P^{k1 j} formed by recurrence from W_P^{k1}, and the exchange between
+// stages through the FFT's own LDS row or column, with t at positions that
+// keep a group's accesses in distinct banks (s1_pos, s1c).  Only the x -> y
+// transposes need workgroup barriers (2 per channel in the fused layout, 4
+// otherwise).
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <algorithm>
