@@ -169,6 +169,32 @@ def test_match_plans_and_ragged_sizes(cf, N, r, H, seed):
     print("stats", stats, flush=True)
 
 
+@pytest.mark.parametrize("path", ["plain", "batched", "mfma"])
+def test_match_different_image_sizes_and_search_centres(cf, path):
+    """A and B of different sizes, each control point's search centre given in
+    B's own coordinates (the images need not share a frame): both are crops at
+    different offsets of one co-registered pair, so the search centre of
+    (x, y) is (x + ax - bx0, y + ay - by0).  Against the oracle on the crops."""
+    spec = synth.PairSpec(220, 220, 40, (2.0, 9.0), 12, 4)
+    A0, B0, s = synth.make_pair(spec, (123, 0))
+    ay, ax, by0, bx0 = 20, 10, 35, 3
+    A = np.ascontiguousarray(A0[ay:ay + 160, ax:ax + 150])   # 160 x 150
+    B = np.ascontiguousarray(B0[by0:by0 + 130, bx0:bx0 + 190])  # 130 x 190
+    N, r = 24, 6
+    _say(f"match A 160x150 / B 130x190, search centres in B's frame, path {path}")
+    pts = [(40, 40), (75, 60), (110, 45), (60, 90), (95, 100), (120, 80)]
+    cps = np.array([[x, y, x + ax - bx0, y + ay - by0] for x, y in pts], np.int32)
+    flags = {"plain": cf.PATH_PLAIN_FFT, "batched": cf.PATH_BATCHED_FFT, "mfma": cf.PATH_MFMA_BF16}[path]
+    res, surf = _run_match(cf, A, B, cps, N, r, flags=flags)
+    tol = parity.BF16_TOL if path == "mfma" else parity.SURF_TOL
+    stats = {}
+    for k, cp in enumerate(cps):
+        S, E1, E2 = parity.oracle_point(A, B, cp, N, r)
+        parity.check_point(k, res, S, E1, E2, r, surf[k], stats, tol=tol)
+    print("stats", stats, flush=True)
+    assert np.all(res["status"] == 0)
+
+
 def test_match_exact_shift_is_recovered_exactly(cf):
     """B is a crop of A's canvas shifted by s: S(s) = 0 up to FP32 and the
     offset must be s for every control point."""
