@@ -41,6 +41,7 @@ constexpr int D_NW = 8;            // waves per workgroup
 constexpr int D_NT = 64 * D_NW;
 constexpr int D_TPAD = 15;         // zero template rows above and below
 constexpr int D_RB = 8;            // rows staged per batch of loads
+constexpr int D_PW = 4;            // waves whose partial correlations are summed together
 
 struct DirectGeom {
   int N, r, K, nblk, NP, Ws;
@@ -64,7 +65,9 @@ static DirectGeom direct_geom(int N, int r) {
   g.SLD = (g.NP + 16 * g.nblk + 2) / 2;
   g.t_bytes = (size_t)g.TROWS * g.TLD * 4;
   const size_t sb = (size_t)g.Ws * g.SLD * 4;
-  const size_t c = (size_t)g.K * g.K * 4 + 16 * D_NW;
+  // after the channels: Cs (K x K) and D_PW partial surfaces; the epilogue's
+  // argmin scratch sits behind Cs once the partials are summed
+  const size_t c = (size_t)g.K * g.K * 4 * (1 + D_PW) + 16 * D_NW;
   g.lds = std::max(g.t_bytes + sb, c);
   return g;
 }
@@ -186,10 +189,17 @@ __global__ __launch_bounds__(D_NT) void match_direct_kernel(MatchJob jd, DirectG
         }
       }
     }
-    __syncthreads();  // all MFMA reads of T/S are done: Cs may overwrite them
-    // sum the waves' partial correlations in wave order (deterministic)
-    for (int w = 0; w < D_NW; ++w) {
-      if (wv == w) {
+    __syncthreads();  // all MFMA reads of T/S are done: Cs and the partials may overwrite them
+    // sum the waves' partial correlations in wave order (deterministic): D_PW
+    // waves at a time store theirs side by side behind Cs, then every thread
+    // adds the D_PW values of its elements into Cs.  (Adding wave by wave into
+    // Cs serialised each wave's read-modify-writes: about 8% of a point's
+    // time at K = 65.)
+    const int KK = K * K;
+    float* part = Cs + KK;
+    for (int w0 = 0; w0 < D_NW; w0 += D_PW) {
+      if (wv >= w0 && wv < w0 + D_PW) {
+        float* mine = part + (size_t)(wv - w0) * KK;
 #pragma unroll
         for (int m = 0; m < NB; ++m)
 #pragma unroll
@@ -197,11 +207,15 @@ __global__ __launch_bounds__(D_NT) void match_direct_kernel(MatchJob jd, DirectG
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int ux = 16 * m + 4 * kg + q, uy = 16 * n + l16;
-              if (ux < K && uy < K) {
-                float* p = Cs + uy * K + ux;
-                *p = (w == 0 ? 0.f : *p) + acc[m][n][q];
-              }
+              if (ux < K && uy < K) mine[uy * K + ux] = acc[m][n][q];
             }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < KK; i += D_NT) {
+        float s = w0 == 0 ? 0.f : Cs[i];
+#pragma unroll
+        for (int w = 0; w < D_PW; ++w) s += part[(size_t)w * KK + i];
+        Cs[i] = s;
       }
       __syncthreads();
     }
