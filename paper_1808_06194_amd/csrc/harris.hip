@@ -39,9 +39,11 @@ struct HarrisArgs {
 constexpr int HR_LD = HR_MAX_CHIP;  // LDS row stride of every chip array
 constexpr int HR_NW = HR_NT / 64;
 
-// Dynamic LDS: five 64 x 64 arrays (80 KB, so two chips share a CU).  The
-// chip is dead once the gradients exist and shares storage with the first
-// smoothed product; the response reuses gx.
+// Dynamic LDS: five 64 x 64 arrays (80 KB, so two chips share a CU; the
+// argmax scratch lives in a dead array, as any static LDS would push a
+// workgroup past half of the CU's 160 KB).  The chip is dead once the
+// gradients exist and shares storage with the first smoothed product; the
+// response reuses gx.
 static size_t harris_lds_bytes() { return (size_t)5 * HR_LD * HR_LD * sizeof(float); }
 
 template <int R>
@@ -55,8 +57,8 @@ __global__ __launch_bounds__(HR_NT) void harris_grid_kernel(HarrisArgs a) {
   float* tc = tb + CC;
   float* img = ta;  // read only by the gradient pass
   float* Rv = gx;   // written by the vertical pass, after the last gx read
-  __shared__ float bestv[HR_NW];
-  __shared__ int besti[HR_NW];
+  float* bestv = tb;                                 // HR_NW values, after the vertical pass
+  int* besti = reinterpret_cast<int*>(tb + HR_NW);   // their indices
   const int cell = blockIdx.x, ci = cell / a.n, cj = cell - ci * a.n;
   // chip of cell (ci, cj): centred at ((2 cj + 1) W / 2n, (2 ci + 1) H / 2n), clipped
   const int cy = (int)(((int64_t)(2 * ci + 1) * a.H) / (2 * a.n));
