@@ -177,8 +177,9 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain device-to-device copy of this many MiB "
                          "(a counter calibration point for HBM traffic)")
-    ap.add_argument("--serve-rates", default="200:15,1000:5,2000:4,4000:3",
-                    help="serve: rate:seconds phases (the first one gives the latency figures)")
+    ap.add_argument("--serve-rates", default="200:15,1000:5,2000:4,4000:3,6000:3",
+                    help="serve: rate:seconds phases (the first one gives the latency figures; the value is "
+                         "the highest CP rate any phase served, which the last rate is meant to saturate)")
     ap.add_argument("--serve-pairs", type=int, default=32)
     ap.add_argument("--serve-budget-gib", type=float, default=0.0,
                     help="serve: device memory budget (0: 80%% of free memory)")
