@@ -132,8 +132,9 @@ struct ExTile {
 
 // M > 0: the channel count fixed at compile time (the channel loop unrolls
 // and the orientation smoothing's register rotation disappears); M = 0 reads
-// it from the arguments.
-template <int R, int M>
+// it from the arguments.  S1: scheme 1 instead of Eq. 2, fixed at compile
+// time so that the per-pixel channel value carries no branch.
+template <int R, int M, bool S1>
 __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   using T = ExTile<R>;
   constexpr int IW = T::IW, IH = T::IH, GW = T::GW, GH = T::GH, GWP = T::GWP;
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
     }
   }
   // scheme 1 keeps (|g|, orientation bin position in [0, m)) instead of (gx, gy)
-  if (a.scheme == 1) {
+  if constexpr (S1) {
     const float bscale = (float)m / 3.14159265358979f;
 #pragma unroll
     for (int it = 0; it < (GH * GW + EX_NT - 1) / EX_NT; ++it) {
@@ -257,7 +258,6 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
       }
     }
   };
-  const bool s1 = a.scheme == 1;
   auto channel = [&](int k) {
     const float ck = a.cs[k], sk = a.sn[k];
     const float kf = (float)k, mf = (float)m;
@@ -265,11 +265,12 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
     // |cos(theta_k) gx + sin(theta_k) gy| (Eq. 2), or for scheme 1
     // |g| max(0, 1 - circular distance of the bin position to k)
     auto gk = [&](float u, float v) {
-      if (s1) {
+      if constexpr (S1) {
         const float d = fabsf(v - kf);
         return u * fmaxf(0.f, 1.f - fminf(d, mf - d));
       }
-      return fabsf(fmaf(ck, u, sk * v));
+      else
+        return fabsf(fmaf(ck, u, sk * v));
     };
     float* hb = Hb;
     // horizontal pass: each thread four consecutive outputs of one row from
@@ -689,31 +690,41 @@ size_t extract_workspace_bytes(int H, int W) {
   return sizeof(double) * ((size_t)H * ntx + nty * (size_t)W);
 }
 
-template <int R>
-static int launch_r(const ExtractArgs& a, hipStream_t st) {
+template <int R, bool S1>
+static int launch_rs(const ExtractArgs& a, hipStream_t st) {
   const size_t lds = lds_bytes(a.m, R);
   dim3 grid(a.ntx, a.nty);
   if constexpr (R == 3) {
     if (a.m == 9) {  // the paper's parameters (sigma 0.8, nine orientations)
-      hipLaunchKernelGGL((cfog_extract_kernel<R, 9>), grid, dim3(EX_NT), lds, st, a);
+      hipLaunchKernelGGL((cfog_extract_kernel<R, 9, S1>), grid, dim3(EX_NT), lds, st, a);
       return hipGetLastError() == hipSuccess ? 0 : -2;
     }
   }
-  hipLaunchKernelGGL((cfog_extract_kernel<R, 0>), grid, dim3(EX_NT), lds, st, a);
+  hipLaunchKernelGGL((cfog_extract_kernel<R, 0, S1>), grid, dim3(EX_NT), lds, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 template <int R>
-static int set_attr() {
-  if (hipFuncSetAttribute((const void*)cfog_extract_kernel<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+static int launch_r(const ExtractArgs& a, hipStream_t st) {
+  return a.scheme == 1 ? launch_rs<R, true>(a, st) : launch_rs<R, false>(a, st);
+}
+
+template <int R, bool S1>
+static int set_attr_s() {
+  if (hipFuncSetAttribute((const void*)cfog_extract_kernel<R, 0, S1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)kMaxLds) != hipSuccess)
     return -2;
   if constexpr (R == 3) {
-    if (hipFuncSetAttribute((const void*)cfog_extract_kernel<R, 9>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    if (hipFuncSetAttribute((const void*)cfog_extract_kernel<R, 9, S1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)kMaxLds) != hipSuccess)
       return -2;
   }
   return 0;
+}
+
+template <int R>
+static int set_attr() {
+  return set_attr_s<R, false>() != 0 || set_attr_s<R, true>() != 0 ? -2 : 0;
 }
 
 template <int C>
