@@ -555,14 +555,17 @@ def test_batched_objective_and_subpixel_equal_plain(cf):
 
 # ------------------------------------------------------------ CFOG scheme 1
 
-@pytest.mark.parametrize("H,W,m,seed", [(96, 130, 9, 91), (64, 64, 6, 92), (300, 257, 12, 93)])
-def test_extract_scheme1_matches_oracle(cf, H, W, m, seed):
-    _say(f"extract scheme 1 {H}x{W} m={m} seed={seed}")
+@pytest.mark.parametrize("H,W,m,sigma,seed", [(96, 130, 9, 0.8, 91), (64, 64, 6, 0.8, 92), (300, 257, 12, 0.8, 93),
+                                              (80, 150, 9, 0.5, 95), (70, 90, 8, 2.0, 96)])
+def test_extract_scheme1_matches_oracle(cf, H, W, m, sigma, seed):
+    """Scheme 1 at the paper's parameters and at other channel counts and
+    Gaussian radii (each radius and scheme is its own compiled kernel)."""
+    _say(f"extract scheme 1 {H}x{W} m={m} sigma={sigma} seed={seed}")
     A, _, _ = synth.make_pair(synth.PairSpec(H, W, max(4, H * W // 1500), (3.0, 15.0), max(2, H * W // 3000), 4),
                               (seed, 0))
-    vol, sat = cf.cfog_extract(_dev(A), m=m, scheme=1)
+    vol, sat = cf.cfog_extract(_dev(A), m=m, sigma=sigma, scheme=1)
     torch.cuda.synchronize()
-    D = O.cfog(A.astype(np.float64), m=m, scheme=1)
+    D = O.cfog(A.astype(np.float64), m=m, sigma=sigma, scheme=1)
     parity.check_volume(vol.cpu().numpy(), D)
     Q = np.sum(vol.cpu().numpy().astype(np.float64) ** 2, axis=0)
     np.testing.assert_allclose(sat.cpu().numpy(), O.sat(Q), rtol=1e-12, atol=1e-9 * O.sat(Q)[-1, -1])
