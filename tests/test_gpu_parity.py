@@ -330,6 +330,33 @@ def test_match_plain_2048_full_size_sampled(cf):
     print("stats", stats, flush=True)
 
 
+@pytest.mark.parametrize("path", ["fft", "mfma"])
+def test_match_precision_4096_full_size_sampled(cf, path):
+    """The 4096^2 workload (10,000 random CPs, template 128, radius 32) in the
+    launch configuration the benchmark times: the FP32 FFT path (P = 192)
+    and the BF16 MFMA path.  Every point is checked for self-consistency; a
+    seeded sample against the FP64 oracle, at each path's surface bound."""
+    spec = synth.PairSpec(4096, 4096, 3200, (3.0, 40.0), 1200, 20)
+    A, B, s = synth.make_pair(spec, (3, 0))
+    cps = synth.random_cps(np.random.default_rng(np.random.SeedSequence([3, 1])), 4096, 4096, 128, 32, 10000)
+    N, r, K = 128, 32, 65
+    _say("match precision_4096", path, A.shape, len(cps), N, r)
+    flags = cf.PATH_PLAIN_FFT if path == "fft" else cf.PATH_MFMA_BF16
+    res, surf = _run_match(cf, A, B, cps, N, r, flags=flags)
+    assert np.all(res["status"] == 0)
+    flat = surf.reshape(len(cps), -1)
+    i = np.argmin(flat, axis=1)
+    assert np.array_equal(i % K - r, res["dx"]) and np.array_equal(i // K - r, res["dy"])
+    assert np.array_equal(flat[np.arange(len(cps)), i], res["best"])
+    rng = np.random.default_rng(4096)
+    stats = {}
+    tol = parity.SURF_TOL if path == "fft" else parity.BF16_TOL
+    for k in rng.choice(len(cps), 3, replace=False):
+        S, E1, E2 = parity.oracle_point(A, B, cps[k], N, r)
+        parity.check_point(int(k), res, S, E1, E2, r, surf[k], stats, tol=tol)
+    print("stats", stats, flush=True)
+
+
 def test_extract_large_image_sampled(cf):
     """A 4100 x 4096 image: sampled windows against the oracle, and the SAT
     against box sums of the returned volume (a property at any size)."""
