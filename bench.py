@@ -220,10 +220,15 @@ def main():
         imgs.append((dA, vA, sA))
         imgs.append((dB, vB, sB))
         jobs.append(cfog.Job(vA, sA, vB, sB, torch.from_numpy(p["cps"]).to(dev), p["N"], p["r"]))
-    # the images are extracted on two streams (every second image on the
-    # other one, each stream with its own workspace), joined before matching
+    # CFOG volumes: all images in one batched extraction call (up to 8 images
+    # per launch); pixel-wise HOG: the images on two streams (every second
+    # image on the other one, each stream with its own workspace), joined
+    # before matching
     ws_bytes = max(cfog.extract_workspace_size(*img[0].shape) for img in imgs)
     ws_ext = [torch.empty(ws_bytes, dtype=torch.uint8, device=dev) for _ in range(2)]
+    ws_batch = torch.empty(max(1, cfog.extract_batch_workspace_size([img[0].shape for img in imgs])),
+                           dtype=torch.uint8, device=dev)
+    batch_imgs, batch_vols, batch_sats = ([img[k] for img in imgs] for k in range(3))
     n_cps = sum(len(p["cps"]) for p in pairs)
     stream = torch.cuda.current_stream()
     side = torch.cuda.Stream(device=dev)  # default priority
@@ -233,17 +238,17 @@ def main():
     def step(evs=None):
         if evs:
             evs[0].record(stream)
-        fork.record(stream)
-        side.wait_event(fork)
-        for i, (img, vol, sat) in enumerate(imgs):
-            st = stream if i % 2 == 0 else side
-            if desc == "fhog":
+        if desc == "fhog":
+            fork.record(stream)
+            side.wait_event(fork)
+            for i, (img, vol, sat) in enumerate(imgs):
+                st = stream if i % 2 == 0 else side
                 cfog.fhog_extract(img, vol=vol, sat=sat, stream=st, workspace=ws_ext[i % 2])
-            else:
-                cfog.cfog_extract(img, m=m, vol=vol, sat=sat, stream=st, workspace=ws_ext[i % 2],
-                                  scheme=1 if desc == "scheme1" else 2)
-        join.record(side)
-        stream.wait_event(join)
+            join.record(side)
+            stream.wait_event(join)
+        else:
+            cfog.cfog_extract_batch(batch_imgs, m=m, vols=batch_vols, sats=batch_sats, stream=stream,
+                                    workspace=ws_batch, scheme=1 if desc == "scheme1" else 2)
         if evs:
             evs[1].record(stream)
         cfog.match_batch(jobs, m=m, flags=flags, stream=stream)

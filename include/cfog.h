@@ -139,6 +139,32 @@ int cfog_extract_fhog(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, i
  * image: 8 * (H * ceil(W/64) + ceil(H/32) * W). */
 size_t cfog_extract_workspace_size(int32_t H, int32_t W);
 
+/* One image of cfog_extract_batch: the arguments of cfog_extract that differ
+ * between images (same meaning, layout and ownership). */
+typedef struct cfog_image {
+  const float* d_img;  /* DEVICE [H][row_stride] fp32 */
+  int64_t row_stride;  /* >= W, in elements */
+  int32_t H, W;
+  float* d_vol;        /* DEVICE out [m][H][W] fp32 */
+  double* d_sat;       /* DEVICE out [(H+1)][(W+1)] fp64, or NULL for no SAT */
+} cfog_image;
+
+/* cfog_extract_batch - cfog_extract_scheme (Section III-F, Eq. 2 or scheme 1)
+ * of n images with the same m, sigma, radius and scheme, in one stream-ordered
+ * call: up to 8 images share each launch, which saves the launch boundaries
+ * of per-image calls.  Each image's outputs are bit-identical to those of
+ * cfog_extract_scheme on it.
+ *   imgs        HOST array of n images (read during the call only).
+ *   d_ws        device workspace of ws_bytes >=
+ *               cfog_extract_batch_workspace_size(imgs, n), or NULL for the
+ *               context's (then calls on several streams must not overlap).
+ * Errors as for cfog_extract_scheme, checked for every image before any work
+ * is queued; CFOG_EINVAL also for n < 0, or imgs NULL with n > 0.  n = 0
+ * queues nothing.  The workspace size is 0 for n <= 0 or imgs NULL. */
+size_t cfog_extract_batch_workspace_size(const cfog_image* imgs, int32_t n);
+int cfog_extract_batch(cfog_ctx* ctx, const cfog_image* imgs, int32_t n, int32_t m, float sigma,
+                       int32_t gauss_radius, int32_t scheme, void* d_ws, size_t ws_bytes, void* stream);
+
 /* One control point: template centre (x, y) in A; search centre (bx, by) in B
  * (a georeferenced prediction; bx = x, by = y when A and B are co-registered). */
 typedef struct {

@@ -38,7 +38,8 @@ NO_SPLIT = 0x800
 # Exported symbols, as declared in include/cfog.h.
 EXPORTS = (
     "cfog_ctx_create", "cfog_ctx_destroy", "cfog_ctx_last_error", "cfog_status_str",
-    "cfog_extract", "cfog_extract_scheme", "cfog_extract_fhog", "cfog_extract_workspace_size", "match_batch_workspace_size", "match_batch",
+    "cfog_extract", "cfog_extract_scheme", "cfog_extract_fhog", "cfog_extract_workspace_size",
+    "cfog_extract_batch_workspace_size", "cfog_extract_batch", "match_batch_workspace_size", "match_batch",
     "cfog_max_window", "cfog_fft_size", "cfog_set_plan", "cfog_plan_for", "cfog_harris_grid",
     "cfog_reject_outliers",
     "cfog_server_create", "cfog_server_destroy", "cfog_server_add_pair", "cfog_server_submit",
@@ -59,6 +60,13 @@ class cfog_job(ctypes.Structure):
         ("cps", ctypes.c_void_p), ("n_cps", ctypes.c_int32), ("N", ctypes.c_int32), ("r", ctypes.c_int32),
         ("pad_", ctypes.c_int32), ("out", ctypes.c_void_p), ("surfaces", ctypes.c_void_p),
         ("subpix", ctypes.c_void_p),
+    ]
+
+
+class cfog_image(ctypes.Structure):
+    _fields_ = [
+        ("d_img", ctypes.c_void_p), ("row_stride", ctypes.c_int64), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+        ("d_vol", ctypes.c_void_p), ("d_sat", ctypes.c_void_p),
     ]
 
 
@@ -118,6 +126,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cfog_extract_fhog.argtypes = [vp, vp, i32, i32, i64, i32, vp, vp, vp, sz, vp]
     lib.cfog_extract_workspace_size.argtypes = [i32, i32]
     lib.cfog_extract_workspace_size.restype = sz
+    lib.cfog_extract_batch_workspace_size.argtypes = [ctypes.POINTER(cfog_image), i32]
+    lib.cfog_extract_batch_workspace_size.restype = sz
+    lib.cfog_extract_batch.argtypes = [vp, ctypes.POINTER(cfog_image), i32, i32, ctypes.c_float, i32, i32, vp, sz, vp]
     lib.match_batch_workspace_size.argtypes = [vp, ctypes.POINTER(cfog_job), i32, i32, i32]
     lib.match_batch_workspace_size.restype = sz
     lib.match_batch.argtypes = [vp, ctypes.POINTER(cfog_job), i32, i32, i32, vp, sz, vp]
@@ -225,6 +236,44 @@ def cfog_extract(img: torch.Tensor, m: int = 9, sigma: float = 0.8, radius: int 
                                     workspace.numel() if workspace is not None else 0, _stream_ptr(stream))
     _check(rc, "cfog_extract")
     return vol, (sat if with_sat else None)
+
+
+def _image_array(imgs, vols, sats):
+    arr = (cfog_image * max(1, len(imgs)))()
+    for i, (img, vol, sat) in enumerate(zip(imgs, vols, sats)):
+        arr[i] = cfog_image(img.data_ptr(), img.stride(0), img.shape[0], img.shape[1], vol.data_ptr(), _ptr(sat))
+    return arr
+
+
+def extract_batch_workspace_size(shapes, with_sat: bool = True) -> int:
+    """Workspace bytes of cfog_extract_batch for images of the given (H, W)."""
+    arr = (cfog_image * max(1, len(shapes)))()
+    for i, (H, W) in enumerate(shapes):
+        arr[i] = cfog_image(None, W, H, W, None, 8 if with_sat else None)  # only the sizes and SAT presence count
+    return int(load().cfog_extract_batch_workspace_size(arr, len(shapes)))
+
+
+def cfog_extract_batch(imgs, m: int = 9, sigma: float = 0.8, radius: int = -1, with_sat: bool = True,
+                       vols=None, sats=None, stream=None, workspace: Optional[torch.Tensor] = None, scheme: int = 2):
+    """cfog_extract of several 2-D cuda fp32 images (same parameters) in one
+    call: lists of volumes (m, H, W) and SATs (H+1, W+1) (None without SATs)."""
+    for img in imgs:
+        if img.dim() != 2 or img.dtype != torch.float32 or not img.is_cuda or img.stride(1) != 1:
+            raise ValueError("every image must be a 2-D row-contiguous cuda float32 tensor")
+    if vols is None:
+        vols = [torch.empty((m, *img.shape), dtype=torch.float32, device=img.device) for img in imgs]
+    if not with_sat:
+        sats = [None] * len(imgs)
+    elif sats is None:
+        sats = [torch.empty((img.shape[0] + 1, img.shape[1] + 1), dtype=torch.float64, device=img.device)
+                for img in imgs]
+    arr = _image_array(imgs, vols, sats)
+    ctx = context(imgs[0].device.index if len(imgs) else None)
+    rc = load().cfog_extract_batch(ctx.handle, arr, len(imgs), m, float(sigma), int(radius), int(scheme),
+                                   _ptr(workspace), workspace.numel() if workspace is not None else 0,
+                                   _stream_ptr(stream))
+    _check(rc, "cfog_extract_batch")
+    return vols, (sats if with_sat else None)
 
 
 FHOG_CHANNELS = 36

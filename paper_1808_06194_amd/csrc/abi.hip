@@ -518,6 +518,55 @@ int cfog_extract_scheme(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W,
   return CFOG_OK;
 }
 
+static std::vector<cfog::ExtractImage> batch_images(const cfog_image* imgs, int32_t n) {
+  std::vector<cfog::ExtractImage> v((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    const cfog_image& c = imgs[i];
+    v[i] = cfog::ExtractImage{c.d_img, c.row_stride, c.H, c.W, c.d_vol, c.d_sat};
+  }
+  return v;
+}
+
+size_t cfog_extract_batch_workspace_size(const cfog_image* imgs, int32_t n) {
+  if (!imgs || n <= 0) return 0;
+  std::vector<int> H((size_t)n), W((size_t)n);
+  std::unique_ptr<bool[]> with_sat(new bool[(size_t)n]);
+  for (int i = 0; i < n; ++i) {
+    if (imgs[i].H < 1 || imgs[i].W < 1) return 0;
+    H[i] = imgs[i].H;
+    W[i] = imgs[i].W;
+    with_sat[i] = imgs[i].d_sat != nullptr;
+  }
+  return cfog::extract_batch_workspace_bytes(H.data(), W.data(), with_sat.get(), n);
+}
+
+int cfog_extract_batch(cfog_ctx* ctx, const cfog_image* imgs, int32_t n, int32_t m, float sigma,
+                       int32_t gauss_radius, int32_t scheme, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!ctx || n < 0 || (n > 0 && !imgs) || (scheme != 1 && scheme != 2)) return CFOG_EINVAL;
+  if (m < 1 || m > cfog::kMaxOrient || !(sigma > 0.f) || !isfinite(sigma)) return CFOG_EINVAL;
+  if (n == 0) return CFOG_OK;
+  for (int i = 0; i < n; ++i) {
+    const cfog_image& c = imgs[i];
+    if (!c.d_img || !c.d_vol || c.H < 1 || c.W < 1 || c.row_stride < c.W) return CFOG_EINVAL;
+    if (!aligned(c.d_sat, 8)) return CFOG_EINVAL;
+  }
+  const int R = gauss_radius < 0 ? (int)(4.0 * sigma + 0.5) : gauss_radius;
+  if (R > cfog::kMaxGaussRadius) return CFOG_EUNSUPPORTED;
+  if (cfog::extract_lds_bytes(m, R) > cfog::kMaxLds) return CFOG_EUNSUPPORTED;
+  if (!aligned(d_ws, 8)) return CFOG_EINVAL;
+  const size_t need = cfog_extract_batch_workspace_size(imgs, n);
+  if (need && d_ws && ws_bytes < need) return CFOG_ENOMEM;
+  if (need && !d_ws) {
+    const int rc = context_extract_ws(ctx, need, &d_ws);
+    if (rc != CFOG_OK) return rc;
+  }
+  const std::vector<cfog::ExtractImage> v = batch_images(imgs, n);
+  const int rc = cfog::launch_extract_batch(v.data(), n, m, sigma, R, d_ws, (hipStream_t)stream, scheme);
+  if (rc == -1) return CFOG_EUNSUPPORTED;
+  if (rc != 0) return record(ctx, hipGetLastError());
+  return CFOG_OK;
+}
+
 int cfog_extract_fhog(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride, int32_t cell,
                       float* d_vol, double* d_sat, void* d_ws, size_t ws_bytes, void* stream) {
   if (!ctx || !d_img || !d_vol || H < 1 || W < 1 || row_stride < W || cell < 1) return CFOG_EINVAL;

@@ -38,6 +38,8 @@
 // prefixes along each image column; kernel 3 adds the three terms in place.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <algorithm>
+#include <vector>
 #include "kernels.hpp"
 
 namespace cfog {
@@ -47,15 +49,24 @@ constexpr int EX_TY = 32;
 constexpr int EX_NT = 512;
 constexpr int EX_RUN = 4;  // outputs per thread in the sliding Gaussian passes
 
-struct ExtractArgs {
+// One image of an extraction launch (blockIdx.z selects it).
+struct ExImage {
   const float* img;
   int64_t stride;
-  int H, W, m;
   float* vol;
   double* sat;  // nullable
   double* rc;   // [H][ntx] right columns of the tile-local prefixes
   double* bt;   // [nty][W] bottom rows
-  int ntx, nty;
+  int H, W, ntx, nty;
+};
+
+// Images per launch: their tile grids are overlaid (the launch spans the
+// largest), and the tiles outside an image's own grid exit at once.
+constexpr int kExBatch = 8;
+
+struct ExtractArgs {
+  ExImage im[kExBatch];
+  int m;
   int scheme;                     // 2: Eq. 2; 1: binned orientation (scheme 1)
   float cs[kMaxOrient];           // cos(theta_k)
   float sn[kMaxOrient];           // sin(theta_k)
@@ -147,9 +158,11 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   float* img = Hb;                                   // IH * IW, read only by the gradient pass
   double* qx = reinterpret_cast<double*>(gxp);       // 64 wave carries per wave, after the last channel
   static_assert(2 * T::GP * sizeof(float) >= (EX_NT / 64) * 64 * sizeof(double), "wave carries");
+  const ExImage I = a.im[blockIdx.z];
+  if ((int)blockIdx.x >= I.ntx || (int)blockIdx.y >= I.nty) return;  // beyond this image's tiles
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * EX_TX, y0 = blockIdx.y * EX_TY;
-  const int H = a.H, W = a.W;
+  const int H = I.H, W = I.W;
   float w[R + 1];
 #pragma unroll
   for (int j = 0; j <= R; ++j) w[j] = a.w[j];
@@ -165,7 +178,7 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
       if (i < IH * IW) {
         const int r = i / IW, c = i - r * IW;
         const int gy = clampi(y0 - R - 1 + r, 0, H - 1), gx = clampi(x0 - R - 1 + c, 0, W - 1);
-        v[it] = __builtin_nontemporal_load(a.img + (int64_t)gy * a.stride + gx);
+        v[it] = __builtin_nontemporal_load(I.img + (int64_t)gy * I.stride + gx);
       }
     }
 #pragma unroll
@@ -244,7 +257,7 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
 #pragma unroll
   for (int p = 0; p < EX_RUN; ++p) { q[p] = 0.0; g0[p] = g1[p] = pm2[p] = pm1[p] = 0.f; }
   const size_t plane = (size_t)H * W;
-  float* const vout = a.vol + (size_t)min(y0 + orow, H - 1) * W + min(gxx, W - 1);
+  float* const vout = I.vol + (size_t)min(y0 + orow, H - 1) * W + min(gxx, W - 1);
   bool vok[EX_RUN];
 #pragma unroll
   for (int o = 0; o < EX_RUN; ++o) vok[o] = y0 + orow + o < H && gxx < W;
@@ -354,8 +367,8 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
       emit(0, d);
     }
   }
-  if (!a.sat) return;
-  tile_sat_prefix(q, qx, a.sat, a.rc, a.bt, H, W, a.ntx, y0, orow, oc, gxx);
+  if (!I.sat) return;
+  tile_sat_prefix(q, qx, I.sat, I.rc, I.bt, H, W, I.ntx, y0, orow, oc, gxx);
 }
 
 // ------------------------------------------------ pixel-wise HOG (FHOG)
@@ -554,14 +567,31 @@ constexpr int SAT_NT = 1024;
 constexpr int SAT_WAVES = SAT_NT / 64;
 constexpr int SAT_CH = 8;
 
+// The SAT carries and fix-up of up to kExBatch images per launch (the last
+// grid dimension selects the image; images without a SAT are skipped).
+struct SatImage {
+  double* sat;
+  double* rc;
+  double* bt;
+  int H, W, ntx, nty;
+};
+struct SatBatch {
+  SatImage im[kExBatch];
+};
+
 __device__ __forceinline__ double wave_excl_scan(double v, double& total) {
   const double inc = wave_incl_scan(v);
   total = __shfl(inc, 63, 64);
   return inc - v;
 }
 
-__global__ __launch_bounds__(SAT_NT) void sat_carry_kernel(double* rc, double* bt, int H, int W, int ntx, int nty,
-                                                           int row_blocks) {
+__global__ __launch_bounds__(SAT_NT) void sat_carry_kernel(SatBatch b) {
+  const SatImage I = b.im[blockIdx.y];
+  double* const rc = I.rc;
+  double* const bt = I.bt;
+  const int H = I.H, W = I.W, ntx = I.ntx, nty = I.nty;
+  const int row_blocks = (H + SAT_WAVES - 1) / SAT_WAVES;
+  if (!I.sat || (int)blockIdx.x >= row_blocks + (W + 63) / 64) return;  // beyond this image's blocks
   if ((int)blockIdx.x < row_blocks) {
     const int y = blockIdx.x * SAT_WAVES + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (y >= H) return;
@@ -624,9 +654,14 @@ __global__ __launch_bounds__(SAT_NT) void sat_carry_kernel(double* rc, double* b
 // and column 0.  One thread per pixel column of an extraction tile, 4 rows each.
 // The tile's values and carries are loaded first, so their latency overlaps
 // the corner's reduction.
-__global__ __launch_bounds__(EX_NT) void sat_fix_kernel(double* sat, const double* rc, const double* bt, int H,
-                                                        int W, int ntx) {
+__global__ __launch_bounds__(EX_NT) void sat_fix_kernel(SatBatch b) {
   __shared__ double corner_part[EX_NT / 64];
+  const SatImage I = b.im[blockIdx.z];
+  if (!I.sat || (int)blockIdx.x >= I.ntx || (int)blockIdx.y >= I.nty) return;  // beyond this image's tiles
+  double* const sat = I.sat;
+  const double* const rc = I.rc;
+  const double* const bt = I.bt;
+  const int H = I.H, W = I.W, ntx = I.ntx;
   const int tid = threadIdx.x, oc = tid & 63, wv = tid >> 6;
   const int tx = blockIdx.x, ty = blockIdx.y;
   const int x0 = tx * EX_TX, y0 = ty * EX_TY;
@@ -691,9 +726,8 @@ size_t extract_workspace_bytes(int H, int W) {
 }
 
 template <int R, bool S1>
-static int launch_rs(const ExtractArgs& a, hipStream_t st) {
+static int launch_rs(const ExtractArgs& a, dim3 grid, hipStream_t st) {
   const size_t lds = lds_bytes(a.m, R);
-  dim3 grid(a.ntx, a.nty);
   if constexpr (R == 3) {
     if (a.m == 9) {  // the paper's parameters (sigma 0.8, nine orientations)
       hipLaunchKernelGGL((cfog_extract_kernel<R, 9, S1>), grid, dim3(EX_NT), lds, st, a);
@@ -705,8 +739,8 @@ static int launch_rs(const ExtractArgs& a, hipStream_t st) {
 }
 
 template <int R>
-static int launch_r(const ExtractArgs& a, hipStream_t st) {
-  return a.scheme == 1 ? launch_rs<R, true>(a, st) : launch_rs<R, false>(a, st);
+static int launch_r(const ExtractArgs& a, dim3 grid, hipStream_t st) {
+  return a.scheme == 1 ? launch_rs<R, true>(a, grid, st) : launch_rs<R, false>(a, grid, st);
 }
 
 template <int R, bool S1>
@@ -745,15 +779,35 @@ int init_extract_attributes() {
   return 0;
 }
 
-int launch_extract(const float* img, int64_t stride, int H, int W, int m, float sigma, int R, float* vol,
-                   double* sat, void* ws, hipStream_t st, int scheme) {
+// The SAT carries and fix-up of the images of one launch.
+static int launch_sat(const SatBatch& b, int n, hipStream_t st) {
+  int carry_blocks = 0, ntx = 0, nty = 0;
+  for (int i = 0; i < n; ++i) {
+    const SatImage& I = b.im[i];
+    if (!I.sat) continue;
+    carry_blocks = std::max(carry_blocks, (I.H + SAT_WAVES - 1) / SAT_WAVES + (I.W + 63) / 64);
+    ntx = std::max(ntx, I.ntx);
+    nty = std::max(nty, I.nty);
+  }
+  if (!carry_blocks) return 0;
+  hipLaunchKernelGGL(sat_carry_kernel, dim3(carry_blocks, n), dim3(SAT_NT), 0, st, b);
+  hipLaunchKernelGGL(sat_fix_kernel, dim3(ntx, nty, n), dim3(EX_NT), 0, st, b);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+size_t extract_batch_workspace_bytes(const int* H, const int* W, const bool* with_sat, int n) {
+  size_t off = 0;
+  for (int i = 0; i < n; ++i)
+    if (with_sat[i]) off += (extract_workspace_bytes(H[i], W[i]) + 255) / 256 * 256;
+  return off;
+}
+
+int launch_extract_batch(const ExtractImage* ims, int n, int m, float sigma, int R, void* ws, hipStream_t st,
+                         int scheme) {
+  if (lds_bytes(m, R) > kMaxLds || R < 0 || R > kMaxGaussRadius) return -1;
   ExtractArgs a{};
   a.scheme = scheme;
-  a.img = img; a.stride = stride; a.H = H; a.W = W; a.m = m; a.vol = vol; a.sat = sat;
-  a.ntx = (W + EX_TX - 1) / EX_TX;
-  a.nty = (H + EX_TY - 1) / EX_TY;
-  a.rc = (double*)ws;
-  a.bt = a.rc + (size_t)H * a.ntx;
+  a.m = m;
   for (int k = 0; k < m; ++k) {
     double th = k * 3.14159265358979323846 / m;
     a.cs[k] = (float)cos(th);
@@ -762,26 +816,66 @@ int launch_extract(const float* img, int64_t stride, int H, int W, int m, float 
   double ws_[kMaxGaussRadius + 1], tot = 0.0;
   for (int j = 0; j <= R; ++j) { ws_[j] = exp(-(double)j * j / (2.0 * sigma * sigma)); tot += (j ? 2 : 1) * ws_[j]; }
   for (int j = 0; j <= R; ++j) a.w[j] = (float)(ws_[j] / tot);
-  if (lds_bytes(m, R) > kMaxLds) return -1;
-  int rc = -1;
-  switch (R) {
-    case 0: rc = launch_r<0>(a, st); break;
-    case 1: rc = launch_r<1>(a, st); break;
-    case 2: rc = launch_r<2>(a, st); break;
-    case 3: rc = launch_r<3>(a, st); break;
-    case 4: rc = launch_r<4>(a, st); break;
-    case 5: rc = launch_r<5>(a, st); break;
-    case 6: rc = launch_r<6>(a, st); break;
-    case 7: rc = launch_r<7>(a, st); break;
-    case 8: rc = launch_r<8>(a, st); break;
-    default: return -1;
+  // the images' carry workspaces follow each other in image order
+  std::vector<size_t> off((size_t)n);
+  size_t o = 0;
+  for (int i = 0; i < n; ++i) {
+    off[i] = o;
+    if (ims[i].sat) o += (extract_workspace_bytes(ims[i].H, ims[i].W) + 255) / 256 * 256;
   }
-  if (rc != 0 || !sat) return rc;
-  const int row_blocks = (H + SAT_NT / 64 - 1) / (SAT_NT / 64);
-  hipLaunchKernelGGL(sat_carry_kernel, dim3(row_blocks + (W + 63) / 64), dim3(SAT_NT), 0, st, a.rc, a.bt, H, W,
-                     a.ntx, a.nty, row_blocks);
-  hipLaunchKernelGGL(sat_fix_kernel, dim3(a.ntx, a.nty), dim3(EX_NT), 0, st, sat, a.rc, a.bt, H, W, a.ntx);
-  return hipGetLastError() == hipSuccess ? 0 : -2;
+  // launch groups of images of similar size (largest first), so that few
+  // workgroups of a group's overlaid grid fall outside their image
+  std::vector<int> order((size_t)n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (int64_t)ims[x].H * ims[x].W > (int64_t)ims[y].H * ims[y].W;
+  });
+  for (int i0 = 0; i0 < n; i0 += kExBatch) {
+    const int nb = std::min(kExBatch, n - i0);
+    SatBatch sb{};
+    int ntx = 0, nty = 0;
+    for (int i = 0; i < nb; ++i) {
+      const int j = order[i0 + i];
+      const ExtractImage& src = ims[j];
+      ExImage& I = a.im[i];
+      I = ExImage{};
+      I.img = src.img; I.stride = src.stride; I.vol = src.vol; I.sat = src.sat; I.H = src.H; I.W = src.W;
+      I.ntx = (src.W + EX_TX - 1) / EX_TX;
+      I.nty = (src.H + EX_TY - 1) / EX_TY;
+      if (src.sat) {
+        I.rc = (double*)((char*)ws + off[j]);
+        I.bt = I.rc + (size_t)src.H * I.ntx;
+      }
+      sb.im[i] = SatImage{I.sat, I.rc, I.bt, I.H, I.W, I.ntx, I.nty};
+      ntx = std::max(ntx, I.ntx);
+      nty = std::max(nty, I.nty);
+    }
+    for (int i = nb; i < kExBatch; ++i) a.im[i] = ExImage{};
+    const dim3 grid(ntx, nty, nb);
+    int rc = -1;
+    switch (R) {
+      case 0: rc = launch_r<0>(a, grid, st); break;
+      case 1: rc = launch_r<1>(a, grid, st); break;
+      case 2: rc = launch_r<2>(a, grid, st); break;
+      case 3: rc = launch_r<3>(a, grid, st); break;
+      case 4: rc = launch_r<4>(a, grid, st); break;
+      case 5: rc = launch_r<5>(a, grid, st); break;
+      case 6: rc = launch_r<6>(a, grid, st); break;
+      case 7: rc = launch_r<7>(a, grid, st); break;
+      case 8: rc = launch_r<8>(a, grid, st); break;
+      default: return -1;
+    }
+    if (rc != 0) return rc;
+    rc = launch_sat(sb, nb, st);
+    if (rc != 0) return rc;
+  }
+  return 0;
+}
+
+int launch_extract(const float* img, int64_t stride, int H, int W, int m, float sigma, int R, float* vol,
+                   double* sat, void* ws, hipStream_t st, int scheme) {
+  const ExtractImage im{img, stride, H, W, vol, sat};
+  return launch_extract_batch(&im, 1, m, sigma, R, ws, st, scheme);
 }
 
 }  // namespace cfog
@@ -814,11 +908,9 @@ int launch_fhog(const float* img, int64_t stride, int H, int W, int cell, float*
   }
   if (hipGetLastError() != hipSuccess) return -2;
   if (!sat) return 0;
-  const int row_blocks = (H + SAT_NT / 64 - 1) / (SAT_NT / 64);
-  hipLaunchKernelGGL(sat_carry_kernel, dim3(row_blocks + (W + 63) / 64), dim3(SAT_NT), 0, st, a.rc, a.bt, H, W,
-                     a.ntx, a.nty, row_blocks);
-  hipLaunchKernelGGL(sat_fix_kernel, dim3(a.ntx, a.nty), dim3(EX_NT), 0, st, sat, a.rc, a.bt, H, W, a.ntx);
-  return hipGetLastError() == hipSuccess ? 0 : -2;
+  SatBatch sb{};
+  sb.im[0] = SatImage{sat, a.rc, a.bt, H, W, a.ntx, a.nty};
+  return launch_sat(sb, 1, st);
 }
 
 }  // namespace cfog

@@ -35,6 +35,19 @@ enum : int { kCpOk = 0, kCpOutOfBounds = 1, kCpNonFinite = 2 };
 // scheme 2: oriented channels of Eq. 2; scheme 1: binned orientation.
 int launch_extract(const float* img, int64_t stride, int H, int W, int m, float sigma, int R,
                    float* vol, double* sat, void* ws, hipStream_t st, int scheme = 2);
+// Several images with the same parameters: up to 8 per launch (three launches
+// per group of 8 with SATs).  The carry workspaces of the images with a SAT
+// follow each other in ws, each rounded up to 256 bytes.
+struct ExtractImage {
+  const float* img;
+  int64_t stride;
+  int H, W;
+  float* vol;
+  double* sat;  // nullable
+};
+int launch_extract_batch(const ExtractImage* ims, int n, int m, float sigma, int R, void* ws, hipStream_t st,
+                         int scheme);
+size_t extract_batch_workspace_bytes(const int* H, const int* W, const bool* with_sat, int n);
 // Pixel-wise HOG (36 channels) with cells of `cell` pixels (1..8); the SAT as
 // for the CFOG volume.  0 ok, -1 unsupported cell, -2 HIP error.
 int launch_fhog(const float* img, int64_t stride, int H, int W, int cell, float* vol, double* sat, void* ws,

@@ -65,6 +65,29 @@ def test_job_struct_layout_matches_header():
     assert cfog.cfog_job.subpix.offset == 88
 
 
+def test_image_struct_layout_matches_header():
+    from paper_1808_06194_amd import cfog
+    assert ctypes.sizeof(cfog.cfog_image) == 40
+    assert cfog.cfog_image.row_stride.offset == 8 and cfog.cfog_image.H.offset == 16
+    assert cfog.cfog_image.d_vol.offset == 24 and cfog.cfog_image.d_sat.offset == 32
+
+
+def test_extract_batch_workspace_and_argument_checks(lib):
+    """The batch workspace is the per-image workspaces of the images with a
+    SAT, each rounded up to 256 bytes; invalid batches are rejected on the
+    host."""
+    from paper_1808_06194_amd import cfog
+    shapes = [(37, 53), (1, 1), (2048, 2048), (129, 7)]
+    one = [lib.cfog_extract_workspace_size(H, W) for H, W in shapes]
+    assert one[2] == 8 * (2048 * 32 + 64 * 2048)
+    assert cfog.extract_batch_workspace_size(shapes) == sum((b + 255) // 256 * 256 for b in one)
+    assert cfog.extract_batch_workspace_size(shapes, with_sat=False) == 0
+    assert cfog.extract_batch_workspace_size([]) == 0
+    assert lib.cfog_extract_batch_workspace_size(None, 3) == 0
+    arr = (cfog.cfog_image * 1)()
+    assert lib.cfog_extract_batch(None, arr, 1, 9, 0.8, -1, 2, None, 0, None) == cfog.CFOG_EINVAL
+
+
 def test_max_window(lib):
     assert lib.cfog_max_window() >= 192
 

@@ -580,6 +580,64 @@ def test_batched_objective_and_subpixel_equal_plain(cf):
     assert int(r1[0]["status"][-1]) == cf.CP_OUT_OF_BOUNDS and np.all(np.isnan(r1[2][-1]))
 
 
+# ------------------------------------------------------ batched extraction
+
+_BATCH_SHAPES = [(37, 53), (256, 256), (1, 1), (129, 7), (300, 257), (64, 64), (33, 700), (700, 33), (5, 5),
+                 (97, 130), (1100, 900)]
+
+
+@pytest.mark.parametrize("m,sigma,scheme", [(9, 0.8, 2), (12, 1.5, 1), (4, 0.5, 2)])
+def test_extract_batch_equals_single_calls(cf, m, sigma, scheme):
+    """cfog_extract_batch over 11 images of mixed sizes (two launch groups of
+    at most 8), some without a SAT: every volume and SAT bit-identical to the
+    single-image call, and the volumes against the oracle."""
+    _say("extract batch", len(_BATCH_SHAPES), m, sigma, scheme)
+    rng = np.random.default_rng(77 + m)
+    imgs = [_dev(rng.random(sh).astype(np.float32)) for sh in _BATCH_SHAPES]
+    sats = [torch.full((H + 1, W + 1), float("nan"), dtype=torch.float64, device="cuda") if i % 3 != 1 else None
+            for i, (H, W) in enumerate(_BATCH_SHAPES)]
+    vols, _ = cf.cfog_extract_batch(imgs, m=m, sigma=sigma, sats=sats, scheme=scheme)
+    torch.cuda.synchronize()
+    for i, img in enumerate(imgs):
+        v1, s1 = cf.cfog_extract(img, m=m, sigma=sigma, scheme=scheme, with_sat=sats[i] is not None)
+        torch.cuda.synchronize()
+        assert torch.equal(vols[i].view(torch.int32), v1.view(torch.int32)), (i, _BATCH_SHAPES[i])
+        if sats[i] is not None:
+            assert torch.equal(sats[i].view(torch.int64), s1.view(torch.int64)), (i, _BATCH_SHAPES[i])
+    for i in (0, 3, 9):
+        D = O.cfog(imgs[i].cpu().numpy().astype(np.float64), m=m, sigma=sigma, scheme=scheme)
+        parity.check_volume(vols[i].cpu().numpy(), D)
+
+
+def test_extract_batch_edge_cases(cf):
+    """An empty batch queues nothing; an invalid image anywhere in the batch
+    is rejected before any output is written; a caller workspace of the
+    queried size is enough."""
+    _say("extract batch edge cases")
+    assert cf.cfog_extract_batch([]) == ([], [])
+    good = _dev(np.ones((40, 40), np.float32))
+    vol = torch.full((9, 40, 40), 7.0, device="cuda")
+    bad_img = torch.ones((40, 40), device="cuda")
+    bad_vol = torch.empty((9, 40, 40), device="cuda")
+    arr = (cf.cfog_image * 2)()
+    arr[0] = cf.cfog_image(good.data_ptr(), 40, 40, 40, vol.data_ptr(), None)
+    arr[1] = cf.cfog_image(bad_img.data_ptr(), 30, 40, 40, bad_vol.data_ptr(), None)  # row_stride < W
+    rc = cf.load().cfog_extract_batch(cf.context().handle, arr, 2, 9, 0.8, -1, 2, None, 0, None)
+    assert rc == cf.CFOG_EINVAL
+    torch.cuda.synchronize()
+    assert torch.all(vol == 7.0)
+    shapes = [(40, 40), (70, 130)]
+    ws = torch.empty(cf.extract_batch_workspace_size(shapes), dtype=torch.uint8, device="cuda")
+    imgs = [_dev(np.random.default_rng(i).random(sh).astype(np.float32)) for i, sh in enumerate(shapes)]
+    vols, sats = cf.cfog_extract_batch(imgs, workspace=ws)
+    for img, v, s in zip(imgs, vols, sats):
+        v1, s1 = cf.cfog_extract(img)
+        torch.cuda.synchronize()
+        assert torch.equal(v, v1) and torch.equal(s, s1)
+    with pytest.raises(cf.CfogError):
+        cf.cfog_extract_batch(imgs, workspace=ws[:16])
+
+
 # ------------------------------------------------------------ CFOG scheme 1
 
 @pytest.mark.parametrize("H,W,m,sigma,seed", [(96, 130, 9, 0.8, 91), (64, 64, 6, 0.8, 92), (300, 257, 12, 0.8, 93),
