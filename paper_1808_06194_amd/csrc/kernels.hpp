@@ -35,9 +35,10 @@ enum : int { kCpOk = 0, kCpOutOfBounds = 1, kCpNonFinite = 2 };
 // scheme 2: oriented channels of Eq. 2; scheme 1: binned orientation.
 int launch_extract(const float* img, int64_t stride, int H, int W, int m, float sigma, int R,
                    float* vol, double* sat, void* ws, hipStream_t st, int scheme = 2);
-// Several images with the same parameters: up to 8 per launch (three launches
-// per group of 8 with SATs).  The carry workspaces of the images with a SAT
-// follow each other in ws, each rounded up to 256 bytes.
+// Several images with the same parameters, grouped largest first, up to 8 per
+// launch (three launches per group with SATs).  The carry workspaces of the
+// images with a SAT follow each other in ws in image order, each rounded up
+// to 256 bytes.
 struct ExtractImage {
   const float* img;
   int64_t stride;
