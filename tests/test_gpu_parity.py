@@ -636,6 +636,14 @@ def test_extract_batch_edge_cases(cf):
         assert torch.equal(v, v1) and torch.equal(s, s1)
     with pytest.raises(cf.CfogError):
         cf.cfog_extract_batch(imgs, workspace=ws[:16])
+    # images with a row stride beyond their width, batched with a plain one
+    base = _dev(np.random.default_rng(9).random((90, 140)).astype(np.float32))
+    views = [base[:, :131], base[5:50, 3:70], imgs[1]]
+    vols, sats = cf.cfog_extract_batch(views)
+    for v_img, v, s in zip(views, vols, sats):
+        v1, s1 = cf.cfog_extract(v_img)
+        torch.cuda.synchronize()
+        assert torch.equal(v, v1) and torch.equal(s, s1)
 
 
 # ------------------------------------------------------------ CFOG scheme 1
