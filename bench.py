@@ -2,7 +2,8 @@
 """Benchmark of the CFOG + 3-D-FFT SSD matching hot path on one MI355X.
 
 One step = the whole hot path on one batch of synthetic input: CFOG extraction
-of every image (volume + FP64 summed-area table; the images alternate between
+of every image (volume + FP64 summed-area table; all images in one batched
+extraction call, up to 8 per launch; pixel-wise HOG volumes alternate between
 two streams) and SSD matching of every control point (correlation, FP64
 energies, argmin).  Inputs are resident in HBM before the timed region starts.
 
