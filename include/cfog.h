@@ -166,7 +166,12 @@ int cfog_extract_batch(cfog_ctx* ctx, const cfog_image* imgs, int32_t n, int32_t
                        int32_t gauss_radius, int32_t scheme, void* d_ws, size_t ws_bytes, void* stream);
 
 /* One control point: template centre (x, y) in A; search centre (bx, by) in B
- * (a georeferenced prediction; bx = x, by = y when A and B are co-registered). */
+ * (a georeferenced prediction; bx = x, by = y when A and B are co-registered).
+ * Any int32 values are accepted: a point whose template box
+ * [y - N/2, y - N/2 + N) x [x - N/2, x - N/2 + N) leaves A, or whose search box
+ * [by - N/2 - r, by - N/2 + N + r) x [bx - N/2 - r, bx - N/2 + N + r) leaves B,
+ * gets CFOG_CP_OUT_OF_BOUNDS (the test is computed in 64 bits, so coordinates
+ * near INT_MIN or INT_MAX cannot wrap into the image). */
 typedef struct {
   int32_t x, y, bx, by;
 } cfog_cp;
@@ -250,7 +255,8 @@ size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n
  *               rounding.  CFOG_NO_SPLIT turns splitting off (the plain and
  *               batched paths then return identical bits).
  *   Returns CFOG_EINVAL for invalid jobs, CFOG_EUNSUPPORTED when 2r+1 or
- *   N + 2r exceeds what the chosen path supports, CFOG_ENOMEM when the
+ *   N + 2r exceeds what the chosen path supports (always for N or r above
+ *   65536), CFOG_ENOMEM when the
  *   workspace is too small.  Per-point failures are reported in out[].status.
  */
 int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags, void* d_ws,
@@ -408,7 +414,11 @@ int cfog_server_destroy(cfog_server* srv);
 
 /* Register an image pair: A and B are DEVICE fp32 images [h][stride] owned by
  * the caller, which must keep them unchanged while the server lives.  *pair_id
- * receives the pair's id (0, 1, ...).  Volumes are computed on first use.
+ * receives the pair's id (0, 1, ...).  Volumes are computed on first use, on
+ * the server's own streams, which do not wait for any stream of the caller:
+ * the writes that fill the images must have completed on the device (e.g.
+ * hipStreamSynchronize of the stream that wrote them) before the first
+ * cfog_server_submit naming the pair.
  * CFOG_ENOMEM if the pair alone exceeds the budget. */
 int cfog_server_add_pair(cfog_server* srv, const float* d_imgA, int32_t hA, int32_t wA, int64_t strideA,
                          const float* d_imgB, int32_t hB, int32_t wB, int64_t strideB, int32_t* pair_id);
@@ -418,6 +428,11 @@ int cfog_server_add_pair(cfog_server* srv, const float* d_imgA, int32_t hA, int3
  * are written to the caller's HOST buffers h_out[n_cps] and, if h_surfaces is
  * not NULL, h_surfaces[n_cps][2r+1][2r+1]; both must stay valid until the
  * request is reported by cfog_server_poll.  *req_id receives the id.
+ * Every point is first tested on the host against the pair's image sizes with
+ * the rule the kernels use (template box of Eq. 3 inside A, search box inside
+ * B, computed in 64 bits so that any int32 coordinate is safe); points outside
+ * never reach the device and get the CFOG_CP_OUT_OF_BOUNDS result (NaN
+ * surface).  A request with no point inside is reported at once.
  * CFOG_EINVAL for bad arguments, CFOG_EUNSUPPORTED for (N, r) the path cannot
  * match, CFOG_ENOMEM for a request that could never fit the budget or the
  * per-batch limits, CFOG_EHIP after a device failure of the server. */

@@ -79,6 +79,7 @@ int validate_job(const cfog_job& j, int m) {
   if (j.n_cps < 0 || (j.n_cps > 0 && (!j.cps || !j.out))) return CFOG_EINVAL;
   if (j.hA < 1 || j.wA < 1 || j.hB < 1 || j.wB < 1) return CFOG_EINVAL;
   if (j.N < 1 || j.r < 0 || m < 1 || m > cfog::kMaxChannels) return CFOG_EINVAL;
+  if (j.N > cfog::kMaxSide || j.r > cfog::kMaxSide) return CFOG_EUNSUPPORTED;
   if (!aligned(j.cps, 16) || !aligned(j.out, 8) || !aligned(j.satA, 8) || !aligned(j.satB, 8) ||
       !aligned(j.volA, 4) || !aligned(j.volB, 4) || !aligned(j.surfaces, 4) || !aligned(j.subpix, 8))
     return CFOG_EINVAL;

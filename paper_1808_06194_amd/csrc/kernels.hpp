@@ -10,6 +10,8 @@ constexpr int kMaxOrient = 16;        // m <= 16 orientation channels (CFOG extr
 constexpr int kMaxChannels = 64;      // channels of a volume the matcher takes (FHOG: 36)
 constexpr int kMaxGaussRadius = 8;    // Gaussian radius R <= 8 taps each side
 constexpr size_t kMaxLds = 160 * 1024;
+constexpr int kMaxSide = 1 << 16;      // template sides and radii above this are rejected before any
+                                       // arithmetic on them (no path supports them anyway)
 
 // Per-control-point result, 24 bytes (mirrors cfog_result of the C-ABI).
 struct Result {

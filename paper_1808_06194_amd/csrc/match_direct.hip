@@ -22,14 +22,22 @@
 //      byte shift;
 //   B (lane l, u_y block n): 8 bf16 of template row s - 16n - l%16, columns
 //      32kc + 8(l/16) .. +7, one aligned 16-byte LDS read.
-// Inputs are rounded to BF16 (relative error 2^-9 each), so |C_bf16 - C| <=
-// 2^-8 sum |T S| <= 2^-9 (E1 + E2): the SSD surface is within 2^-8 (E1 + E2)
-// of the exact one, against ~1e-6 for the FP32 FFT path.
+// Precision: inputs are rounded to BF16 (round to nearest, 8 significant bits,
+// unit roundoff u = 2^-8), products are exact in FP32, so
+//   |C_bf16 - C| <= [(2u + u^2) + gamma_L (1 + u)^2] sum |T S|,
+// with gamma_L = L 2^-24 / (1 - L 2^-24) for the longest chain of L FP32
+// additions into one output: m channels x ceil(Ws / 8) search rows of a wave x
+// ceil(N / 32) chunks of MFMAs of 32 products each, plus the 8 wave partials.
+// As sum |T S| <= sqrt(E1 E2) <= (E1 + E2) / 2 and SSD = E1 + E2 - 2C, the
+// SSD surface is within [(2u + u^2) + gamma_L (1 + u)^2 + 2^-23] (E1 + E2(d))
+// of the exact one (the last term is its own FP32 rounding): about 2^-7, or
+// 0.0095 at N = 128, r = 32, m = 9, against ~1e-6 for the FP32 FFT path.
 #include <hip/hip_runtime.h>
 #include <algorithm>
 #include "cfog.h"
 #include "epilogue.hpp"
 #include "kernels.hpp"
+#include "window.hpp"
 
 namespace cfog {
 
@@ -121,15 +129,13 @@ __global__ __launch_bounds__(D_NT) void match_direct_kernel(MatchJob jd, DirectG
 
   for (int cpi = blockIdx.x; cpi < jd.n_cps; cpi += gridDim.x) {
     const int4 cp = jd.cps[cpi];
-    const int h = N / 2;
-    const int tx0 = cp.x - h, ty0 = cp.y - h, sx0 = cp.z - h - r, sy0 = cp.w - h - r;
+    const CpBoxes bx = cp_boxes(cp.x, cp.y, cp.z, cp.w, N, r, jd.hA, jd.wA, jd.hB, jd.wB);
     __syncthreads();  // the previous point's epilogue is done with LDS
-    const bool inA = tx0 >= 0 && ty0 >= 0 && tx0 + N <= jd.wA && ty0 + N <= jd.hA;
-    const bool inB = sx0 >= 0 && sy0 >= 0 && sx0 + Ws <= jd.wB && sy0 + Ws <= jd.hB;
-    if (!(inA && inB)) {
+    if (!bx.inside) {
       oob_result<D_NT>(jd, cpi);
       continue;
     }
+    const int tx0 = bx.tx0, ty0 = bx.ty0, sx0 = bx.sx0, sy0 = bx.sy0;
     // acc[m][n]: u_x block m, u_y block n; lane element q is
     // u_x = 16 m + 4 (lane / 16) + q, u_y = 16 n + lane % 16
     f32x4 acc[NB][NB];
@@ -240,11 +246,8 @@ int init_direct_attributes() {
 }
 
 int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, int obj, void*, int num_cus, hipStream_t st) {
-  for (int i = 0; i < n_jobs; ++i) {
-    const cfog_job& j = jobs[i];
-    const DirectGeom g = direct_geom(j.N, j.r);
-    if (g.nblk > D_NB || g.lds > kMaxLds) return -1;
-  }
+  for (int i = 0; i < n_jobs; ++i)
+    if (!direct_supported(jobs[i].N, jobs[i].r)) return -1;
   for (int i = 0; i < n_jobs; ++i) {
     const cfog_job& j = jobs[i];
     if (j.n_cps == 0) continue;
@@ -273,6 +276,7 @@ int launch_match_direct(const cfog_job* jobs, int n_jobs, int m, int obj, void*,
 }
 
 bool direct_supported(int N, int r) {
+  if (N < 1 || r < 0 || N > kMaxSide || r > kMaxSide) return false;
   const DirectGeom g = direct_geom(N, r);
   return g.nblk <= D_NB && g.lds <= kMaxLds;
 }

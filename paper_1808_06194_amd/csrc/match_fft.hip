@@ -45,6 +45,7 @@
 #include "dft.hpp"
 #include "epilogue.hpp"
 #include "kernels.hpp"
+#include "window.hpp"
 
 namespace cfog {
 
@@ -439,15 +440,13 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
                           float* __restrict__ part, int g) {
   constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH, NT = C::NT, KF = C::KF;
   const int4 cp = jd.cps[cpi];
-  const int N = jd.N, r = jd.r, K = 2 * r + 1, h = N / 2, Ws = N + 2 * r;
-  const int tx0 = cp.x - h, ty0 = cp.y - h;
-  const int sx0 = cp.z - h - r, sy0 = cp.w - h - r;
-  const bool inA = tx0 >= 0 && ty0 >= 0 && tx0 + N <= jd.wA && ty0 + N <= jd.hA;
-  const bool inB = sx0 >= 0 && sy0 >= 0 && sx0 + Ws <= jd.wB && sy0 + Ws <= jd.hB;
-  if (!(inA && inB)) {
+  const int N = jd.N, r = jd.r, K = 2 * r + 1, Ws = N + 2 * r;
+  const CpBoxes bx = cp_boxes(cp.x, cp.y, cp.z, cp.w, N, r, jd.hA, jd.wA, jd.hB, jd.wB);
+  if (!bx.inside) {
     if (g == 0) oob_result<NT>(jd, cpi);
     return;
   }
+  const int tx0 = bx.tx0, ty0 = bx.ty0, sx0 = bx.sx0, sy0 = bx.sy0;
 
   float2 acc[KF][R2];
 #pragma unroll
@@ -694,6 +693,7 @@ const FftPlan* fft_plans(int* count) {
 }
 
 bool plan_fits(const FftPlan* p, int N, int r) {
+  if (N < 1 || r < 0 || N > kMaxSide || r > kMaxSide) return false;
   const int Ws = N + 2 * r, K = 2 * r + 1;
   if (p->P < Ws || N > p->t_rows) return false;
   const int PH = p->P / 2 + 1;
@@ -755,12 +755,9 @@ __global__ __launch_bounds__(SR_NT) void split_reduce_kernel(MatchJob job0, cons
     cpi = tk.y;
   }
   const int4 cp = jd.cps[cpi];
-  const int N = jd.N, r = jd.r, K = 2 * r + 1, h = N / 2, Ws = N + 2 * r;
-  const int tx0 = cp.x - h, ty0 = cp.y - h;
-  const int sx0 = cp.z - h - r, sy0 = cp.w - h - r;
-  const bool inA = tx0 >= 0 && ty0 >= 0 && tx0 + N <= jd.wA && ty0 + N <= jd.hA;
-  const bool inB = sx0 >= 0 && sy0 >= 0 && sx0 + Ws <= jd.wB && sy0 + Ws <= jd.hB;
-  if (!(inA && inB)) return;  // reported by the task's first item
+  const int K = 2 * jd.r + 1;
+  const CpBoxes bx = cp_boxes(cp.x, cp.y, cp.z, cp.w, jd.N, jd.r, jd.hA, jd.wA, jd.hB, jd.wB);
+  if (!bx.inside) return;  // reported by the task's first item
   const float* p = sp.part + (size_t)blockIdx.x * sp.G * sp.slot;
   for (int i = threadIdx.x; i < K * K; i += SR_NT) {
     float s = ldg(p + i);
@@ -768,7 +765,7 @@ __global__ __launch_bounds__(SR_NT) void split_reduce_kernel(MatchJob job0, cons
     Cs[i] = s;
   }
   __syncthreads();
-  ssd_epilogue<SR_NT>(jd, cpi, tx0, ty0, sx0, sy0, Cs, red);
+  ssd_epilogue<SR_NT>(jd, cpi, bx.tx0, bx.ty0, bx.sx0, bx.sy0, Cs, red);
 }
 
 int launch_split_reduce(const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks, int n_tasks,

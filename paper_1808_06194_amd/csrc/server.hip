@@ -15,6 +15,7 @@
 // per-batch limits; the pair volumes live in one device region managed by
 // the scheduler's arena.
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <string.h>
 #include <time.h>
 #include <algorithm>
@@ -29,6 +30,7 @@
 #include "cfog.h"
 #include "kernels.hpp"
 #include "sched.hpp"
+#include "window.hpp"
 
 namespace {
 
@@ -52,7 +54,9 @@ struct PairImg {
 struct Req {
   int64_t id;
   int pair;
-  std::vector<cfog_cp> cps;
+  std::vector<cfog_cp> cps;  // the points inside both images (sent to the device)
+  std::vector<int32_t> idx;  // their positions in the caller's list
+  int n_all;                 // points of the request
   int N, r;
   cfog_result* h_out;
   float* h_surf;
@@ -116,6 +120,7 @@ struct cfog_server {
   bool stop = false;
   int failed = 0;  // first device failure (a negative status); sticky
   int64_t next_id = 0, submitted = 0;
+  int64_t done_at_submit = 0;  // requests with no point inside the images
   int in_flight = 0, max_in_flight = 0;
 };
 
@@ -125,7 +130,7 @@ void report(cfog_server* s, Req* r, int status, int batch_reqs) {
   cfog_request_info info{};
   info.id = r->id;
   info.status = status;
-  info.n_cps = (int32_t)r->cps.size();
+  info.n_cps = (int32_t)r->n_all;
   info.t_submit_ns = r->t_submit;
   info.t_admit_ns = r->t_admit;
   info.t_launch_ns = r->t_launch;
@@ -199,16 +204,34 @@ int launch(cfog_server* s, Slot& sl) {
   return CFOG_OK;
 }
 
+// Results of the points of request r that were sent to the device (res,
+// surf: in the order of r->idx) into the caller's buffers; the other points
+// are outside an image and get the out-of-bounds result.
+void scatter_results(const Req* r, const cfog_result* res, const float* surf) {
+  const size_t KK = (2 * (size_t)r->r + 1) * (2 * (size_t)r->r + 1);
+  const cfog_result oob{0, 0, NAN, NAN, CFOG_CP_OUT_OF_BOUNDS, 0};
+  size_t k = 0;
+  for (int i = 0; i < r->n_all; ++i) {
+    const bool sent = k < r->idx.size() && r->idx[k] == i;
+    r->h_out[i] = sent ? res[k] : oob;
+    if (r->h_surf) {
+      float* dst = r->h_surf + (size_t)i * KK;
+      if (sent)
+        memcpy(dst, surf + k * KK, KK * sizeof(float));
+      else
+        std::fill(dst, dst + KK, NAN);
+    }
+    k += sent;
+  }
+}
+
 // Retire the slot's batch: copy results out (status CFOG_OK) or fail it.
 void retire(cfog_server* s, Slot& sl, int status) {
   size_t cp_off = 0, sf_off = 0;
   const int nb = (int)sl.reqs.size();
   for (Req* r : sl.reqs) {
     const size_t n = r->cps.size(), K = 2 * (size_t)r->r + 1;
-    if (status == CFOG_OK) {
-      memcpy(r->h_out, sl.h_out + cp_off, n * sizeof(cfog_result));
-      if (r->h_surf) memcpy(r->h_surf, sl.h_surf + sf_off, n * K * K * sizeof(float));
-    }
+    if (status == CFOG_OK) scatter_results(r, sl.h_out + cp_off, r->h_surf ? sl.h_surf + sf_off : nullptr);
     cp_off += n;
     if (r->h_surf) sf_off += n * K * K;
     report(s, r, status, nb);
@@ -453,26 +476,49 @@ int cfog_server_submit(cfog_server* s, int32_t pair_id, const cfog_cp* h_cps, in
   if (!s || !req_id || n_cps < 1 || !h_cps || !h_out || N < 1 || r < 0) return CFOG_EINVAL;
   if (!supported(s->cfg.flags & CFOG_PATH_MASK, N, r)) return CFOG_EUNSUPPORTED;
   const size_t K = 2 * (size_t)r + 1;
-  const size_t surf = h_surfaces ? (size_t)n_cps * K * K : 0;
   std::unique_ptr<Req> q(new Req());
   q->pair = pair_id;
-  q->cps.assign(h_cps, h_cps + n_cps);
+  q->n_all = n_cps;
   q->N = N;
   q->r = r;
   q->h_out = h_out;
   q->h_surf = h_surfaces;
+  bool immediate = false;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->failed) return s->failed;
     if (pair_id < 0 || pair_id >= s->sched->n_pairs()) return CFOG_EINVAL;
-    if (!s->sched->feasible(pair_id, n_cps, surf)) return CFOG_ENOMEM;
+    // only points whose template and search boxes lie inside the images go to
+    // the device (the kernels' own test, run here on the host)
+    const PairImg& p = s->pairs[pair_id];
+    for (int i = 0; i < n_cps; ++i) {
+      const cfog_cp& c = h_cps[i];
+      if (cfog::cp_boxes(c.x, c.y, c.bx, c.by, N, r, p.h[0], p.w[0], p.h[1], p.w[1]).inside) {
+        q->cps.push_back(c);
+        q->idx.push_back(i);
+      }
+    }
+    const size_t surf = h_surfaces ? q->cps.size() * K * K : 0;
+    if (!q->cps.empty() && !s->sched->feasible(pair_id, (int)q->cps.size(), surf)) return CFOG_ENOMEM;
     q->id = s->next_id++;
     q->t_submit = now_ns();
     *req_id = q->id;
     ++s->submitted;
-    s->incoming.push_back(q.release());
+    if (q->cps.empty()) {
+      // nothing to match: every point is out of bounds; reported at once
+      scatter_results(q.get(), nullptr, nullptr);
+      q->t_admit = q->t_launch = q->t_submit;
+      report(s, q.release(), CFOG_OK, 0);
+      ++s->done_at_submit;
+      immediate = true;
+    } else {
+      s->incoming.push_back(q.release());
+    }
   }
-  s->cv_work.notify_one();
+  if (immediate)
+    s->cv_done.notify_all();
+  else
+    s->cv_work.notify_one();
   return CFOG_OK;
 }
 
@@ -497,7 +543,7 @@ int cfog_server_get_stats(cfog_server* s, cfog_server_stats* o) {
   const auto& st = s->sched->stats();
   *o = cfog_server_stats{};
   o->submitted = s->submitted;
-  o->completed = st.completed;
+  o->completed = st.completed + s->done_at_submit;
   o->batches = st.batches;
   o->evictions = st.evictions;
   o->extractions = st.extractions;

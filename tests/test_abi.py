@@ -162,3 +162,19 @@ def test_channel_split_planner(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
     assert "ALL OK" in r.stdout
+
+
+def test_window_rule_host_build(tmp_path):
+    """The control-point window rule the kernels and the server share
+    (window.hpp), built for the host with the sanitizers: control points at
+    INT_MIN / INT_MAX, +-N/2 and +-r around every edge, flush boxes and one
+    past them, against a 128-bit reference and pixel enumeration."""
+    src = os.path.join(ROOT, "tests", "cpp", "window_test.cpp")
+    exe = tmp_path / "window_test"
+    inc = os.path.join(ROOT, "paper_1808_06194_amd", "csrc")
+    r = subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        "-I", inc, src, "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
+    assert "ALL OK" in r.stdout

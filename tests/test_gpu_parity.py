@@ -186,7 +186,7 @@ def test_match_different_image_sizes_and_search_centres(cf, path):
     cps = np.array([[x, y, x + ax - bx0, y + ay - by0] for x, y in pts], np.int32)
     flags = {"plain": cf.PATH_PLAIN_FFT, "batched": cf.PATH_BATCHED_FFT, "mfma": cf.PATH_MFMA_BF16}[path]
     res, surf = _run_match(cf, A, B, cps, N, r, flags=flags)
-    tol = parity.BF16_TOL if path == "mfma" else parity.SURF_TOL
+    tol = parity.bf16_tol(N, r) if path == "mfma" else parity.SURF_TOL
     stats = {}
     for k, cp in enumerate(cps):
         S, E1, E2 = parity.oracle_point(A, B, cp, N, r)
@@ -220,6 +220,69 @@ def test_match_constant_images_tie_to_first_offset(cf):
     res, surf = _run_match(cf, A, A, cps, 16, 5)
     assert np.all(res["dx"] == -5) and np.all(res["dy"] == -5)
     assert np.all(res["best"] == 0) and np.all(res["second"] == 0) and np.all(surf == 0)
+
+
+I32_MIN, I32_MAX = -2 ** 31, 2 ** 31 - 1
+
+
+def _edge_cases(N, r, hA, wA, hB, wB):
+    """(control point, inside) pairs at every edge: template box flush against
+    A's four edges and one pixel past, search box flush against B's four edges
+    and one pixel past, and int32 extremes in each coordinate."""
+    h = N // 2
+    cx, cy, cbx, cby = wA // 2, hA // 2, wB // 2, hB // 2
+    xl, xr, yt, yb = h, wA - N + h, h, hA - N + h                      # template flush
+    sl, sr, st, sb = h + r, wB - N - r + h, h + r, hB - N - r + h      # search box flush
+    cases = [((xl, cy, cbx, cby), True), ((xl - 1, cy, cbx, cby), False),
+             ((xr, cy, cbx, cby), True), ((xr + 1, cy, cbx, cby), False),
+             ((cx, yt, cbx, cby), True), ((cx, yt - 1, cbx, cby), False),
+             ((cx, yb, cbx, cby), True), ((cx, yb + 1, cbx, cby), False),
+             ((cx, cy, sl, cby), True), ((cx, cy, sl - 1, cby), False),
+             ((cx, cy, sr, cby), True), ((cx, cy, sr + 1, cby), False),
+             ((cx, cy, cbx, st), True), ((cx, cy, cbx, st - 1), False),
+             ((cx, cy, cbx, sb), True), ((cx, cy, cbx, sb + 1), False),
+             ((xr, yb, sr, sb), True), ((xr + 1, yb + 1, sr + 1, sb + 1), False)]
+    for v in (I32_MIN, I32_MIN + 1, -h, -r - h, I32_MAX - h, I32_MAX - 1, I32_MAX):
+        for k in range(4):
+            cp = [cx, cy, cbx, cby]
+            cp[k] = v
+            cases.append((tuple(cp), False))
+        cases.append(((v, v, v, v), False))
+    return cases
+
+
+@pytest.mark.parametrize("path", ["plain", "plain_whole", "batched", "mfma"])
+@pytest.mark.parametrize("N", [12, 13])
+def test_match_window_edges_and_extreme_points(cf, path, N):
+    """Template boxes flush against A's right, bottom, left and top edges and
+    search boxes flush against B's are inside, and are matched against the
+    FP64 oracle (their last row and column included); one pixel further is
+    out of bounds; control points at int32 extremes are out of bounds and do
+    not disturb the other points of the launch.  A (64 x 64) and B (60 x 72)
+    differ in size; even and odd N; the plain path with and without the
+    channel split, the batched path and the MFMA path."""
+    r = 4
+    _say("match window edges", path, "N", N, "r", r)
+    rng = np.random.default_rng(700 + N)
+    A = rng.random((64, 64)).astype(np.float32)
+    B = rng.random((60, 72)).astype(np.float32)
+    cases = _edge_cases(N, r, 64, 64, 60, 72)
+    cps = np.array([c for c, _ in cases], np.int64).astype(np.int32)
+    assert np.array_equal(cps.astype(np.int64), np.array([c for c, _ in cases], np.int64))
+    inside = np.array([ok for _, ok in cases])
+    flags = {"plain": cf.PATH_PLAIN_FFT, "plain_whole": cf.PATH_PLAIN_FFT | cf.NO_SPLIT,
+             "batched": cf.PATH_BATCHED_FFT, "mfma": cf.PATH_MFMA_BF16}[path]
+    res, surf = _run_match(cf, A, B, cps, N, r, flags=flags)
+    want = np.where(inside, cf.CP_OK, cf.CP_OUT_OF_BOUNDS)
+    assert np.array_equal(res["status"], want), (res["status"], want)
+    assert np.all(np.isnan(surf[~inside])) and np.all(np.isnan(res["best"][~inside]))
+    assert np.all(res["dx"][~inside] == 0) and np.all(res["dy"][~inside] == 0)
+    tol = parity.bf16_tol(N, r) if path == "mfma" else parity.SURF_TOL
+    stats = {}
+    for k in np.flatnonzero(inside):
+        S, E1, E2 = parity.oracle_point(A, B, cps[k], N, r)
+        parity.check_point(int(k), res, S, E1, E2, r, surf[k], stats, tol=tol)
+    _say("stats", stats)
 
 
 def test_match_out_of_bounds_status(cf):
@@ -350,7 +413,7 @@ def test_match_precision_4096_full_size_sampled(cf, path):
     assert np.array_equal(flat[np.arange(len(cps)), i], res["best"])
     rng = np.random.default_rng(4096)
     stats = {}
-    tol = parity.SURF_TOL if path == "fft" else parity.BF16_TOL
+    tol = parity.SURF_TOL if path == "fft" else parity.bf16_tol(N, r)
     for k in rng.choice(len(cps), 3, replace=False):
         S, E1, E2 = parity.oracle_point(A, B, cps[k], N, r)
         parity.check_point(int(k), res, S, E1, E2, r, surf[k], stats, tol=tol)
@@ -465,7 +528,7 @@ def test_mfma_bf16_direct_against_oracle(cf, N, r, H, seed):
     stats = {}
     for k, cp in enumerate(cps):
         S, E1, E2 = parity.oracle_point(A, B, cp, N, r)
-        parity.check_point(k, res, S, E1, E2, r, surf[k], stats, tol=parity.BF16_TOL)
+        parity.check_point(k, res, S, E1, E2, r, surf[k], stats, tol=parity.bf16_tol(N, r))
     print("stats", stats, flush=True)
 
 
@@ -559,7 +622,7 @@ def test_mfma_objective_and_subpixel_against_oracle(cf):
     ora = O.match(D1, D2, cps, N, r, surfaces=True, objective="corr", subpix=True)
     for k, cp in enumerate(cps):
         E1, E2 = O.energies(D1, D2, cp, N, r)
-        eps = 0.5 * parity.BF16_TOL * (E1 + E2)
+        eps = 0.5 * parity.bf16_tol(N, r) * (E1 + E2)
         So = ora["surfaces"][k]
         assert np.all(np.abs(surf[k] - So) <= eps), k
         dg, do = (int(res["dx"][k]), int(res["dy"][k])), (int(ora["dx"][k]), int(ora["dy"][k]))
@@ -634,8 +697,21 @@ def test_extract_batch_edge_cases(cf):
         v1, s1 = cf.cfog_extract(img)
         torch.cuda.synchronize()
         assert torch.equal(v, v1) and torch.equal(s, s1)
-    with pytest.raises(cf.CfogError):
+    with pytest.raises(ValueError):  # the binding checks the workspace size
         cf.cfog_extract_batch(imgs, workspace=ws[:16])
+    arr2 = cf._image_array(imgs, vols, sats)  # and so does the C entry point
+    rc = cf.load().cfog_extract_batch(cf.context().handle, arr2, 2, 9, 0.8, -1, 2, ws.data_ptr(), 16, None)
+    assert rc == cf.CFOG_ENOMEM
+    # caller-supplied outputs of the wrong shape, dtype or layout are refused
+    # before any work is queued
+    for bad in ([vols[0], vols[1][:, :, :-1]], [vols[0], vols[1].to(torch.float64)],
+                [vols[0], vols[1].transpose(1, 2).contiguous().transpose(1, 2)]):
+        with pytest.raises(ValueError):
+            cf.cfog_extract_batch(imgs, vols=bad, sats=sats)
+    with pytest.raises(ValueError):
+        cf.cfog_extract_batch(imgs, vols=vols, sats=[sats[0], sats[1].to(torch.float32)])
+    with pytest.raises(ValueError):
+        cf.cfog_extract(imgs[1], vol=vols[0])
     # images with a row stride beyond their width, batched with a plain one
     base = _dev(np.random.default_rng(9).random((90, 140)).astype(np.float32))
     views = [base[:, :131], base[5:50, 3:70], imgs[1]]

@@ -214,3 +214,45 @@ def test_server_rejections(cf):
         with pytest.raises(cf.CfogError) as e:
             small.add_pair(big, big)
         assert e.value.code == cf.CFOG_ENOMEM
+
+
+def test_server_points_outside_never_reach_the_device(cf):
+    """Points at int32 extremes and one pixel past an edge, mixed with valid
+    points in one request, give the out-of-bounds result without disturbing
+    the others (equal to a direct match_batch call, whose kernels apply the
+    same rule); a request with no point inside completes at once."""
+    seed = 44
+    _say("server: out-of-bounds and extreme points, seed", seed)
+    pairs = _pairs(seed)
+    imgs = _dev_pairs(pairs)
+    H, W = pairs[1][0].shape  # 200 x 232
+    N, r = 21, 5
+    h = N // 2
+    I32_MIN, I32_MAX = -2 ** 31, 2 ** 31 - 1
+    good = [(60, 70, 62, 68), (W - N + h, H - N + h, W - N - r + h, H - N - r + h), (h, h, h + r, h + r)]
+    bad = [(I32_MIN, 70, 60, 70), (60, I32_MAX, 60, 70), (60, 70, I32_MAX - h, 70), (60, 70, 60, I32_MIN + 1),
+           (W - N + h + 1, 70, 60, 70), (60, 70, 60, H - N - r + h + 1), (I32_MAX, I32_MAX, I32_MAX, I32_MAX)]
+    mixed = np.array([bad[0], good[0], bad[1], bad[2], good[1], bad[3], bad[4], good[2], bad[5], bad[6]], np.int32)
+    reqs = [dict(pair=1, cps=mixed, N=N, r=r, surfaces=True), dict(pair=1, cps=mixed, N=N, r=r, surfaces=False)]
+    ref = _direct(cf, pairs, reqs, cf.PATH_BATCHED_FFT)
+    res = cf.results_np(ref[0][0])
+    assert [int(s) for s in res["status"]] == [1, 0, 1, 1, 0, 1, 1, 0, 1, 1]
+    with _server(cf, imgs, 1 << 30, n_slots=2, max_batch_cps=64, max_batch_reqs=4) as srv:
+        ids = [srv.submit(q["pair"], q["cps"], q["N"], q["r"], surfaces=q["surfaces"]) for q in reqs]
+        none_inside = srv.submit(1, np.array(bad, np.int32), N, r, surfaces=True)
+        got = srv.wait(ids + [none_inside])
+        st = srv.stats()
+    for i, rid in enumerate(ids):
+        assert got[rid].status == cf.CFOG_OK
+        _same((got[rid].out, got[rid].surfaces), ref[i])
+    c = got[none_inside]
+    assert c.status == cf.CFOG_OK and c.batch_reqs == 0
+    assert np.all(c.out[:, 4] == cf.CP_OUT_OF_BOUNDS) and np.all(c.out[:, :2] == 0)
+    assert np.all(np.isnan(cf.results_np(c.out)["best"])) and np.all(np.isnan(c.surfaces))
+    assert st["completed"] == st["submitted"] == 3
+    stats = {}
+    A, B = pairs[1]
+    for k in np.flatnonzero(res["status"] == 0):
+        S, E1, E2 = parity.oracle_point(A, B, mixed[k], N, r)
+        parity.check_point(int(k), res, S, E1, E2, r, surf_gpu=ref[0][1][k], stats=stats)
+    _say("oracle", stats)

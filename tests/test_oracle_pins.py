@@ -203,6 +203,81 @@ def test_out_of_bounds_status():
     assert list(res["status"]) == [O.STATUS_OUT_OF_BOUNDS, O.STATUS_OUT_OF_BOUNDS, O.STATUS_OK]
 
 
+def _box_pixels_valid(x0, y0, n, h_img, w_img):
+    """Every pixel of the n x n box with top-left (x0, y0) is an index of an
+    h_img x w_img image (written as a loop over the box's pixels)."""
+    for yy in range(y0, y0 + n):
+        for xx in range(x0, x0 + n):
+            if not (0 <= yy < h_img and 0 <= xx < w_img):
+                return False
+    return True
+
+
+@pytest.mark.parametrize("N", [1, 2, 5, 6])
+@pytest.mark.parametrize("r", [0, 1, 3])
+def test_window_rule_against_pixel_enumeration(N, r):
+    """Section III-G, Eq. 3: the template box (side N, top-left p - N//2)
+    must lie in A and the search box (side N + 2r) in B.  window_ok against
+    enumerating the boxes' pixels at every position, even and odd N, A and B of
+    different sizes: pins both the left/top and the right/bottom edges."""
+    hA, wA, hB, wB = 9, 11, 13, 12
+    h = N // 2
+    for y in range(-3, 14):
+        for x in range(-3, 16):
+            for by, bx in ((6, 6), (y, x), (x, y)):
+                want = (_box_pixels_valid(x - h, y - h, N, hA, wA)
+                        and _box_pixels_valid(bx - h - r, by - h - r, N + 2 * r, hB, wB))
+                assert O.window_ok((x, y, bx, by), N, r, hA, wA, hB, wB) == want, (x, y, bx, by)
+
+
+def _ssd_loop(D1, D2, cp, N, r):
+    """Eq. 3 as explicit loops with every index checked (numpy would wrap a
+    negative index or silently shorten a slice)."""
+    x, y, bx, by = cp
+    h = N // 2
+    m, hA, wA = D1.shape
+    _, hB, wB = D2.shape
+    K = 2 * r + 1
+    out = np.zeros((K, K))
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            acc = 0.0
+            for c in range(m):
+                for i in range(N):
+                    for j in range(N):
+                        ya, xa = y - h + i, x - h + j
+                        yb, xb = by - h + i + dy, bx - h + j + dx
+                        assert 0 <= ya < hA and 0 <= xa < wA and 0 <= yb < hB and 0 <= xb < wB
+                        acc += (D1[c, ya, xa] - D2[c, yb, xb]) ** 2
+            out[dy + r, dx + r] = acc
+    return out
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_flush_right_and_bottom_windows(N):
+    """A template flush against A's right and bottom edges, and a search box
+    flush against B's, are inside and matched over every offset (the surface
+    equals the index-checked loop, so the last row and column are read); one
+    pixel further is out of bounds.  Even and odd N."""
+    rng = np.random.default_rng(40 + N)
+    r = 2
+    D1 = rng.random((2, 10, 12))   # A: 10 x 12
+    D2 = rng.random((2, 13, 11))   # B: 13 x 11
+    h = N // 2
+    xr, yb = 12 - N + h, 10 - N + h            # template flush right / bottom in A
+    sxr, syb = 11 - N - r + h, 13 - N - r + h  # search box flush right / bottom in B
+    cases = [((xr, yb, 5, 6), True), ((xr + 1, yb, 5, 6), False), ((xr, yb + 1, 5, 6), False),
+             ((5, 5, sxr, syb), True), ((5, 5, sxr + 1, syb), False), ((5, 5, sxr, syb + 1), False),
+             ((h, h, h + r, h + r), True), ((h - 1, h, h + r, h + r), False), ((h, h, h + r - 1, h + r), False)]
+    res = O.match(D1, D2, [c for c, _ in cases], N, r, surfaces=True)
+    for k, (cp, inside) in enumerate(cases):
+        assert res["status"][k] == (O.STATUS_OK if inside else O.STATUS_OUT_OF_BOUNDS), cp
+        if inside:
+            np.testing.assert_allclose(res["surfaces"][k], _ssd_loop(D1, D2, cp, N, r), rtol=1e-13)
+        else:
+            assert np.all(np.isnan(res["surfaces"][k]))
+
+
 # ------------------------------------------------------- FFT cross-check pins
 
 @pytest.mark.parametrize("m", [1, 3, 9])
