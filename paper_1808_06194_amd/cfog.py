@@ -212,6 +212,23 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _check_out(t: Optional[torch.Tensor], shape, dtype, like: torch.Tensor, what: str):
+    """A caller-supplied output must have exactly the layout the library
+    writes: shape, dtype, contiguous, on the image's device."""
+    if t is None:
+        return
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype or not t.is_contiguous() or t.device != like.device:
+        raise ValueError(f"{what} must be a contiguous {dtype} tensor of shape {tuple(shape)} on {like.device}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device} (contiguous={t.is_contiguous()})")
+
+
+def _check_workspace(ws: Optional[torch.Tensor], need: int, what: str):
+    if ws is None:
+        return
+    if ws.dtype != torch.uint8 or not ws.is_cuda or not ws.is_contiguous() or ws.numel() < need:
+        raise ValueError(f"{what}: workspace must be a contiguous cuda uint8 tensor of >= {need} bytes")
+
+
 def extract_workspace_size(H: int, W: int) -> int:
     return int(load().cfog_extract_workspace_size(int(H), int(W)))
 
@@ -226,10 +243,14 @@ def cfog_extract(img: torch.Tensor, m: int = 9, sigma: float = 0.8, radius: int 
     if img.dim() != 2 or img.dtype != torch.float32 or not img.is_cuda or img.stride(1) != 1:
         raise ValueError("img must be a 2-D row-contiguous cuda float32 tensor")
     H, W = img.shape
+    _check_out(vol, (m, H, W), torch.float32, img, "vol")
+    _check_out(sat if with_sat else None, (H + 1, W + 1), torch.float64, img, "sat")
     if vol is None:
         vol = torch.empty((m, H, W), dtype=torch.float32, device=img.device)
     if with_sat and sat is None:
         sat = torch.empty((H + 1, W + 1), dtype=torch.float64, device=img.device)
+    if with_sat:
+        _check_workspace(workspace, extract_workspace_size(H, W), "cfog_extract")
     ctx = context(img.device.index)
     rc = load().cfog_extract_scheme(ctx.handle, img.data_ptr(), H, W, img.stride(0), m, float(sigma), int(radius),
                                     int(scheme), vol.data_ptr(), _ptr(sat) if with_sat else None, _ptr(workspace),
@@ -267,6 +288,17 @@ def cfog_extract_batch(imgs, m: int = 9, sigma: float = 0.8, radius: int = -1, w
     elif sats is None:
         sats = [torch.empty((img.shape[0] + 1, img.shape[1] + 1), dtype=torch.float64, device=img.device)
                 for img in imgs]
+    if len(vols) != len(imgs) or len(sats) != len(imgs):
+        raise ValueError("cfog_extract_batch: one volume (and SAT) per image")
+    for i, (img, vol, sat) in enumerate(zip(imgs, vols, sats)):
+        H, W = img.shape
+        _check_out(vol, (m, H, W), torch.float32, img, f"vols[{i}]")
+        if with_sat:
+            if sat is None:
+                raise ValueError(f"sats[{i}] is None")
+            _check_out(sat, (H + 1, W + 1), torch.float64, img, f"sats[{i}]")
+    if with_sat:
+        _check_workspace(workspace, extract_batch_workspace_size([img.shape for img in imgs]), "cfog_extract_batch")
     arr = _image_array(imgs, vols, sats)
     ctx = context(imgs[0].device.index if len(imgs) else None)
     rc = load().cfog_extract_batch(ctx.handle, arr, len(imgs), m, float(sigma), int(radius), int(scheme),
@@ -286,6 +318,10 @@ def fhog_extract(img: torch.Tensor, cell: int = 4, with_sat: bool = True, vol: O
     if img.dim() != 2 or img.dtype != torch.float32 or not img.is_cuda or img.stride(1) != 1:
         raise ValueError("img must be a 2-D row-contiguous cuda float32 tensor")
     H, W = img.shape
+    _check_out(vol, (FHOG_CHANNELS, H, W), torch.float32, img, "vol")
+    _check_out(sat if with_sat else None, (H + 1, W + 1), torch.float64, img, "sat")
+    if with_sat:
+        _check_workspace(workspace, extract_workspace_size(H, W), "fhog_extract")
     if vol is None:
         vol = torch.empty((FHOG_CHANNELS, H, W), dtype=torch.float32, device=img.device)
     if with_sat and sat is None:

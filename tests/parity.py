@@ -18,7 +18,30 @@ import oracle as O
 
 SURF_TOL = 1e-4
 VOL_TOL = 1e-5
-BF16_TOL = 2.0 ** -8 + 1e-5
+
+U_BF16 = 2.0 ** -8   # unit roundoff of round-to-nearest bfloat16 (8 significant bits)
+U_F32 = 2.0 ** -24   # unit roundoff of fp32
+
+
+def bf16_tol(N: int, r: int, m: int = 9) -> float:
+    """Worst-case bound on |S_bf16(d) - S(d)| / (E1 + E2(d)) for the BF16
+    MFMA direct path (template side N, radius r, m channels):
+      * T and S rounded to bf16 (relative error <= u each), products exact in
+        fp32: |T~ S~ - T S| <= (2u + u^2) |T S|;
+      * fp32 accumulation along at most L additions per output:
+        gamma_L (1 + u)^2 sum |T S|, gamma_L = L u32 / (1 - L u32);
+      * sum |T S| <= sqrt(E1 E2) <= (E1 + E2) / 2 (Cauchy-Schwarz, then the
+        arithmetic-geometric mean), and S = E1 + E2 - 2C doubles the
+        correlation error;
+      * the final rounding of S (at most 2 (E1 + E2)) to fp32: 2 u32.
+    L follows the kernel's accumulation: each wave adds m channels x
+    ceil((N + 2r) / 8) search rows x ceil(N / 32) column chunks of MFMAs into
+    one accumulator, each MFMA adding 32 products (counted as 32 sequential
+    additions), then the 8 wave partials are added."""
+    Ws = N + 2 * r
+    L = m * (-(-Ws // 8)) * (-(-N // 32)) * 32 + 8
+    gamma = L * U_F32 / (1.0 - L * U_F32)
+    return (2 * U_BF16 + U_BF16 ** 2) + gamma * (1 + U_BF16) ** 2 + 2 * U_F32
 
 
 def check_volume(vol_gpu: np.ndarray, vol_ora: np.ndarray, tol: float = VOL_TOL) -> float:

@@ -112,7 +112,7 @@ def test_match_on_fhog_volumes(cf, path):
     res = {k: v.cpu().numpy() for k, v in cf.results(job.out).items()}
     D1, D2 = O.fhog(A.astype(np.float64)), O.fhog(B.astype(np.float64))
     ora = O.match(D1, D2, cps, N, r, surfaces=True)
-    tol = parity.BF16_TOL if path == "mfma" else parity.SURF_TOL
+    tol = parity.bf16_tol(N, r, m=cf.FHOG_CHANNELS) if path == "mfma" else parity.SURF_TOL
     stats = {}
     for k, cp in enumerate(cps):
         E1, E2 = O.energies(D1, D2, cp, N, r)
