@@ -41,6 +41,7 @@ one GPU.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -91,48 +92,255 @@ def extract_bytes_per_px(m: int = 9) -> int:
     return 4 + 4 * m + 8
 
 
-def cpu_baseline(pairs, budget_s: float = 20.0, descriptor: str = "cfog"):
-    """The FP64 oracle (the descriptor volumes of the first pair's images +
-    brute-force SSD) on a bounded sample of its control points, scaled to CP
-    matches/s of that pair."""
+# ------------------------------------------------------------ CPU leg
+#
+# The oracle (FP64, test infrastructure) is timed on the host cores on a
+# bounded sample of the workload's control points, in forked worker processes
+# started before anything touches the GPU.  The same oracle outputs then judge
+# the GPU's results for those points (the parity block of the JSON line).
+
+CFOG_R = 3  # Gaussian radius at sigma = 0.8: int(4 sigma + 0.5)
+PAPER_CFOG_MPX_S = 512 * 512 / 0.210 / 1e6  # Table III: 0.210 s per 512^2 image on an i7-4710MQ
+
+
+def cpu_workers() -> int:
+    """Host cores this process may use (the GPU machine grants 16 per GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _crop(img: np.ndarray, y0: int, x0: int, h: int, w: int, margin: int):
+    """Rows [y0 - margin, y0 + h + margin) x cols [x0 - margin, ...) of img,
+    clipped to the image, and the offset of (y0, x0) inside the crop.  CFOG at
+    a pixel reads only its (2R + 3)^2 neighbourhood, so with margin R + 1 the
+    oracle's CFOG of the crop equals that of the whole image on the box."""
+    H, W = img.shape
+    ya, xa = max(0, y0 - margin), max(0, x0 - margin)
+    yb, xb = min(H, y0 + h + margin), min(W, x0 + w + margin)
+    return np.ascontiguousarray(img[ya:yb, xa:xb]), y0 - ya, x0 - xa
+
+
+def _oracle_point_task(args):
+    """One sampled control point through the oracle: CFOG of the crops that
+    hold its template and search box, the direct SSD surface (Eq. 3) and the
+    FP64 FFT form (Eqs. 5, 8-9) with its own SATs; times of each part."""
     import oracle as O
-    desc = {"cfog": O.cfog, "scheme1": lambda I: O.cfog(I, scheme=1), "fhog": O.fhog}[descriptor]
+    A, B, cp, N, r, m, desc = args
+    x, y, bx, by = (int(v) for v in cp)
+    h = N // 2
+    Ws = N + 2 * r
+    M = CFOG_R + 1
+    ca, ay, ax = _crop(A, y - h, x - h, N, N, M)
+    cb, by0, bx0 = _crop(B, by - h - r, bx - h - r, Ws, Ws, M)
+    fn = {"cfog": lambda I: O.cfog(I, m=m), "scheme1": lambda I: O.cfog(I, m=m, scheme=1), "fhog": O.fhog}[desc]
     t0 = time.perf_counter()
-    A, B, cps, N, r = pairs[0]["A"], pairs[0]["B"], pairs[0]["cps"], pairs[0]["N"], pairs[0]["r"]
-    D1 = desc(A.astype(np.float64))
-    D2 = desc(B.astype(np.float64))
-    t_ext = time.perf_counter() - t0
+    D1 = fn(ca.astype(np.float64))
+    D2 = fn(cb.astype(np.float64))
     t1 = time.perf_counter()
-    n = 0
-    for cp in cps:
-        O.ssd_surface_direct(D1, D2, cp, N, r)
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    t_cp = (time.perf_counter() - t1) / n
-    total = t_ext + len(cps) * t_cp
-    return dict(value=round(len(cps) / total, 3), unit="CP matches/s", cores=1, kind="oracle",
-                sample=f"FP64 {descriptor} of both {A.shape[0]}x{A.shape[1]} images ({t_ext:.1f} s) + direct SSD of "
-                       f"{n} of {len(cps)} CPs ({t_cp:.3f} s/CP), extrapolated to all {len(cps)} CPs",
-                seconds=round(time.perf_counter() - t0, 2))
+    T = np.ascontiguousarray(D1[:, ay:ay + N, ax:ax + N])
+    Sw = np.ascontiguousarray(D2[:, by0:by0 + Ws, bx0:bx0 + Ws])
+    loc = (h, h, h + r, h + r)
+    S = O.ssd_surface_direct(T, Sw, loc, N, r)
+    t2 = time.perf_counter()
+    sat1 = O.sat(np.sum(T * T, axis=0))
+    sat2 = O.sat(np.sum(Sw * Sw, axis=0))
+    t3 = time.perf_counter()
+    Sf = O.ssd_surface_fft(T, Sw, loc, N, r, None, sat1, sat2)
+    t4 = time.perf_counter()
+    E1, E2 = O.energies(T, Sw, loc, N, r)
+    return dict(S=S, Sf=Sf, E1=E1, E2=E2, px=ca.size + cb.size, t_cfog=t1 - t0, t_direct=t2 - t1,
+                t_fft=t4 - t3, t_sat=t3 - t2)
 
 
-def make_workload(name: str):
+def _oracle_tile_task(args):
+    """The oracle's CFOG of one image tile; returns (pixels, seconds)."""
+    import oracle as O
+    tile, m, desc = args
+    fn = {"cfog": lambda I: O.cfog(I, m=m), "scheme1": lambda I: O.cfog(I, m=m, scheme=1), "fhog": O.fhog}[desc]
+    t0 = time.perf_counter()
+    fn(tile.astype(np.float64))
+    return tile.size, time.perf_counter() - t0
+
+
+def sample_points(name: str, pairs, n_sample: int):
+    """Seeded sample of (pair, cp) indices: every control point of small
+    workloads, one per pair for batch_64 (so every FFT-size bucket is in it),
+    else n_sample points of the single pair."""
+    rng = np.random.default_rng(np.random.SeedSequence([8, 1808]))
+    if len(pairs) > 1:
+        return [(j, int(rng.integers(0, len(p["cps"])))) for j, p in enumerate(pairs)]
+    n = len(pairs[0]["cps"])
+    if n <= n_sample:
+        return [(0, k) for k in range(n)]
+    return [(0, int(k)) for k in np.sort(rng.choice(n, n_sample, replace=False))]
+
+
+def cpu_leg(name: str, pairs, m: int, desc: str, pool, n_workers: int, n_sample: int):
+    """The oracle on the sampled points (timed) and on image tiles (the CPU
+    CFOG rate), extrapolated to the whole workload over n_workers cores:
+      * cpu_baseline: FP64 CFOG of every image + direct SSD (Eq. 3) of every
+        point, the oracle as it stands;
+      * cpu_fft_baseline: FP64 CFOG + SATs + the FFT form (Eqs. 5, 8-9) per
+        point, the CPU version of the same method.
+    Returns (cpu_baseline, cpu_fft_baseline, cpu_cfog, sample, oracle
+    outputs per sampled point)."""
+    t_all = time.perf_counter()
+    sample = sample_points(name, pairs, n_sample)
+    tasks = [(pairs[j]["A"], pairs[j]["B"], pairs[j]["cps"][k], pairs[j]["N"], pairs[j]["r"], m, desc)
+             for j, k in sample]
+    outs = list(pool.map(_oracle_point_task, tasks, chunksize=1))
+    # CPU CFOG rate on 512^2 tiles (Table III's image size), one per worker
+    rng = np.random.default_rng(512)
+    tiles = []
+    for i in range(n_workers):
+        p = pairs[i % len(pairs)]
+        img = p["A"] if i % 2 == 0 else p["B"]
+        H, W = img.shape
+        th, tw = min(512, H), min(512, W)
+        y0, x0 = int(rng.integers(0, H - th + 1)), int(rng.integers(0, W - tw + 1))
+        tiles.append((np.ascontiguousarray(img[y0:y0 + th, x0:x0 + tw]), m, desc))
+    tile_res = list(pool.map(_oracle_tile_task, tiles, chunksize=1))
+    wall = time.perf_counter() - t_all
+    px_s_core = sum(px for px, _ in tile_res) / sum(t for _, t in tile_res)
+    # per-point cost models fitted on the sample: direct SSD ~ m N^2 (2r+1)^2,
+    # FFT form ~ m Ws^2 log2(Ws^2) (numpy's FFT of the Ws x Ws window)
+    def wd(N, r):
+        return float(N * N * (2 * r + 1) ** 2)
+
+    def wf(N, r):
+        Ws = N + 2 * r
+        return float(Ws * Ws * np.log2(Ws * Ws))
+    cd = sum(o["t_direct"] for o in outs) / sum(wd(pairs[j]["N"], pairs[j]["r"]) for j, _ in sample)
+    cf_ = sum(o["t_fft"] for o in outs) / sum(wf(pairs[j]["N"], pairs[j]["r"]) for j, _ in sample)
+    n_cps = sum(len(p["cps"]) for p in pairs)
+    px_total = sum(p["A"].size + p["B"].size for p in pairs)
+    t_ext = px_total / px_s_core                      # core-seconds
+    t_direct = cd * sum(len(p["cps"]) * wd(p["N"], p["r"]) for p in pairs)
+    t_fft = cf_ * sum(len(p["cps"]) * wf(p["N"], p["r"]) for p in pairs)
+    t_sat = px_total * 8.0 / 1e9                       # two cumulative sums: negligible, counted at 8 ns/px
+    busy = sum(o["t_cfog"] + o["t_direct"] + o["t_fft"] + o["t_sat"] for o in outs) + sum(t for _, t in tile_res)
+    smp = (f"{len(sample)} sampled control points (seeded; {'one per pair' if len(pairs) > 1 else 'of the pair'}) "
+           f"through the oracle on {n_workers} worker processes: CFOG of their crops, direct SSD and FFT form, "
+           f"plus CFOG of {len(tiles)} image tiles of up to 512^2; per-point costs fitted as m N^2 (2r+1)^2 "
+           f"(direct) and m Ws^2 log2 Ws^2 (FFT form) and extrapolated to all {n_cps} points and "
+           f"{px_total / 1e6:.1f} Mpx of CFOG; {busy:.1f} core-s of oracle work in {wall:.1f} s wall")
+    host = f"{cpu_model()}, {n_workers} of {os.cpu_count()} cores used"
+    base = dict(value=round(n_cps / ((t_ext + t_direct) / n_workers), 3), unit="CP matches/s", cores=n_workers,
+                kind="oracle", sample=smp, host=host,
+                est_core_seconds=dict(cfog=round(t_ext, 1), direct_ssd=round(t_direct, 1)))
+    fft = dict(value=round(n_cps / ((t_ext + t_sat + t_fft) / n_workers), 3), unit="CP matches/s",
+               cores=n_workers, kind="oracle FFT form (FP64 numpy FFT + SAT energies)", sample=smp, host=host,
+               est_core_seconds=dict(cfog=round(t_ext, 1), sat=round(t_sat, 1), fft_form=round(t_fft, 1)))
+    cfog_rate = dict(mpx_per_s_per_core=round(px_s_core / 1e6, 3),
+                     mpx_per_s=round(px_s_core * n_workers / 1e6, 3), cores=n_workers,
+                     paper_mpx_per_s=round(PAPER_CFOG_MPX_S, 3),
+                     paper_hardware="Intel Core i7-4710MQ @ 2.5 GHz, one 512^2 image in 0.210 s (Table III)",
+                     sample=f"{len(tiles)} tiles of up to 512^2 from the workload's images", host=host)
+    return base, fft, cfog_rate, sample, outs
+
+
+# ------------------------------------------------------------ parity block
+#
+# The GPU result of each sampled point against the oracle's direct surface,
+# with the rules of the parity tests: the surface within tol (E1 + E2(d)) per
+# element; the offset equal to the oracle's, or an excused near-tie where the
+# oracle's own values differ by at most tol (2 E1 + E2(d_gpu) + E2(d_ora)).
+
+def parity_block(sample, outs, results, surfaces, pairs, tol: float, plan_of=None):
+    exact = excused = mismatched = bad_status = 0
+    worst = 0.0
+    rel_max = 0.0
+    fft_vs_direct = 0.0
+    buckets = {}
+    for (j, k), o in zip(sample, outs):
+        r = pairs[j]["r"]
+        S, E1, E2 = o["S"], o["E1"], o["E2"]
+        fft_vs_direct = max(fft_vs_direct, float(np.max(np.abs(o["Sf"] - S) / (E1 + E2))))
+        res = results[j]
+        if int(res[k, 4]) != 0:
+            bad_status += 1
+            continue
+        sg = surfaces[j][k].astype(np.float64)
+        err = np.abs(sg - S) / (E1 + E2)
+        worst = max(worst, float(err.max()))
+        rel_max = max(rel_max, float(np.max(np.abs(sg - S)) / max(1e-300, float(np.max(np.abs(S))))))
+        dxg, dyg = int(res[k, 0]), int(res[k, 1])
+        io = int(np.argmin(S))
+        dyo, dxo = divmod(io, 2 * r + 1)
+        dxo, dyo = dxo - r, dyo - r
+        if (dxg, dyg) == (dxo, dyo):
+            exact += 1
+        else:
+            gap = S[dyg + r, dxg + r] - S.reshape(-1)[io]
+            allow = tol * (2 * E1 + E2[dyg + r, dxg + r] + E2[dyo + r, dxo + r])
+            if gap <= allow:
+                excused += 1
+            else:
+                mismatched += 1
+        if plan_of is not None:
+            P = plan_of(j)
+            buckets[P] = buckets.get(P, 0) + 1
+    n = len(sample)
+    out = dict(points=n, exact_offsets=exact, excused_near_ties=excused, mismatches=mismatched,
+               status_not_ok=bad_status, excused_fraction=round(excused / max(1, n), 4),
+               mismatch_rate=round(mismatched / max(1, n), 4),
+               max_norm_ssd_err=float(f"{worst:.3e}"), max_rel_ssd_err=float(f"{rel_max:.3e}"),
+               tol_norm=float(f"{tol:.4e}"), oracle_fft_vs_direct=float(f"{fft_vs_direct:.2e}"),
+               judge="oracle direct SSD (Eq. 3) in FP64 on the sampled points; normalised error "
+                     "|S_gpu - S_ora| / (E1 + E2(d))")
+    if buckets:
+        out["points_per_fft_size"] = {str(k): v for k, v in sorted(buckets.items())}
+    return out
+
+
+def self_consistency(results, surfaces, pairs):
+    """Every point: its offset is the argmin of its own surface and its best
+    value that surface's minimum; returns the number of points that fail."""
+    bad = 0
+    for res, surf, p in zip(results, surfaces, pairs):
+        K = 2 * p["r"] + 1
+        ok = res[:, 4] == 0
+        flat = surf.reshape(len(res), -1)
+        i = np.argmin(np.where(np.isnan(flat), np.inf, flat), axis=1)
+        bad += int(np.sum(ok & ((i % K - p["r"] != res[:, 0]) | (i // K - p["r"] != res[:, 1]))))
+        best = res[:, 2].view(np.float32)
+        bad += int(np.sum(ok & (flat[np.arange(len(res)), i] != best)))
+    return bad
+
+
+def make_workload(name: str, speckle_shape: float = 4.0):
     from paper_1808_06194_amd import synth
     if name in ("plain_2048", "plain_256"):
-        w = synth.PLAIN_2048 if name == "plain_2048" else synth.PLAIN_256
+        w = dict(synth.PLAIN_2048 if name == "plain_2048" else synth.PLAIN_256)
+        if speckle_shape != 4.0:
+            w["spec"] = dataclasses.replace(w["spec"], speckle_shape=speckle_shape)
         A, B, s, cps, N, r = synth.plain_workload(w)
         return [dict(A=A, B=B, shift=s, cps=cps, N=N, r=r)]
     if name == "precision_4096":
-        spec = synth.PairSpec(4096, 4096, 3200, (3.0, 40.0), 1200, 20)
+        spec = synth.PairSpec(4096, 4096, 3200, (3.0, 40.0), 1200, 20, speckle_shape=speckle_shape)
         A, B, s = synth.make_pair(spec, (3, 0))
         cps = synth.random_cps(np.random.default_rng(np.random.SeedSequence([3, 1])), 4096, 4096, 128, 32, 10000)
         return [dict(A=A, B=B, shift=s, cps=cps, N=128, r=32)]
     if name == "batch_64":
         from concurrent.futures import ProcessPoolExecutor
         import multiprocessing as mp
-        with ProcessPoolExecutor(max_workers=8, mp_context=mp.get_context("fork")) as ex:
-            return synth.batch_workload(n_pairs=64, pool_map=ex.map)
+        with ProcessPoolExecutor(max_workers=cpu_workers(), mp_context=mp.get_context("fork")) as ex:
+            return synth.batch_workload(n_pairs=64, pool_map=ex.map, speckle_shape=speckle_shape)
     raise ValueError(name)
 
 
@@ -144,37 +352,64 @@ def describe(name: str, pairs) -> str:
         return "plain_256: 256^2 pair, 25 CPs (5x5 grid), template 48, radius 10, m=9, sigma=0.8"
     if name == "precision_4096":
         return "precision_4096: 4096^2 pair, 10000 random CPs, template 128, radius 32, m=9, sigma=0.8"
-    return f"batch_64: 64 pairs (sides 512-4096), {ncp} CPs, templates 40-120, radii 5-30, m=9, sigma=0.8"
+    return (f"batch_64: 64 pairs (sides 512-4096), {ncp} CPs, templates 40-120, radii 5-30, m=9, sigma=0.8; "
+            "all pairs extracted and matched in one step")
+
+
+MATCHER_SOURCES = ("match_fft.hip", "dft.hpp", "epilogue.hpp", "kernels.hpp", "window.hpp", "split_plan.hpp",
+                   "abi.hip")
+
+
+def matcher_digest() -> str:
+    """sha256 over the sources the FFT matcher launches are built from."""
+    h = hashlib.sha256()
+    for f in MATCHER_SOURCES:
+        with open(os.path.join(ROOT, "paper_1808_06194_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def traffic_record(kernel_key: str):
-    """HBM bytes per launch measured by counters, if recorded for the current
-    matcher source (profiles/traffic.json); None otherwise."""
+    """HBM bytes per matching call measured by counters (profiles/traffic.json),
+    if recorded for the current matcher sources; None otherwise."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_1808_06194_amd", "csrc", "match_fft.hip")
     try:
-        rec = json.load(open(path))
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        with open(path) as f:
+            rec = json.load(f)
         e = rec.get(kernel_key)
-        if e and e.get("source_sha256") == digest:
+        if e and e.get("sources_sha256") == matcher_digest():
             return e["bytes_per_launch"]
     except (OSError, ValueError):
         pass
     return None
 
 
+def bf16_tol(N: int, r: int, m: int = 9) -> float:
+    """Bound on |S_bf16(d) - S(d)| / (E1 + E2(d)) of the BF16 MFMA path:
+    bf16 rounding of both operands (unit roundoff 2^-8) plus FP32 accumulation
+    over the kernel's longest chain of additions, with sum |T S| <= (E1 + E2)/2
+    and the final FP32 rounding of S (the derivation is in match_direct.hip)."""
+    u, u32 = 2.0 ** -8, 2.0 ** -24
+    L = m * (-(-(N + 2 * r) // 8)) * (-(-N // 32)) * 32 + 8
+    gamma = L * u32 / (1.0 - L * u32)
+    return (2 * u + u * u) + gamma * (1 + u) ** 2 + 2 * u32
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="plain_2048",
-                    choices=["plain_2048", "plain_256", "precision_4096", "batch_64", "serve", "harris_8192",
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batch_64",
+                    choices=["batch_64", "plain_2048", "plain_256", "precision_4096", "serve", "harris_8192",
                              "reject_3000"])
     ap.add_argument("--path", choices=["plain", "batched", "fft", "mfma"], default=None)
     ap.add_argument("--descriptor", choices=["cfog", "scheme1", "fhog"], default="cfog")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--speckle-shape", type=float, default=4.0,
+                    help="shape of B's Gamma speckle (4: the workload recipe; larger is milder)")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (then no cpu_baseline and no parity block)")
+    ap.add_argument("--cpu-sample", type=int, default=64, help="control points the oracle leg runs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain device-to-device copy of this many MiB "
                          "(a counter calibration point for HBM traffic)")
@@ -199,17 +434,33 @@ def main():
         run_reject(args)
         return
 
-    pairs = make_workload(args.workload)  # before anything touches the GPU (worker processes fork)
+    t_gen = time.perf_counter()
+    pairs = make_workload(args.workload, args.speckle_shape)  # before anything touches the GPU
+    print(f"[bench] {args.workload}: {len(pairs)} pairs, {sum(len(p['cps']) for p in pairs)} CPs generated in "
+          f"{time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    desc = args.descriptor
+    m = 36 if desc == "fhog" else 9
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle leg, in forked workers before the GPU is initialised
+        from concurrent.futures import ProcessPoolExecutor
+        import multiprocessing as mp
+        nw = cpu_workers()
+        t_cpu = time.perf_counter()
+        with ProcessPoolExecutor(max_workers=nw, mp_context=mp.get_context("fork")) as ex:
+            cpu = cpu_leg(args.workload, pairs, m, desc, ex, nw, args.cpu_sample)
+        print(f"[bench] oracle leg: {len(cpu[3])} points on {nw} cores in {time.perf_counter() - t_cpu:.1f} s",
+              file=sys.stderr, flush=True)
+
     import torch
     from paper_1808_06194_amd import cfog
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    desc = args.descriptor
-    m = cfog.FHOG_CHANNELS if desc == "fhog" else 9
     path = args.path or {"batch_64": "batched", "precision_4096": "fft"}.get(args.workload, "plain")
-    flags = {"plain": cfog.PATH_PLAIN_FFT, "fft": cfog.PATH_PLAIN_FFT, "mfma": cfog.PATH_MFMA_BF16,
-             "batched": cfog.PATH_BATCHED_FFT | cfog.AUTOTUNE | cfog.USE_GRAPH}[path]
+    path_flags = {"plain": cfog.PATH_PLAIN_FFT, "fft": cfog.PATH_PLAIN_FFT, "mfma": cfog.PATH_MFMA_BF16,
+                  "batched": cfog.PATH_BATCHED_FFT | cfog.AUTOTUNE | cfog.USE_GRAPH}
+    flags = path_flags[path]
     imgs, jobs = [], []
     for p in pairs:
         H, W = p["A"].shape
@@ -236,20 +487,24 @@ def main():
     fork, join = torch.cuda.Event(), torch.cuda.Event()
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
+    def extract(st=None):
+        st = stream if st is None else st
+        if desc == "fhog":
+            fork.record(st)
+            side.wait_event(fork)
+            for i, (img, vol, sat) in enumerate(imgs):
+                s2 = st if i % 2 == 0 else side
+                cfog.fhog_extract(img, vol=vol, sat=sat, stream=s2, workspace=ws_ext[i % 2])
+            join.record(side)
+            st.wait_event(join)
+        else:
+            cfog.cfog_extract_batch(batch_imgs, m=m, vols=batch_vols, sats=batch_sats, stream=st,
+                                    workspace=ws_batch, scheme=1 if desc == "scheme1" else 2)
+
     def step(evs=None):
         if evs:
             evs[0].record(stream)
-        if desc == "fhog":
-            fork.record(stream)
-            side.wait_event(fork)
-            for i, (img, vol, sat) in enumerate(imgs):
-                st = stream if i % 2 == 0 else side
-                cfog.fhog_extract(img, vol=vol, sat=sat, stream=st, workspace=ws_ext[i % 2])
-            join.record(side)
-            stream.wait_event(join)
-        else:
-            cfog.cfog_extract_batch(batch_imgs, m=m, vols=batch_vols, sats=batch_sats, stream=stream,
-                                    workspace=ws_batch, scheme=1 if desc == "scheme1" else 2)
+        extract()
         if evs:
             evs[1].record(stream)
         cfog.match_batch(jobs, m=m, flags=flags, stream=stream)
@@ -271,13 +526,13 @@ def main():
     ext_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
     match_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
     t_match = float(np.mean(match_ms)) * 1e-3
+    t_ext = float(np.mean(ext_ms)) * 1e-3
+    timed_out = [j.out.cpu().numpy() for j in jobs]
 
     ok = recovered = 0
-    for p, j in zip(pairs, jobs):
-        res = cfog.results(j.out)
-        dx, dy, st = (res[k].cpu().numpy() for k in ("dx", "dy", "status"))
-        ok += int(np.sum(st == 0))
-        recovered += int(np.sum(np.hypot(dx - p["shift"][0], dy - p["shift"][1]) <= 1.5))
+    for p, res in zip(pairs, timed_out):
+        ok += int(np.sum(res[:, 4] == 0))
+        recovered += int(np.sum(np.hypot(res[:, 0] - p["shift"][0], res[:, 1] - p["shift"][1]) <= 1.5))
 
     out = {
         "metric": "CP matches/sec (CFOG+3DFFT SSD) on 1 MI355X; p50/p99 match latency",
@@ -292,25 +547,28 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16 x bf16 -> f32 (FP64 energies)" if path == "mfma" else "f32 (FP64 energies)",
         "data": "synthetic",
-        "config": {"workload": describe(args.workload, pairs), "path": path, "n_cps": n_cps,
+        "config": {"workload": describe(args.workload, pairs), "path": path, "n_cps": n_cps, "pairs": len(pairs),
                    "descriptor": {"cfog": "CFOG (Eq. 2)", "scheme1": "CFOG scheme 1 (binned orientations)",
-                                  "fhog": "pixel-wise HOG, 36 channels, cell 4"}[desc], "m": m},
+                                  "fhog": "pixel-wise HOG, 36 channels, cell 4"}[desc], "m": m,
+                   "speckle_shape": args.speckle_shape},
         "latency_ms": {"step_p50": round(float(np.percentile(step_ms, 50)), 4),
                        "step_p99": round(float(np.percentile(step_ms, 99)), 4),
                        "match_p50": round(float(np.percentile(match_ms, 50)), 4),
                        "match_p99": round(float(np.percentile(match_ms, 99)), 4),
                        "extract_p50": round(float(np.percentile(ext_ms, 50)), 4)},
         "match_only_cp_per_s": round(n_cps / t_match, 1),
-        "extract_gbs": round(sum(i[0].numel() for i in imgs) * extract_bytes_per_px(m)
-                             / (np.mean(ext_ms) * 1e-3) / 1e9, 1),
         "recovered_1p5px": round(recovered / max(1, n_cps), 4),
         "cp_status_ok": ok,
     }
 
-    # roofline of the dominant kernel (the matcher launch timed above)
+    # roofline of the matching call (all matcher launches of the step: one
+    # per FFT-size bucket on forked streams, plus the split reduce), timed by
+    # HIP events on the stream the call is issued on; the forked streams join
+    # back before the closing event
     bytes_launch = sum(len(p["cps"]) * algorithmic_bytes_per_cp(p["N"], p["r"], m) for p in pairs)
     gbs = bytes_launch / t_match / 1e9
     hbm = dict(achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4))
+    plans = {}
     if path == "mfma":
         flops = sum(len(p["cps"]) * direct_flops_per_cp(p["N"], p["r"], m) for p in pairs)
         tfs = flops / t_match / 1e12
@@ -321,24 +579,70 @@ def main():
         flops = 0.0
         for p in pairs:
             P = cfog.plan_for(p["N"], p["r"], m)
+            plans[(p["N"], p["r"])] = P
             flops += len(p["cps"]) * fft_flops_per_cp(p["N"], p["r"], P, m)
         tfs = flops / t_match / 1e12
-        if flops / (FP32_PEAK_TFS * 1e12) > bytes_launch / (HBM_PEAK_GBS * 1e9):
-            roof = dict(bound="alu", achieved=round(tfs, 3), peak=FP32_PEAK_TFS, unit="TFLOP/s",
-                        frac=round(tfs / FP32_PEAK_TFS, 4))
-        else:
-            roof = dict(hbm)
-            roof["bound"] = "hbm"
-        # the timed span is the whole match_batch call: the matcher launch and,
-        # where its last round is split by channel groups, the reduce kernel
-        kernel = "match_fft_kernel" + (f"<P={cfog.plan_for(pairs[0]['N'], pairs[0]['r'], m)}>"
-                                       if len(pairs) == 1 else "<mixed P>") + " + split_reduce_kernel"
+        roof = dict(hbm)
+        roof["bound"] = "hbm"
+        Ps = sorted(set(plans.values()))
+        kernel = ("match_fft_kernel<P=" + ",".join(str(P) for P in Ps) + "> + split_reduce_kernel, one "
+                  "match_batch call")
     key = f"{args.workload}:{path}" + ("" if desc == "cfog" else f":{desc}")
     traffic = traffic_record(key) if path != "mfma" else None
     roof.update(kernel=kernel, traffic=traffic, bytes_per_launch=bytes_launch, flops_per_launch=flops,
-                hbm=hbm, alu=dict(achieved=round(tfs, 3), unit="TFLOP/s",
-                                  peak=BF16_PEAK_TFS if path == "mfma" else FP32_PEAK_TFS))
+                launch_ms=round(t_match * 1e3, 4), hbm=hbm,
+                alu=dict(achieved=round(tfs, 3), unit="TFLOP/s",
+                         peak=BF16_PEAK_TFS if path == "mfma" else FP32_PEAK_TFS,
+                         frac=round(tfs / (BF16_PEAK_TFS if path == "mfma" else FP32_PEAK_TFS), 4)))
     out["roofline"] = roof
+    # the extraction call (every image of the step) against the HBM roofline
+    ext_bytes = sum(i[0].numel() for i in imgs) * extract_bytes_per_px(m)
+    egbs = ext_bytes / t_ext / 1e9
+    out["roofline_extract"] = dict(bound="hbm", achieved=round(egbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                                   frac=round(egbs / HBM_PEAK_GBS, 4), bytes_per_launch=ext_bytes,
+                                   launch_ms=round(t_ext * 1e3, 4),
+                                   kernel="cfog_extract_kernel + sat_carry_kernel + sat_fix_kernel, one "
+                                          "cfog_extract_batch call" if desc != "fhog" else "fhog_kernel + SAT")
+
+    # one more step with every surface written: the results must be the timed
+    # ones bit for bit; the surfaces feed the self-consistency check and the
+    # parity block
+    surfs = []
+    for j in jobs:
+        K = 2 * j.r + 1
+        j.surfaces = torch.empty((len(j.cps), K, K), dtype=torch.float32, device=dev)
+        surfs.append(j.surfaces)
+    cfog.match_batch(jobs, m=m, flags=flags, stream=stream)
+    torch.cuda.synchronize()
+    res_s = [j.out.cpu().numpy() for j in jobs]
+    surf_np = [s.cpu().numpy() for s in surfs]
+    same = all(np.array_equal(a, b) for a, b in zip(res_s, timed_out))
+    out["check"] = {"surfaces_run_equals_timed": bool(same),
+                    "self_consistency_failures": self_consistency(res_s, surf_np, pairs)}
+    if cpu is not None:
+        base, fft_base, cfog_rate, sample, outs = cpu
+        out["cpu_baseline"] = base
+        out["cpu_fft_baseline"] = fft_base
+        out["cpu_cfog"] = cfog_rate
+        tol = bf16_tol(pairs[0]["N"], pairs[0]["r"], m) if path == "mfma" else 1e-4
+        plan_of = (lambda j: plans[(pairs[j]["N"], pairs[j]["r"])]) if plans else None
+        blocks = {path: parity_block(sample, outs, res_s, surf_np, pairs, tol, plan_of)}
+        if args.workload == "precision_4096":
+            # the other precision path on the same points (untimed): FP32 FFT
+            # against BF16 MFMA, each at its own bound
+            other = "mfma" if path == "fft" else "fft"
+            for j in jobs:
+                j.out = None
+            cfog.match_batch(jobs, m=m, flags=path_flags[other], stream=stream)
+            torch.cuda.synchronize()
+            res_o = [j.out.cpu().numpy() for j in jobs]
+            surf_o = [s.cpu().numpy() for s in surfs]
+            tol_o = bf16_tol(pairs[0]["N"], pairs[0]["r"], m) if other == "mfma" else 1e-4
+            blocks[other] = parity_block(sample, outs, res_o, surf_o, pairs, tol_o)
+            blocks[other]["self_consistency_failures"] = self_consistency(res_o, surf_o, pairs)
+            blocks["offsets_fft_vs_mfma_differ"] = int(sum(np.sum(np.any(a[:, :2] != b[:, :2], axis=1))
+                                                          for a, b in zip(res_s, res_o)))
+        out["parity"] = blocks
 
     if args.calib_copy_mib:
         # source written first, then 1 GiB of other writes so that the copy's
@@ -353,8 +657,6 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = nb
         del junk
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pairs, args.cpu_budget, desc)
     print(json.dumps(out), flush=True)
 
 

@@ -165,7 +165,7 @@ def _batch_pair(args):
 
 
 def batch_workload(n_pairs: int = 64, sides=(512, 1024, 2048, 4096), seed: int = 2,
-                   max_cps: int = 600, min_cps: int = 50, pool_map=map):
+                   max_cps: int = 600, min_cps: int = 50, pool_map=map, speckle_shape: float = 4.0):
     """Heterogeneous batch: list of dicts (A, B, shift, cps, N, r) per pair.
     `pool_map` may be a process pool's map (each pair has its own seed)."""
     meta = _rng(seed, 999)
@@ -175,7 +175,8 @@ def batch_workload(n_pairs: int = 64, sides=(512, 1024, 2048, 4096), seed: int =
         N = 2 * int(meta.integers(20, 61))
         r = int(meta.integers(5, 31))
         n = int(meta.integers(min_cps, max_cps + 1))
-        draws.append((side, N, r, n, area_scaled_spec(side, min(8, r))))
+        spec = dataclasses.replace(area_scaled_spec(side, min(8, r)), speckle_shape=speckle_shape)
+        draws.append((side, N, r, n, spec))
     imgs = list(pool_map(_batch_pair, [(d[4], seed, j) for j, d in enumerate(draws)]))
     out = []
     for j, ((side, N, r, n, _), (A, B, s)) in enumerate(zip(draws, imgs)):
