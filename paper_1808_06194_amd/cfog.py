@@ -290,16 +290,12 @@ def cfog_extract_batch(imgs, m: int = 9, sigma: float = 0.8, radius: int = -1, w
                 for img in imgs]
     if len(vols) != len(imgs) or len(sats) != len(imgs):
         raise ValueError("cfog_extract_batch: one volume (and SAT) per image")
-    for i, (img, vol, sat) in enumerate(zip(imgs, vols, sats)):
+    for i, (img, vol, sat) in enumerate(zip(imgs, vols, sats)):  # a None SAT: that image gets none
         H, W = img.shape
         _check_out(vol, (m, H, W), torch.float32, img, f"vols[{i}]")
-        if with_sat:
-            if sat is None:
-                raise ValueError(f"sats[{i}] is None")
-            _check_out(sat, (H + 1, W + 1), torch.float64, img, f"sats[{i}]")
-    if with_sat:
-        _check_workspace(workspace, extract_batch_workspace_size([img.shape for img in imgs]), "cfog_extract_batch")
+        _check_out(sat, (H + 1, W + 1), torch.float64, img, f"sats[{i}]")
     arr = _image_array(imgs, vols, sats)
+    _check_workspace(workspace, int(load().cfog_extract_batch_workspace_size(arr, len(imgs))), "cfog_extract_batch")
     ctx = context(imgs[0].device.index if len(imgs) else None)
     rc = load().cfog_extract_batch(ctx.handle, arr, len(imgs), m, float(sigma), int(radius), int(scheme),
                                    _ptr(workspace), workspace.numel() if workspace is not None else 0,
