@@ -262,6 +262,33 @@ size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n
 int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags, void* d_ws,
                 size_t ws_bytes, void* stream);
 
+/* match_batch_noalloc - match_batch for callers that cannot allocate memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  It allocates nothing, host or device: its workspace is a
+ * device array of CFOG_NOALLOC_SCRATCH_MIB MiB that the library holds on each
+ * GPU from its load until the process ends (its address is taken once per
+ * device by cfog_ctx_create).  The caller still owns and passes the inputs
+ * and outputs (the jobs, as for match_batch).
+ *   flags   CFOG_PATH_PLAIN_FFT or CFOG_PATH_MFMA_BF16, optionally
+ *           | CFOG_OBJ_CORR | CFOG_NO_SPLIT (CFOG_EINVAL for the batched path,
+ *           CFOG_AUTOTUNE or CFOG_USE_GRAPH: they stage host tables or time
+ *           trial launches).
+ *   Results are bit-identical to match_batch with a workspace of
+ *   cfog_noalloc_scratch_bytes() bytes (and so to match_batch with its
+ *   recommended workspace whenever that is no larger).  The array needs no
+ *   clearing between calls (every value read is written earlier in the same
+ *   call).  All calls on one GPU share the one array: calls that overlap on
+ *   the device (other streams, other threads, other contexts) race and give
+ *   undefined results; order them on one stream or synchronise.
+ *   Returns CFOG_ENOMEM when the call's workspace without channel splits
+ *   exceeds the array, otherwise as match_batch. */
+#define CFOG_NOALLOC_SCRATCH_MIB 48
+int match_batch_noalloc(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags,
+                        void* stream);
+
+/* Bytes of the device array match_batch_noalloc works in. */
+size_t cfog_noalloc_scratch_bytes(void);
+
 /* Largest N + 2r the FFT paths support. */
 int32_t cfog_max_window(void);
 

@@ -43,7 +43,7 @@ EXPORTS = (
     "cfog_max_window", "cfog_fft_size", "cfog_set_plan", "cfog_plan_for", "cfog_harris_grid",
     "cfog_reject_outliers",
     "cfog_server_create", "cfog_server_destroy", "cfog_server_add_pair", "cfog_server_submit",
-    "cfog_server_poll", "cfog_server_get_stats",
+    "cfog_server_poll", "cfog_server_get_stats", "match_batch_noalloc", "cfog_noalloc_scratch_bytes",
 )
 
 
@@ -132,6 +132,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.match_batch_workspace_size.argtypes = [vp, ctypes.POINTER(cfog_job), i32, i32, i32]
     lib.match_batch_workspace_size.restype = sz
     lib.match_batch.argtypes = [vp, ctypes.POINTER(cfog_job), i32, i32, i32, vp, sz, vp]
+    lib.match_batch_noalloc.argtypes = [vp, ctypes.POINTER(cfog_job), i32, i32, i32, vp]
+    lib.cfog_noalloc_scratch_bytes.restype = sz
     lib.cfog_max_window.restype = i32
     lib.cfog_fft_size.argtypes = [i32, i32]
     lib.cfog_fft_size.restype = i32
@@ -392,6 +394,23 @@ def match_batch(jobs: List[Job], m: int = 9, flags: int = PATH_PLAIN_FFT, stream
             continue
         break
     _check(rc, "match_batch")
+    return [j.out for j in jobs]
+
+
+def match_batch_noalloc(jobs: List[Job], m: int = 9, flags: int = PATH_PLAIN_FFT, stream=None) -> List[torch.Tensor]:
+    """match_batch through the entry point that allocates nothing (its
+    workspace is the library's static device array; see match_batch_noalloc
+    in include/cfog.h).  The jobs' result tensors must already exist: this
+    wrapper allocates nothing either."""
+    if not jobs:
+        return []
+    for j in jobs:
+        if j.out is None or tuple(j.out.shape) != (int(j.cps.shape[0]), 6) or j.out.dtype != torch.int32:
+            raise ValueError("match_batch_noalloc: every job needs its (n, 6) int32 `out` tensor")
+    ctx = context(jobs[0].cps.device.index)
+    arr = make_jobs_array(jobs)
+    _check(load().match_batch_noalloc(ctx.handle, arr, len(jobs), m, flags, _stream_ptr(stream)),
+           "match_batch_noalloc")
     return [j.out for j in jobs]
 
 

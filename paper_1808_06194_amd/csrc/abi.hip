@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -20,6 +21,27 @@
 namespace {
 
 constexpr int kBucketStreams = 4;
+
+// Device scratch of match_batch_noalloc: one array per GPU, resident from the
+// library's load until the process ends, shared by every call on that GPU.
+// Host code never uses its name as an address: the device address of each
+// GPU's copy comes from hipGetSymbolAddress (scratch_address below).
+constexpr size_t kNoallocScratchBytes = (size_t)CFOG_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+// Device address of `scratch` on the current device (which must be `device`),
+// looked up once per device; nullptr if the lookup failed.
+void* scratch_address(int device) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) return it->second;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) p = nullptr;
+  addr[device] = p;
+  return p;
+}
 
 struct GraphEntry {
   std::vector<unsigned char> key;  // exact call signature (jobs bytes + scalars)
@@ -57,6 +79,7 @@ struct cfog_ctx {
   std::map<long, int> tuned;    // (N, r, m) -> P chosen by the autotuner
   std::string plan_cache_path;  // optional persistent autotuner cache
   std::unordered_map<uint64_t, std::unique_ptr<GraphEntry>> graphs;
+  void* scratch = nullptr;      // this device's static scratch (match_batch_noalloc)
 };
 
 namespace {
@@ -390,6 +413,8 @@ int cfog_ctx_create(int device, cfog_ctx** out) {
   }
   if (hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) return CFOG_EHIP;
   if (cfog::init_kernel_attributes() != 0) return CFOG_EHIP;
+  c->scratch = scratch_address(device);
+  if (!c->scratch) return CFOG_EHIP;
   if (const char* p = getenv("CFOG_PLAN_CACHE")) c->plan_cache_path = p;
   load_plan_cache(c.get());
   *out = c.release();
@@ -738,6 +763,25 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
   if (ctx->graphs.size() >= 64) ctx->graphs.clear();
   ctx->graphs[h] = std::move(g);
   return CFOG_OK;
+}
+
+size_t cfog_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
+
+int match_batch_noalloc(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags,
+                        void* stream) {
+  if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return CFOG_EINVAL;
+  const int path = flags & CFOG_PATH_MASK;
+  // the batched path stages its task tables in pinned host memory and the
+  // autotuner creates events: neither runs here
+  if (path != CFOG_PATH_PLAIN_FFT && path != CFOG_PATH_MFMA_BF16) return CFOG_EINVAL;
+  if (flags & ~(CFOG_PATH_MASK | CFOG_OBJ_CORR | CFOG_NO_SPLIT)) return CFOG_EINVAL;
+  if (!ctx->scratch) return CFOG_EHIP;
+  const size_t need = ws_need(ctx, jobs, n_jobs, m, flags, false);  // without channel splits
+  if (need == (size_t)-1) return CFOG_EINVAL;
+  if (need > kNoallocScratchBytes) return CFOG_ENOMEM;
+  // the channel splits are taken where their partials also fit, exactly as
+  // match_batch does with a workspace of this size
+  return match_batch(ctx, jobs, n_jobs, m, flags, ctx->scratch, kNoallocScratchBytes, stream);
 }
 
 }  // extern "C"

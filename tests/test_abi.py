@@ -56,6 +56,8 @@ def test_null_context_is_rejected(lib):
     assert lib.match_batch_workspace_size(None, None, 0, 9, 1) == ctypes.c_size_t(-1).value
     assert lib.cfog_ctx_create(0, None) == cfog.CFOG_EINVAL
     assert lib.cfog_ctx_destroy(None) == 0
+    assert lib.match_batch_noalloc(None, None, 0, 9, 1, None) == cfog.CFOG_EINVAL
+    assert lib.cfog_noalloc_scratch_bytes() == 48 << 20
 
 
 def test_job_struct_layout_matches_header():
