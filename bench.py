@@ -323,7 +323,7 @@ def self_consistency(results, surfaces, pairs):
     return bad
 
 
-def make_workload(name: str, speckle_shape: float = 4.0):
+def make_workload(name: str, speckle_shape: float = 4.0, gen_workers: int = -1):
     from paper_1808_06194_amd import synth
     if name in ("plain_2048", "plain_256"):
         w = dict(synth.PLAIN_2048 if name == "plain_2048" else synth.PLAIN_256)
@@ -337,9 +337,12 @@ def make_workload(name: str, speckle_shape: float = 4.0):
         cps = synth.random_cps(np.random.default_rng(np.random.SeedSequence([3, 1])), 4096, 4096, 128, 32, 10000)
         return [dict(A=A, B=B, shift=s, cps=cps, N=128, r=32)]
     if name == "batch_64":
+        if gen_workers == 0:  # in this process (e.g. under a profiler that has set up the GPU already)
+            return synth.batch_workload(n_pairs=64, speckle_shape=speckle_shape)
         from concurrent.futures import ProcessPoolExecutor
         import multiprocessing as mp
-        with ProcessPoolExecutor(max_workers=cpu_workers(), mp_context=mp.get_context("fork")) as ex:
+        nw = cpu_workers() if gen_workers < 0 else gen_workers
+        with ProcessPoolExecutor(max_workers=nw, mp_context=mp.get_context("fork")) as ex:
             return synth.batch_workload(n_pairs=64, pool_map=ex.map, speckle_shape=speckle_shape)
     raise ValueError(name)
 
@@ -410,6 +413,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (then no cpu_baseline and no parity block)")
     ap.add_argument("--cpu-sample", type=int, default=64, help="control points the oracle leg runs")
+    ap.add_argument("--gen-workers", type=int, default=-1,
+                    help="processes generating batch_64 (-1: the host cores, 0: this process only)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain device-to-device copy of this many MiB "
                          "(a counter calibration point for HBM traffic)")
@@ -435,7 +440,7 @@ def main():
         return
 
     t_gen = time.perf_counter()
-    pairs = make_workload(args.workload, args.speckle_shape)  # before anything touches the GPU
+    pairs = make_workload(args.workload, args.speckle_shape, args.gen_workers)  # before anything touches the GPU
     print(f"[bench] {args.workload}: {len(pairs)} pairs, {sum(len(p['cps']) for p in pairs)} CPs generated in "
           f"{time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     desc = args.descriptor

@@ -2,8 +2,9 @@
 //
 // dft<R, DIR>(v) transforms R complex values held in registers:
 //   X[k] = sum_n v[n] * exp(DIR * 2 pi i n k / R),   DIR = -1 forward, +1 inverse
-// (unnormalised).  R in {2,3,4,5} are written out; composite R = A*B are built
-// by a compile-time Cooley-Tukey split with constant-folded twiddles, so every
+// (unnormalised).  R in {2,3,4,5} are written out; composite R = A*B with
+// coprime factors use the prime-factor mapping (no twiddles), the others a
+// compile-time Cooley-Tukey split with constant-folded twiddles, so every
 // loop below is fully unrolled and every twiddle is an immediate.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -186,16 +187,57 @@ struct DftSplit {
   }
 };
 
-template <int DIR> struct Dft<6, DIR> : DftSplit<2, 3, DIR> {};
+// Coprime R = A * B (Good-Thomas prime-factor algorithm): with the input map
+// n = (B a + A b) mod R and the output map k = (B tA k1 + A tB k2) mod R,
+// tA = B^-1 mod A, tB = A^-1 mod B, the exponent n k reduces mod R to
+// B (B tA) a k1 + A (A tB) b k2, so
+//   X[k(k1, k2)] = sum_b W_B^{b k2} sum_a W_A^{a k1} v[n(a, b)]
+// with no twiddle factors between the two sets of small DFTs (the maps are
+// compile-time register permutations).
+constexpr int inv_mod(int x, int m) {
+  for (int t = 1; t < m; ++t)
+    if ((x * t) % m == 1) return t;
+  return 1;  // m == 1
+}
+
+template <int A, int B, int DIR>
+struct DftPfa {
+  CFOG_HD static void run(float2* v) {
+    constexpr int R = A * B;
+    constexpr int tA = inv_mod(B % A, A), tB = inv_mod(A % B, B);
+    float2 y[B][A];
+    static_for<0, B>([&](auto bI) {
+      constexpr int b = decltype(bI)::value;
+      float2 t[A];
+      static_for<0, A>([&](auto aI) { constexpr int a = decltype(aI)::value; t[a] = v[(B * a + A * b) % R]; });
+      Dft<A, DIR>::run(t);
+      static_for<0, A>([&](auto kI) { constexpr int k1 = decltype(kI)::value; y[b][k1] = t[k1]; });
+    });
+    float2 out[R];
+    static_for<0, A>([&](auto kI) {
+      constexpr int k1 = decltype(kI)::value;
+      float2 t[B];
+      static_for<0, B>([&](auto bI) { constexpr int b = decltype(bI)::value; t[b] = y[b][k1]; });
+      Dft<B, DIR>::run(t);
+      static_for<0, B>([&](auto k2I) {
+        constexpr int k2 = decltype(k2I)::value;
+        out[(B * tA * k1 + A * tB * k2) % R] = t[k2];
+      });
+    });
+    static_for<0, R>([&](auto iI) { constexpr int i = decltype(iI)::value; v[i] = out[i]; });
+  }
+};
+
+template <int DIR> struct Dft<6, DIR> : DftPfa<2, 3, DIR> {};
 template <int DIR> struct Dft<8, DIR> : DftSplit<2, 4, DIR> {};
 template <int DIR> struct Dft<9, DIR> : DftSplit<3, 3, DIR> {};
-template <int DIR> struct Dft<10, DIR> : DftSplit<2, 5, DIR> {};
-template <int DIR> struct Dft<12, DIR> : DftSplit<4, 3, DIR> {};
-template <int DIR> struct Dft<15, DIR> : DftSplit<3, 5, DIR> {};
+template <int DIR> struct Dft<10, DIR> : DftPfa<2, 5, DIR> {};
+template <int DIR> struct Dft<12, DIR> : DftPfa<4, 3, DIR> {};
+template <int DIR> struct Dft<15, DIR> : DftPfa<3, 5, DIR> {};
 template <int DIR> struct Dft<16, DIR> : DftSplit<4, 4, DIR> {};
-template <int DIR> struct Dft<18, DIR> : DftSplit<2, 9, DIR> {};
-template <int DIR> struct Dft<20, DIR> : DftSplit<4, 5, DIR> {};
-template <int DIR> struct Dft<24, DIR> : DftSplit<8, 3, DIR> {};
+template <int DIR> struct Dft<18, DIR> : DftPfa<2, 9, DIR> {};
+template <int DIR> struct Dft<20, DIR> : DftPfa<4, 5, DIR> {};
+template <int DIR> struct Dft<24, DIR> : DftPfa<8, 3, DIR> {};
 
 template <int R, int DIR>
 CFOG_HD void dft(float2* v) { Dft<R, DIR>::run(v); }

@@ -551,19 +551,20 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   }
   __syncthreads();
 
-  // ---- inverse along x: C2R, two output rows per complex FFT, kept u_x < K;
-  // the correlation C(u_y, u_x) goes to LDS behind the row-FFT scratch.
+  // ---- inverse along x: C2R, two output rows per complex FFT, kept u_x < K.
+  // A pair's stage-1 outputs overwrite its own two input rows (2 PH >= P
+  // slots, read into registers by the same wave first); the correlation
+  // C(u_y, u_x) goes to LDS behind all the pairs' rows.
   const int npair = (K + 1) >> 1;
-  float2* SC = X + K * PH;
-  float* Cs = reinterpret_cast<float*>(SC + npair * P);
+  float* Cs = reinterpret_cast<float*>(X + 2 * npair * PH);
   const float inv = 1.0f / ((float)P * (float)P);
   for (int p = L.g; p < npair; p += C::NG) {
-    float2* sc = SC + opaque(p) * P;
+    float2* sc = X + 2 * opaque(p) * PH;
+    float2 v[R1];
     if (L.li < R2) {
       const int j = L.li;
       const float2* v1r = X + (2 * p) * PH;
       const bool has2 = 2 * p + 1 < K;
-      float2 v[R1];
 #pragma unroll
       for (int a = 0; a < R1; ++a) {
         const int kx = j + R2 * a;
@@ -573,9 +574,12 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
         const float2 v2 = has2 ? v1r[PH + kk] : make_float2(0.f, 0.f);
         v[a] = lo ? make_float2(v1.x - v2.y, v1.y + v2.x) : make_float2(v1.x + v2.y, v2.x - v1.y);
       }
+    }
+    wave_sync();  // every read of the pair's rows precedes the writes into them
+    if (L.li < R2) {
       dft<R1, +1>(v);
 #pragma unroll
-      for (int k = 0; k < R1; ++k) sc[j * R1 + k] = v[k];
+      for (int k = 0; k < R1; ++k) sc[L.li * R1 + k] = v[k];
     }
     wave_sync();
     if (L.li < R1) {
@@ -697,8 +701,8 @@ bool plan_fits(const FftPlan* p, int N, int r) {
   const int Ws = N + 2 * r, K = 2 * r + 1;
   if (p->P < Ws || N > p->t_rows) return false;
   const int PH = p->P / 2 + 1;
-  // inverse row scratch and the K x K correlation behind it must fit in LDS
-  return 2L * ((long)(K + 1) / 2 * p->P) + (long)K * K <= 2L * (long)(p->P - K) * PH;
+  // the K x K correlation must fit behind the rows of the inverse's row pairs
+  return (long)K * K <= 2L * (long)(p->P - 2 * ((K + 1) / 2)) * PH;
 }
 
 const FftPlan* choose_fft_plan(int N, int r) {

@@ -164,10 +164,9 @@ def _batch_pair(args):
     return make_pair(spec, (seed, j))
 
 
-def batch_workload(n_pairs: int = 64, sides=(512, 1024, 2048, 4096), seed: int = 2,
-                   max_cps: int = 600, min_cps: int = 50, pool_map=map, speckle_shape: float = 4.0):
-    """Heterogeneous batch: list of dicts (A, B, shift, cps, N, r) per pair.
-    `pool_map` may be a process pool's map (each pair has its own seed)."""
+def batch_draws(n_pairs: int = 64, sides=(512, 1024, 2048, 4096), seed: int = 2, max_cps: int = 600,
+                min_cps: int = 50, speckle_shape: float = 4.0):
+    """Per-pair draws of the heterogeneous batch: (side, N, r, n_cps, spec)."""
     meta = _rng(seed, 999)
     draws = []
     for j in range(n_pairs):
@@ -177,6 +176,22 @@ def batch_workload(n_pairs: int = 64, sides=(512, 1024, 2048, 4096), seed: int =
         n = int(meta.integers(min_cps, max_cps + 1))
         spec = dataclasses.replace(area_scaled_spec(side, min(8, r)), speckle_shape=speckle_shape)
         draws.append((side, N, r, n, spec))
+    return draws
+
+
+def batch_pair(draws, j: int, seed: int = 2):
+    """Pair j of a batch drawn by batch_draws: dict (A, B, shift, cps, N, r)."""
+    side, N, r, n, spec = draws[j]
+    A, B, s = make_pair(spec, (seed, j))
+    cps = random_cps(_rng(seed, j, 1), side, side, N, r, n)
+    return dict(A=A, B=B, shift=s, cps=cps, N=N, r=r)
+
+
+def batch_workload(n_pairs: int = 64, sides=(512, 1024, 2048, 4096), seed: int = 2,
+                   max_cps: int = 600, min_cps: int = 50, pool_map=map, speckle_shape: float = 4.0):
+    """Heterogeneous batch: list of dicts (A, B, shift, cps, N, r) per pair.
+    `pool_map` may be a process pool's map (each pair has its own seed)."""
+    draws = batch_draws(n_pairs, sides, seed, max_cps, min_cps, speckle_shape)
     imgs = list(pool_map(_batch_pair, [(d[4], seed, j) for j, d in enumerate(draws)]))
     out = []
     for j, ((side, N, r, n, _), (A, B, s)) in enumerate(zip(draws, imgs)):
