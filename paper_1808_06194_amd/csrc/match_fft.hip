@@ -234,7 +234,9 @@ __device__ __forceinline__ void xpass_stage2(const Lane<C>& L, float2* base, int
     float2 v[R2];
     stage2_inputs<C, false>(v, tw, k1, [&](int b) { return base[s1_pos<C>(b, k1)]; });
     dft<R2, -1>(v);
-    // separate the packed rows: A(k) = (Z(k) + conj Z(-k)) / 2, B(k) = (Z(k) - conj Z(-k)) / 2i.
+    // separate the packed rows: 2 A(k) = Z(k) + conj Z(-k), 2 B(k) = (Z(k) - conj Z(-k)) / i
+    // (the factor 2 of both spectra, 4 in their product, is taken out by the
+    // inverse's normalisation: exact, being a power of two).
     // Z(-k) for k = k1 + R1 k2 is Z((R1-k1) + R1 (R2-1-k2)), i.e. register R2-1-k2 of
     // lane R1-k1 of the group (k1 > 0), or this lane's register (R2-k2) mod R2 (k1 = 0).
     const int lane = threadIdx.x & 63;
@@ -247,8 +249,8 @@ __device__ __forceinline__ void xpass_stage2(const Lane<C>& L, float2* base, int
       const int k = k1 + R1 * k2;
       if (L.li < R1 && k <= P / 2) {
         const float2 z = v[k2];
-        base[k] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
-        base[PH + k] = odd_pad ? make_float2(0.f, 0.f) : make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x));
+        base[k] = make_float2(z.x + zm.x, z.y - zm.y);
+        base[PH + k] = odd_pad ? make_float2(0.f, 0.f) : make_float2(z.y + zm.y, zm.x - z.x);
       }
     });
     wave_sync();
@@ -557,7 +559,8 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   // C(u_y, u_x) goes to LDS behind all the pairs' rows.
   const int npair = (K + 1) >> 1;
   float* Cs = reinterpret_cast<float*>(X + 2 * npair * PH);
-  const float inv = 1.0f / ((float)P * (float)P);
+  // 1/P^2 of the inverse 2-D DFT and 1/4 for the doubled row spectra of T and S
+  const float inv = 0.25f / ((float)P * (float)P);
   for (int p = L.g; p < npair; p += C::NG) {
     float2* sc = X + 2 * opaque(p) * PH;
     float2 v[R1];

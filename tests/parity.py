@@ -116,3 +116,17 @@ def oracle_point(A, B, cp, N, r, m=9, sigma=0.8):
     S = O.ssd_surface_direct(D1, D2, cp_local, N, r)
     E1, E2 = O.energies(D1, D2, cp_local, N, r)
     return S, E1, E2
+
+
+def oracle_point_fft(A, B, cp, N, r, m=9, sigma=0.8):
+    """As oracle_point, with the surface from the oracle's FP64 FFT form
+    (Eqs. 5, 8-9; pinned to the direct form to 1e-10 by the oracle pins),
+    which makes full-size checks of every point affordable on the host."""
+    x, y, bx, by = (int(v) for v in cp)
+    h = N // 2
+    T = cfog_window(A, y - h, x - h, N, N, m, sigma)
+    Sw = cfog_window(B, by - h - r, bx - h - r, N + 2 * r, N + 2 * r, m, sigma)
+    loc = (h, h, h + r, h + r)
+    S = O.ssd_surface_fft(T, Sw, loc, N, r)
+    E1, E2 = O.energies(T, Sw, loc, N, r)
+    return S, E1, E2

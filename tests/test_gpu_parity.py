@@ -1,6 +1,8 @@
 """GPU parity: libcfog (through its C-ABI) against the FP64 oracle.
 
 Every case prints its name, shapes and seed before touching the GPU."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -371,53 +373,141 @@ def test_channel_split_matches_unsplit(cf, N, r, H, n, seed):
     _say("stats", stats)
 
 
-def test_match_plain_2048_full_size_sampled(cf):
-    """The 2048^2 workload (400 CPs, template 100, radius 20; P = 144) in the
-    launch configuration the benchmark times.  Every point is checked for
-    self-consistency (status, argmin of its own surface); a seeded sample of
-    points is checked element-wise against the FP64 oracle."""
-    A, B, s, cps, N, r = synth.plain_workload(synth.PLAIN_2048)
-    _say("match plain_2048", A.shape, len(cps), N, r)
-    res, surf = _run_match(cf, A, B, cps, N, r)
+def _check_all(res, surf, cps, A, B, N, r, ks, tol=parity.SURF_TOL, fft=True):
+    """Points ks against the oracle (FFT form, or the direct form)."""
+    stats = {}
+    for k in ks:
+        S, E1, E2 = (parity.oracle_point_fft if fft else parity.oracle_point)(A, B, cps[k], N, r)
+        parity.check_point(int(k), res, S, E1, E2, r, surf[k], stats, tol=tol)
+    return stats
+
+
+def _self_consistent(res, surf, n, r):
     K = 2 * r + 1
     assert np.all(res["status"] == 0)
-    flat = surf.reshape(len(cps), -1)
+    flat = surf.reshape(n, -1)
     i = np.argmin(flat, axis=1)
     assert np.array_equal(i % K - r, res["dx"]) and np.array_equal(i // K - r, res["dy"])
-    assert np.array_equal(flat[np.arange(len(cps)), i], res["best"])
-    rng = np.random.default_rng(2048)
-    stats = {}
-    for k in rng.choice(len(cps), 6, replace=False):
-        S, E1, E2 = parity.oracle_point(A, B, cps[k], N, r)
-        parity.check_point(int(k), res, S, E1, E2, r, surf[k], stats)
-    print("stats", stats, flush=True)
+    assert np.array_equal(flat[np.arange(n), i], res["best"])
+
+
+def test_match_plain_2048_full_size_every_point(cf):
+    """The 2048^2 workload (400 CPs, template 100, radius 20; P = 144) in the
+    launch configuration the benchmark times (plain path, channel split of
+    the last round): every point element by element against the oracle's FFT
+    form, eight of them against its direct form; excused near-ties at most 2%."""
+    A, B, s, cps, N, r = synth.plain_workload(synth.PLAIN_2048)
+    _say("match plain_2048 every point", A.shape, len(cps), N, r)
+    res, surf = _run_match(cf, A, B, cps, N, r)
+    _self_consistent(res, surf, len(cps), r)
+    stats = _check_all(res, surf, cps, A, B, N, r, range(len(cps)))
+    direct = _check_all(res, surf, cps, A, B, N, r, np.random.default_rng(2048).choice(len(cps), 8, replace=False),
+                        fft=False)
+    _say("stats", stats, "direct sample", direct)
+    assert stats.get("exact", 0) + stats.get("excused", 0) == len(cps)
+    assert stats.get("excused", 0) <= 0.02 * len(cps)
+
+
+def test_match_plain_2048_mild_speckle_recovers_the_shift(cf):
+    """The 2048^2 workload with milder speckle (Gamma shape 64): most points
+    recover the seeded shift within 1.5 px (the paper's criterion), and a
+    sample of 64 points matches the oracle.  With the workload's shape-4
+    speckle only about 9% do, so this variant makes the recovery rate mean
+    something."""
+    w = dict(synth.PLAIN_2048)
+    w["spec"] = dataclasses.replace(w["spec"], speckle_shape=64.0)
+    A, B, s, cps, N, r = synth.plain_workload(w)
+    _say("match plain_2048, speckle shape 64", A.shape, len(cps), N, r, "shift", s)
+    res, surf = _run_match(cf, A, B, cps, N, r)
+    _self_consistent(res, surf, len(cps), r)
+    rec = float(np.mean(np.hypot(res["dx"] - s[0], res["dy"] - s[1]) <= 1.5))
+    stats = _check_all(res, surf, cps, A, B, N, r, np.random.default_rng(64).choice(len(cps), 64, replace=False))
+    _say("recovered", rec, "stats", stats)
+    assert rec >= 0.6
+    assert stats.get("excused", 0) <= 2
+
+
+_P4096 = {}
+
+
+def _precision_4096():
+    if not _P4096:
+        spec = synth.PairSpec(4096, 4096, 3200, (3.0, 40.0), 1200, 20)
+        A, B, s = synth.make_pair(spec, (3, 0))
+        cps = synth.random_cps(np.random.default_rng(np.random.SeedSequence([3, 1])), 4096, 4096, 128, 32, 10000)
+        ks = np.sort(np.random.default_rng(4096).choice(len(cps), 64, replace=False))
+        ora = {int(k): parity.oracle_point_fft(A, B, cps[k], 128, 32) for k in ks}
+        _P4096.update(A=A, B=B, cps=cps, ks=ks, ora=ora)
+    return _P4096
 
 
 @pytest.mark.parametrize("path", ["fft", "mfma"])
 def test_match_precision_4096_full_size_sampled(cf, path):
     """The 4096^2 workload (10,000 random CPs, template 128, radius 32) in the
     launch configuration the benchmark times: the FP32 FFT path (P = 192)
-    and the BF16 MFMA path.  Every point is checked for self-consistency; a
-    seeded sample against the FP64 oracle, at each path's surface bound."""
-    spec = synth.PairSpec(4096, 4096, 3200, (3.0, 40.0), 1200, 20)
-    A, B, s = synth.make_pair(spec, (3, 0))
-    cps = synth.random_cps(np.random.default_rng(np.random.SeedSequence([3, 1])), 4096, 4096, 128, 32, 10000)
-    N, r, K = 128, 32, 65
+    and the BF16 MFMA path.  Every point is checked for self-consistency; 64
+    seeded points against the oracle at each path's surface bound, with at
+    most 2 (FFT) or 4 (MFMA) excused near-ties."""
+    D = _precision_4096()
+    A, B, cps, N, r = D["A"], D["B"], D["cps"], 128, 32
     _say("match precision_4096", path, A.shape, len(cps), N, r)
     flags = cf.PATH_PLAIN_FFT if path == "fft" else cf.PATH_MFMA_BF16
     res, surf = _run_match(cf, A, B, cps, N, r, flags=flags)
-    assert np.all(res["status"] == 0)
-    flat = surf.reshape(len(cps), -1)
-    i = np.argmin(flat, axis=1)
-    assert np.array_equal(i % K - r, res["dx"]) and np.array_equal(i // K - r, res["dy"])
-    assert np.array_equal(flat[np.arange(len(cps)), i], res["best"])
-    rng = np.random.default_rng(4096)
+    _self_consistent(res, surf, len(cps), r)
     stats = {}
     tol = parity.SURF_TOL if path == "fft" else parity.bf16_tol(N, r)
-    for k in rng.choice(len(cps), 3, replace=False):
-        S, E1, E2 = parity.oracle_point(A, B, cps[k], N, r)
+    for k in D["ks"]:
+        S, E1, E2 = D["ora"][int(k)]
         parity.check_point(int(k), res, S, E1, E2, r, surf[k], stats, tol=tol)
-    print("stats", stats, flush=True)
+    _say("stats", stats)
+    assert stats.get("excused", 0) <= (2 if path == "fft" else 4)
+
+
+def test_match_batch_64_pairs_of_every_fft_size(cf):
+    """The 64-pair batch as the benchmark runs it (batched path, autotuned FFT
+    sizes, hipGraph capture): from the batch's own seeded pairs, the smallest
+    pair of every default FFT size (13 pairs, all their points in one call).
+    Every point is checked for self-consistency, six seeded points per pair
+    against the oracle's FFT form and one against its direct form; excused
+    near-ties at most 2% of the checked points."""
+    draws = synth.batch_draws()
+    by_P = {}
+    for j, (side, N, r, n, spec) in enumerate(draws):
+        P = cf.fft_size(N, r)
+        if P not in by_P or side < draws[by_P[P]][0]:
+            by_P[P] = j
+    sel = [by_P[P] for P in sorted(by_P)]
+    _say("match batch_64 pairs", sel, "default FFT sizes", sorted(by_P))
+    pairs = [synth.batch_pair(draws, j) for j in sel]
+    jobs = []
+    for p in pairs:
+        vA, sA = cf.cfog_extract(_dev(p["A"]))
+        vB, sB = cf.cfog_extract(_dev(p["B"]))
+        K = 2 * p["r"] + 1
+        jobs.append(cf.Job(vA, sA, vB, sB, _dev(p["cps"]), p["N"], p["r"],
+                           surfaces=torch.empty((len(p["cps"]), K, K), device="cuda")))
+    cf.match_batch(jobs, flags=cf.PATH_BATCHED_FFT | cf.AUTOTUNE | cf.USE_GRAPH)
+    cf.match_batch(jobs, flags=cf.PATH_BATCHED_FFT | cf.AUTOTUNE | cf.USE_GRAPH)  # the graph replay
+    torch.cuda.synchronize()
+    stats, checked = {}, 0
+    rng = np.random.default_rng(64)
+    tuned = set()
+    for p, j in zip(pairs, jobs):
+        res = {k: v.cpu().numpy() for k, v in cf.results(j.out).items()}
+        surf = j.surfaces.cpu().numpy()
+        _self_consistent(res, surf, len(p["cps"]), p["r"])
+        ks = rng.choice(len(p["cps"]), 7, replace=False)
+        st = _check_all(res, surf, p["cps"], p["A"], p["B"], p["N"], p["r"], ks[:6])
+        st2 = _check_all(res, surf, p["cps"], p["A"], p["B"], p["N"], p["r"], ks[6:], fft=False)
+        for d in (st, st2):
+            for key in ("exact", "excused"):
+                stats[key] = stats.get(key, 0) + d.get(key, 0)
+            stats["max_norm_err"] = max(stats.get("max_norm_err", 0.0), d.get("max_norm_err", 0.0))
+        checked += 7
+        tuned.add(cf.plan_for(p["N"], p["r"]))
+    _say("stats", stats, "tuned FFT sizes", sorted(tuned))
+    assert stats.get("exact", 0) + stats.get("excused", 0) == checked
+    assert stats.get("excused", 0) <= 0.02 * checked
 
 
 def test_extract_large_image_sampled(cf):
