@@ -5,30 +5,37 @@
 // contiguous H*W plane per orientation); SAT [(H+1)][(W+1)] fp64 with a zero
 // first row and column, SAT(y+1, x+1) = sum_{y'<=y, x'<=x} Q(y', x').
 //
+// The volume and table writes are nontemporal stores: they stream past the
+// caches, which nothing reads again before the matcher (measured on the
+// extraction's write pattern alone: 10-13% faster than cached stores).
+//
 // Kernel 1 (cfog_extract_kernel<R, M>) produces a 64 x 32 output tile for all
 // m channels:
 //   A. stage the image tile plus an (R+1)-pixel halo in LDS (clamp-to-edge);
 //   B. gx, gy by [-1,0,1] (the filters given after Eq. 2) at every pixel of
 //      the tile + R halo, at the clamped pixel (which is what clamp-to-edge
-//      Gaussian borders read), into two LDS planes;
-//   C. per channel k: the horizontal Gaussian pass of
-//      g_k = |cos(theta_k) gx + sin(theta_k) gy| (Eq. 2, theta_k = k pi / m),
-//      the channel values formed on the fly from 16-byte reads of both
-//      planes (four outputs per thread, consecutive lanes on consecutive
-//      columns), then the vertical pass (radius R, 4 outputs per thread from
-//      a sliding window down a column); the circular [1,2,1]/4 orientation
-//      smoothing is applied to the spatially smoothed channels with rolling
-//      registers, and each finished channel goes straight to HBM; Q
-//      accumulated in FP64 from the FP32 outputs;
+//      Gaussian borders read), kept in registers by the thread that owns the
+//      pixel for the whole channel loop;
+//   C. per channel k: each thread forms g_k = |cos(theta_k) gx + sin(theta_k) gy|
+//      (Eq. 2, theta_k = k pi / m) once for its pixels into the LDS channel
+//      plane (channel k + 1's while the vertical pass of channel k runs);
+//      the horizontal Gaussian pass reads it by 16-byte pieces (four outputs
+//      per thread, consecutive lanes on consecutive columns), then the
+//      vertical pass (radius R, 4 outputs per thread from a sliding window
+//      down a column); the circular [1,2,1]/4 orientation smoothing is
+//      applied to the spatially smoothed channels with rolling registers,
+//      and each finished channel goes straight to HBM; Q accumulated in FP64
+//      from the FP32 outputs;
 //   D. the tile-local 2-D inclusive prefix L of Q (row scan across the 64 lanes
 //      of a wave, column scan down the tile), written into the SAT buffer,
 //      plus the tile's right column and bottom row into a small workspace.
-// LDS holds the two gradient planes and one row-pass buffer (the image tile
-// shares its storage; the wave carries of D reuse the dead gradient planes),
-// about 33 KB at R = 3; four 512-thread workgroups (32 waves) share a CU; two
+// LDS holds the channel plane and one row-pass buffer (the image tile shares
+// its storage; the wave carries of D reuse the dead channel plane), about
+// 22 KB at R = 3; four 512-thread workgroups (32 waves) share a CU; two
 // barriers per channel.  (Measured on 2048^2 images: 64 x 16 tiles of 256
 // threads, eight per CU, 4% slower; with two row-pass buffers, one barrier per
-// channel and six per CU, 7-8% slower.)
+// channel and six per CU, 7-8% slower.  Forming g_k from two gradient planes
+// inside the horizontal pass computed each value three times.)
 
 // Global SAT from tile-local prefixes: for a tile (i, j) with origin (y0, x0),
 //   SAT(y, x) = L(y, x) + sum_{j'<j} Rc_{i,j'}(y) + sum_{i'<i} Bt_{i',j}(x)
@@ -118,7 +125,7 @@ __device__ __forceinline__ void tile_sat_prefix(double (&q)[EX_RUN], double* qx,
   for (int o = 0; o < EX_RUN; ++o) {
     q[o] += up;
     const int gyy = y0 + orow + o;
-    if (gyy < H && gxx < W) sat[(size_t)(gyy + 1) * W1 + gxx + 1] = q[o];
+    if (gyy < H && gxx < W) __builtin_nontemporal_store(q[o], sat + (size_t)(gyy + 1) * W1 + gxx + 1);
     if (oc == 63 && gyy < H) rc[(size_t)gyy * ntx + blockIdx.x] = q[o];
   }
   if (wv == EX_NT / 64 - 1 && gxx < W) bt[(size_t)blockIdx.y * W + gxx] = q[EX_RUN - 1];
@@ -134,11 +141,22 @@ struct ExTile {
   static constexpr int GWP = ((GW + 3) / 4 * 4) > (EX_TX - 4 + 4 * NQ) ? ((GW + 3) / 4 * 4) : (EX_TX - 4 + 4 * NQ);
   static constexpr int NQUAD = GH * EX_TX / 4;    // horizontal outputs four at a time
   static constexpr size_t IMG = ((size_t)IH * IW + 3) / 4 * 4;   // floats
-  static constexpr size_t GP = (size_t)GH * GWP;                 // floats per gradient plane
+  static constexpr size_t GP = (size_t)GH * GWP;                 // floats of the channel plane
   static constexpr size_t HB = (size_t)GH * EX_TX;                // floats: one channel's row pass
-  // the image tile is dead once the gradients exist: it shares HB's storage
+  // the image tile is dead once the gradients are in registers: it shares
+  // HB's storage
   static constexpr size_t HBI = HB > IMG ? HB : IMG;
-  static constexpr size_t BYTES = 4 * 2 * GP + 4 * HBI;
+  // the spatially smoothed channels 0 and 1 of a thread's 4 outputs, needed
+  // again by the circular orientation smoothing after the last channel
+  static constexpr size_t KEEP = 2 * EX_RUN * EX_NT;  // floats, [value][thread]
+  static constexpr size_t BYTES = 4 * GP + 4 * HBI + 4 * KEEP;
+  // halo-tile pixels of a thread: lane l of wave w takes column l of the rows
+  // w, w + 8, ... (NROW of them), and the 2R columns right of the first 64
+  // are spread over the threads (NEXTRA each)
+  static constexpr int NROW = (GH + EX_NT / 64 - 1) / (EX_NT / 64);
+  static constexpr int NX = 2 * R;
+  static constexpr int NEXTRA = (NX * GH + EX_NT - 1) / EX_NT;
+  static constexpr int NPX = NROW + NEXTRA;
 };
 
 // M > 0: the channel count fixed at compile time (the channel loop unrolls
@@ -152,12 +170,12 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   const int m = M > 0 ? M : a.m;
-  float* gxp = lds;                                  // GH * GWP: gx (scheme 1: |g|)
-  float* gyp = gxp + T::GP;                          // GH * GWP: gy (scheme 1: bin position)
-  float* Hb = gyp + T::GP;                           // GH * EX_TX row-pass outputs
+  float* gk = lds;                                   // GH * GWP: one oriented-gradient channel
+  float* Hb = gk + T::GP;                            // GH * EX_TX row-pass outputs
   float* img = Hb;                                   // IH * IW, read only by the gradient pass
-  double* qx = reinterpret_cast<double*>(gxp);       // 64 wave carries per wave, after the last channel
-  static_assert(2 * T::GP * sizeof(float) >= (EX_NT / 64) * 64 * sizeof(double), "wave carries");
+  float* keep = Hb + T::HBI;                         // KEEP: Gs_0, Gs_1 of this thread's outputs
+  double* qx = reinterpret_cast<double*>(gk);        // 64 wave carries per wave, after the last channel
+  static_assert(T::GP * sizeof(float) >= (EX_NT / 64) * 64 * sizeof(double), "wave carries");
   const ExImage I = a.im[blockIdx.z];
   if ((int)blockIdx.x >= I.ntx || (int)blockIdx.y >= I.nty) return;  // beyond this image's tiles
   const int tid = threadIdx.x;
@@ -193,37 +211,42 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   // directly; tiles at the border take them at clamped positions, which is
   // what clamp-to-edge gradient and Gaussian borders read.
   const bool interior = x0 - R - 1 >= 0 && y0 - R - 1 >= 0 && x0 + EX_TX + R <= W - 1 && y0 + EX_TY + R <= H - 1;
-  float2 gb[(GH * GW + EX_NT - 1) / EX_NT];  // held until the image tile is dead
-  if (interior) {
-#pragma unroll
-    for (int it = 0; it < (GH * GW + EX_NT - 1) / EX_NT; ++it) {
-      const int i = tid + it * EX_NT;
-      if (i < GH * GW) {
-        const int r = i / GW, c = i - r * GW;
-        const float* p = img + (r + 1) * IW + c + 1;
-        gb[it] = make_float2(p[1] - p[-1], p[IW] - p[-IW]);
-      }
+  const int oy = y0 - R - 1, ox = x0 - R - 1;  // global coords of img[0][0]
+  auto grad = [&](int r, int c) {              // (gx, gy) at halo-tile pixel (r, c)
+    if (interior) {
+      const float* p = img + (r + 1) * IW + c + 1;
+      return make_float2(p[1] - p[-1], p[IW] - p[-IW]);
     }
-  } else {
-    const int oy = y0 - R - 1, ox = x0 - R - 1;  // global coords of img[0][0]
+    const int Yc = clampi(y0 - R + r, 0, H - 1), Xc = clampi(x0 - R + c, 0, W - 1);
+    const int yl = Yc - oy, xl = Xc - ox;
+    const int xp = clampi(Xc + 1, 0, W - 1) - ox, xm = clampi(Xc - 1, 0, W - 1) - ox;
+    const int yp = clampi(Yc + 1, 0, H - 1) - oy, ym = clampi(Yc - 1, 0, H - 1) - oy;
+    return make_float2(img[yl * IW + xp] - img[yl * IW + xm], img[yp * IW + xl] - img[ym * IW + xl]);
+  };
+  // this thread's pixels (the mapping of ExTile) and their offsets in the
+  // channel plane: row slots at rbase + it 8 GWP (rows beyond the tile are
+  // skipped, uniformly per wave), extra slots at xoff[e] (-1: none)
+  const int wv = tid >> 6, lane = tid & 63;
+  const int rbase = wv * GWP + lane;
+  int xoff[T::NEXTRA > 0 ? T::NEXTRA : 1];
+  float2 gb[T::NPX];  // this thread's pixels, held through the channel loop
 #pragma unroll
-    for (int it = 0; it < (GH * GW + EX_NT - 1) / EX_NT; ++it) {
-      const int i = tid + it * EX_NT;
-      if (i < GH * GW) {
-        const int r = i / GW, c = i - r * GW;
-        const int Yc = clampi(y0 - R + r, 0, H - 1), Xc = clampi(x0 - R + c, 0, W - 1);
-        const int yl = Yc - oy, xl = Xc - ox;
-        const int xp = clampi(Xc + 1, 0, W - 1) - ox, xm = clampi(Xc - 1, 0, W - 1) - ox;
-        const int yp = clampi(Yc + 1, 0, H - 1) - oy, ym = clampi(Yc - 1, 0, H - 1) - oy;
-        gb[it] = make_float2(img[yl * IW + xp] - img[yl * IW + xm], img[yp * IW + xl] - img[ym * IW + xl]);
-      }
-    }
+  for (int it = 0; it < T::NROW; ++it) {
+    const int r = wv + it * (EX_NT / 64);
+    gb[it] = r < GH ? grad(r, lane) : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int e = 0; e < T::NEXTRA; ++e) {
+    const int t = tid + e * EX_NT;
+    const int r = t / T::NX, c = EX_TX + (t - r * T::NX);
+    xoff[e] = t < T::NX * GH ? r * GWP + c : -1;
+    gb[T::NROW + e] = t < T::NX * GH ? grad(r, c) : make_float2(0.f, 0.f);
   }
   // scheme 1 keeps (|g|, orientation bin position in [0, m)) instead of (gx, gy)
   if constexpr (S1) {
     const float bscale = (float)m / 3.14159265358979f;
 #pragma unroll
-    for (int it = 0; it < (GH * GW + EX_NT - 1) / EX_NT; ++it) {
+    for (int it = 0; it < T::NPX; ++it) {
       const float2 g = gb[it];
       float phi = atan2f(g.y, g.x);
       if (phi < 0.f) phi += 3.14159265358979f;
@@ -232,17 +255,30 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
       gb[it] = make_float2(sqrtf(g.x * g.x + g.y * g.y), b);
     }
   }
-#pragma unroll
-  for (int it = 0; it < (GH * GW + EX_NT - 1) / EX_NT; ++it) {
-    const int i = tid + it * EX_NT;
-    if (i < GH * GW) {
-      const int r = i / GW, c = i - r * GW;
-      gxp[r * GWP + c] = gb[it].x;
-      gyp[r * GWP + c] = gb[it].y;
-    }
-  }
-  // the padding columns of the gradient planes feed only channel values that
+  // the padding columns of the channel plane feed only channel values that
   // no output reads
+  const float mf = (float)m;
+  // oriented gradient g_k of one pixel from its two gradient values:
+  // |cos(theta_k) gx + sin(theta_k) gy| (Eq. 2), or for scheme 1
+  // |g| max(0, 1 - circular distance of the bin position to k)
+  auto form_channel = [&](int k) {
+    const float ck = a.cs[k], sk = a.sn[k], kf = (float)k;
+    auto g_of = [&](float2 uv) {
+      if constexpr (S1) {
+        const float d = fabsf(uv.y - kf);
+        return uv.x * fmaxf(0.f, 1.f - fminf(d, mf - d));
+      } else {
+        return fabsf(fmaf(ck, uv.x, sk * uv.y));
+      }
+    };
+#pragma unroll
+    for (int it = 0; it < T::NROW; ++it)
+      if (wv + it * (EX_NT / 64) < GH) gk[rbase + it * (EX_NT / 64) * GWP] = g_of(gb[it]);
+#pragma unroll
+    for (int e = 0; e < T::NEXTRA; ++e)
+      if (xoff[e] >= 0) gk[xoff[e]] = g_of(gb[T::NROW + e]);
+  };
+  form_channel(0);  // the channel plane does not alias the image tile
   __syncthreads();
 
   // C. per channel: the horizontal Gaussian of the oriented gradient (the
@@ -253,9 +289,9 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   const int oc = tid & 63, orow = (tid >> 6) * EX_RUN;
   const int gxx = x0 + oc;
   double q[EX_RUN];
-  float g0[EX_RUN], g1[EX_RUN], pm2[EX_RUN], pm1[EX_RUN];
+  float pm2[EX_RUN], pm1[EX_RUN];
 #pragma unroll
-  for (int p = 0; p < EX_RUN; ++p) { q[p] = 0.0; g0[p] = g1[p] = pm2[p] = pm1[p] = 0.f; }
+  for (int p = 0; p < EX_RUN; ++p) { q[p] = 0.0; pm2[p] = pm1[p] = 0.f; }
   const size_t plane = (size_t)H * W;
   float* const vout = I.vol + (size_t)min(y0 + orow, H - 1) * W + min(gxx, W - 1);
   bool vok[EX_RUN];
@@ -266,43 +302,29 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
 #pragma unroll
     for (int o = 0; o < EX_RUN; ++o) {
       if (vok[o]) {
-        p[(size_t)o * W] = d[o];
+        __builtin_nontemporal_store(d[o], p + (size_t)o * W);
         q[o] = fma((double)d[o], (double)d[o], q[o]);
       }
     }
   };
   auto channel = [&](int k) {
-    const float ck = a.cs[k], sk = a.sn[k];
-    const float kf = (float)k, mf = (float)m;
-    // oriented gradient g_k of one pixel from its two gradient-plane values:
-    // |cos(theta_k) gx + sin(theta_k) gy| (Eq. 2), or for scheme 1
-    // |g| max(0, 1 - circular distance of the bin position to k)
-    auto gk = [&](float u, float v) {
-      if constexpr (S1) {
-        const float d = fabsf(v - kf);
-        return u * fmaxf(0.f, 1.f - fminf(d, mf - d));
-      }
-      else
-        return fabsf(fmaf(ck, u, sk * v));
-    };
     float* hb = Hb;
     // horizontal pass: each thread four consecutive outputs of one row from
-    // 16-byte reads of both gradient planes (16 threads cover a row)
+    // 16-byte reads of the channel plane (16 threads cover a row)
 #pragma unroll
     for (int it = 0; it < (T::NQUAD + EX_NT - 1) / EX_NT; ++it) {
       const int qd = tid + it * EX_NT;
       if (T::NQUAD % EX_NT == 0 || qd < T::NQUAD) {
         const int r = qd >> 4, c4 = (qd & 15) * 4;
-        const float4* sx = reinterpret_cast<const float4*>(gxp + r * GWP + c4);
-        const float4* sy = reinterpret_cast<const float4*>(gyp + r * GWP + c4);
+        const float4* sx = reinterpret_cast<const float4*>(gk + r * GWP + c4);
         float x[4 * T::NQ];
 #pragma unroll
         for (int u = 0; u < T::NQ; ++u) {
-          const float4 vx = sx[u], vy = sy[u];
-          x[4 * u] = gk(vx.x, vy.x);
-          x[4 * u + 1] = gk(vx.y, vy.y);
-          x[4 * u + 2] = gk(vx.z, vy.z);
-          x[4 * u + 3] = gk(vx.w, vy.w);
+          const float4 vx = sx[u];
+          x[4 * u] = vx.x;
+          x[4 * u + 1] = vx.y;
+          x[4 * u + 2] = vx.z;
+          x[4 * u + 3] = vx.w;
         }
         float o4[4];
 #pragma unroll
@@ -331,12 +353,10 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
       }
     }
   // circular [1,2,1]/4 along orientation: D_{k-1} = Gs_{k-2}/4 + Gs_{k-1}/2 + Gs_k/4
-    if (k == 0) {
+    if (k < 2) {
+      // kept in this thread's LDS slots (registers are the occupancy limit)
 #pragma unroll
-      for (int o = 0; o < EX_RUN; ++o) g0[o] = cur[o];
-    } else if (k == 1) {
-#pragma unroll
-      for (int o = 0; o < EX_RUN; ++o) g1[o] = cur[o];
+      for (int o = 0; o < EX_RUN; ++o) keep[(k * EX_RUN + o) * EX_NT + tid] = cur[o];
     } else {
       float d[EX_RUN];
 #pragma unroll
@@ -345,7 +365,10 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
     }
 #pragma unroll
     for (int o = 0; o < EX_RUN; ++o) { pm2[o] = pm1[o]; pm1[o] = cur[o]; }
-    __syncthreads();  // every read of Hb is done before the next row pass
+    // the next channel's values: the channel plane was last read by this
+    // channel's row pass, which the barrier above has closed
+    if (k + 1 < m) form_channel(k + 1);
+    __syncthreads();  // every read of Hb is done and the next channel is formed
   };
   if constexpr (M > 0) {
 #pragma unroll
@@ -354,7 +377,12 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
     for (int k = 0; k < m; ++k) channel(k);
   }
   {
-    float d[EX_RUN];
+    float d[EX_RUN], g0[EX_RUN], g1[EX_RUN];
+#pragma unroll
+    for (int o = 0; o < EX_RUN; ++o) {
+      g0[o] = keep[o * EX_NT + tid];
+      g1[o] = m > 1 ? keep[(EX_RUN + o) * EX_NT + tid] : 0.f;
+    }
     if (m == 1) {
       emit(0, g0);
     } else {
@@ -547,7 +575,7 @@ __global__ __launch_bounds__(EX_NT) void fhog_kernel(FhogArgs a) {
       for (int k = 0; k < FH_BINS; ++k) {
         const float val = v[k][c4][o] * inv;
         if (ok) {
-          vout[(size_t)(c4 * FH_BINS + k) * plane + (size_t)o * W] = val;
+          __builtin_nontemporal_store(val, vout + (size_t)(c4 * FH_BINS + k) * plane + (size_t)o * W);
           q[o] = fma((double)val, (double)val, q[o]);
         }
       }
@@ -693,7 +721,7 @@ __global__ __launch_bounds__(EX_NT) void sat_fix_kernel(SatBatch b) {
   for (int k = 0; k < EX_NT / 64; ++k) corner += corner_part[k];
 #pragma unroll
   for (int o = 0; o < EX_RUN; ++o)
-    if (ok[o]) p0[(size_t)o * W1] = l[o] + r[o] + colc + corner;
+    if (ok[o]) __builtin_nontemporal_store(l[o] + r[o] + colc + corner, p0 + (size_t)o * W1);
   if (ty == 0) {
     for (int x = x0 + tid; x < min(W + 1, x0 + EX_TX + 1); x += EX_NT) sat[x] = 0.0;
   }
