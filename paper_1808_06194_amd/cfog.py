@@ -372,14 +372,16 @@ def make_jobs_array(jobs: List[Job]):
 
 
 def match_batch(jobs: List[Job], m: int = 9, flags: int = PATH_PLAIN_FFT, stream=None,
-                workspace: Optional[torch.Tensor] = None) -> List[torch.Tensor]:
+                workspace: Optional[torch.Tensor] = None, ctx: Optional["Context"] = None) -> List[torch.Tensor]:
     """Match every control point of every job; returns the (n, 6) int32 result
     tensors (see `results`).  Asynchronous on `stream`.  Without an explicit
-    `workspace` the context's cached one is used (grown on demand)."""
+    `workspace` the context's cached one is used (grown on demand).  `ctx`:
+    the context whose FFT-size choices (pins, autotuned picks) apply; by
+    default the device's shared one."""
     if not jobs:
         return []
     dev = jobs[0].cps.device.index
-    ctx = context(dev)
+    ctx = context(dev) if ctx is None else ctx
     arr = make_jobs_array(jobs)
     lib = load()
     for attempt in range(2):

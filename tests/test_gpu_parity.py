@@ -466,7 +466,7 @@ def test_match_precision_4096_full_size_sampled(cf, path):
 def test_match_batch_64_pairs_of_every_fft_size(cf):
     """The 64-pair batch as the benchmark runs it (batched path, autotuned FFT
     sizes, hipGraph capture): from the batch's own seeded pairs, the smallest
-    pair of every default FFT size (13 pairs, all their points in one call).
+    pair of every default FFT size (all their points in one call).
     Every point is checked for self-consistency, six seeded points per pair
     against the oracle's FFT form and one against its direct form; excused
     near-ties at most 2% of the checked points."""

@@ -64,7 +64,9 @@ def _requests(seed, pairs, n, surf_every=3, oob_every=7):
 
 def _direct(cf, pairs, reqs, flags):
     """Reference results: each request as its own match_batch call on volumes
-    extracted separately (same kernels, same FFT sizes)."""
+    extracted separately (same kernels, same FFT sizes: a fresh context, like
+    the server's own, so that no FFT size tuned by another test applies)."""
+    ctx = cf.Context(0)
     vols = []
     for A, B in pairs:
         vA, sA = cf.cfog_extract(torch.from_numpy(A).cuda())
@@ -76,10 +78,12 @@ def _direct(cf, pairs, reqs, flags):
         K = 2 * q["r"] + 1
         surf = torch.empty((len(q["cps"]), K, K), device="cuda") if q["surfaces"] else None
         job = cf.Job(vA, sA, vB, sB, torch.from_numpy(q["cps"]).cuda(), q["N"], q["r"], surfaces=surf)
-        cf.match_batch([job], flags=flags | cf.NO_SPLIT)  # the server matches every point whole
+        cf.match_batch([job], flags=flags | cf.NO_SPLIT, ctx=ctx)  # the server matches every point whole
         out.append((job, surf))
     torch.cuda.synchronize()
-    return [(j.out.cpu().numpy(), None if s is None else s.cpu().numpy()) for j, s in out]
+    res = [(j.out.cpu().numpy(), None if s is None else s.cpu().numpy()) for j, s in out]
+    ctx.close()
+    return res
 
 
 def _same(a, b):
