@@ -657,12 +657,16 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
 //  P, R1, R2, NT, layout  (R1 >= R2 keeps the per-lane outputs of stage 2
 //  small).  NT is set per size from measurement: as many waves as the
 //  registers allow without starving the column rounds (P = 96..108 at 768
-//  threads take every column in one round; P = 128 and 144 at 512 threads
-//  beat 256-384 threads; P = 120 and the global-layout sizes P >= 160 gain
-//  3-5% from 768 threads over 512 despite their register spilling).  The
-//  layout too: the fused one was 6-18% faster than parking T^ in registers
-//  for P = 80..144 except P = 128 (2.5% slower, more spills); the largest
-//  sizes park T^ in global memory.
+//  threads take every column in one round; P = 144 at 512 threads beats
+//  256-384 threads; P = 120 and the global-layout sizes P >= 160 gain 3-5%
+//  from 768 threads over 512 despite their register spilling).  The layout
+//  too: the fused one was 6-18% faster than parking T^ in registers for
+//  P = 80..144; the largest sizes park T^ in global memory.  Sizes that
+//  lost to the next larger one on every measured (N, r) are left out: P = 128
+//  (T^ in registers, 256 VGPRs and spills: 25-35% slower than P = 144) and
+//  P = 180 (15 x 12, several hundred spilled registers at any workgroup
+//  size: twice the time of P = 192).  P = 150 (fused, 512 threads) is 4-5%
+//  faster than P = 160 where both fit.
 #define CFOG_PLANS(X)                  \
   X(16, 4, 4, 64, LAY_REG)             \
   X(24, 6, 4, 128, LAY_REG)            \
@@ -678,10 +682,9 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
   X(100, 10, 10, 768, LAY_FUSED)       \
   X(108, 12, 9, 768, LAY_FUSED)        \
   X(120, 12, 10, 768, LAY_FUSED)       \
-  X(128, 16, 8, 512, LAY_REG)          \
   X(144, 12, 12, 512, LAY_FUSED)       \
+  X(150, 15, 10, 512, LAY_FUSED)       \
   X(160, 16, 10, 768, LAY_GLOBAL)      \
-  X(180, 15, 12, 768, LAY_GLOBAL)      \
   X(192, 16, 12, 768, LAY_GLOBAL)
 
 #define CFOG_CFG(P_, R1_, R2_, NT_, TG_) FftCfg<P_, R1_, R2_, NT_, TG_>
