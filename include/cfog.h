@@ -135,8 +135,10 @@ int cfog_extract_fhog(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, i
                       int32_t cell, float* d_vol, double* d_sat, void* d_ws, size_t ws_bytes,
                       void* stream);
 
-/* Device workspace (bytes) cfog_extract needs to build the SAT of an H x W
- * image: 8 * (H * ceil(W/64) + ceil(H/32) * W). */
+/* Device workspace (bytes) cfog_extract (and cfog_extract_fhog) needs to
+ * build the SAT of an H x W image: the larger of
+ * 8 * (H * ceil(W/128) + ceil(H/16) * W) (CFOG tiles of 128 x 16) and
+ * 8 * (H * ceil(W/64) + ceil(H/32) * W) (pixel-wise HOG tiles of 64 x 32). */
 size_t cfog_extract_workspace_size(int32_t H, int32_t W);
 
 /* One image of cfog_extract_batch: the arguments of cfog_extract that differ

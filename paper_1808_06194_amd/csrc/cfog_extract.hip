@@ -105,58 +105,89 @@ __device__ __forceinline__ double wave_incl_scan(double v) {
 }
 
 // D. Tile-local 2-D inclusive prefix of the per-pixel energies q (rows
-// [orow, orow + EX_RUN) of column oc of the tile at row y0), written into the
-// SAT buffer, plus the tile's right column (rc) and bottom row (bt) for the
-// carry kernels.  qx: 4 x 64 doubles of LDS.
+// [orow, orow + EX_RUN) of column oc of a TX x TY tile at row y0; a row of the
+// tile spans TX / 64 waves, EX_NT / TX row groups of EX_RUN rows stack down),
+// written into the SAT buffer, plus the tile's right column (rc) and bottom
+// row (bt) for the carry kernels.  qx: (EX_NT / TX) TX + EX_NT / 64 EX_RUN
+// doubles of LDS.
+template <int TX, int TY>
 __device__ __forceinline__ void tile_sat_prefix(double (&q)[EX_RUN], double* qx, double* sat, double* rc, double* bt,
                                                 int H, int W, int ntx, int y0, int orow, int oc, int gxx) {
-  const int tid = threadIdx.x;
+  constexpr int NWX = TX / 64, NRG = EX_NT / TX;
+  static_assert(TX % 64 == 0 && NRG * EX_RUN == TY, "tile geometry");
+  const int tid = threadIdx.x, lane = tid & 63, rg = tid / TX, hx = (tid >> 6) % NWX;
 #pragma unroll
-  for (int o = 0; o < EX_RUN; ++o) q[o] = wave_incl_scan(q[o]);  // along x (lanes = columns)
+  for (int o = 0; o < EX_RUN; ++o) q[o] = wave_incl_scan(q[o]);  // along x within the wave's 64 columns
+  if constexpr (NWX > 1) {
+    // the row totals of the waves to the left in the same row group
+    double* wt = qx + NRG * TX;  // [row group][wave][row]
+    if (lane == 63) {
+#pragma unroll
+      for (int o = 0; o < EX_RUN; ++o) wt[(rg * NWX + hx) * EX_RUN + o] = q[o];
+    }
+    __syncthreads();
+    for (int h = 0; h < hx; ++h) {
+#pragma unroll
+      for (int o = 0; o < EX_RUN; ++o) q[o] += wt[(rg * NWX + h) * EX_RUN + o];
+    }
+  }
 #pragma unroll
   for (int o = 1; o < EX_RUN; ++o) q[o] += q[o - 1];              // along y within the thread
-  const int wv = tid >> 6;
-  qx[wv * 64 + oc] = q[EX_RUN - 1];
+  qx[rg * TX + oc] = q[EX_RUN - 1];
   __syncthreads();
   double up = 0.0;
-  for (int i = 0; i < wv; ++i) up += qx[i * 64 + oc];
+  for (int i = 0; i < rg; ++i) up += qx[i * TX + oc];
   const int W1 = W + 1;
 #pragma unroll
   for (int o = 0; o < EX_RUN; ++o) {
     q[o] += up;
     const int gyy = y0 + orow + o;
     if (gyy < H && gxx < W) __builtin_nontemporal_store(q[o], sat + (size_t)(gyy + 1) * W1 + gxx + 1);
-    if (oc == 63 && gyy < H) rc[(size_t)gyy * ntx + blockIdx.x] = q[o];
+    if (oc == TX - 1 && gyy < H) rc[(size_t)gyy * ntx + blockIdx.x] = q[o];
   }
-  if (wv == EX_NT / 64 - 1 && gxx < W) bt[(size_t)blockIdx.y * W + gxx] = q[EX_RUN - 1];
+  if (rg == NRG - 1 && gxx < W) bt[(size_t)blockIdx.y * W + gxx] = q[EX_RUN - 1];
 }
 
-// LDS geometry of the extraction tile for Gaussian radius R.
+// The CFOG tile: 128 x 16 outputs, so that each row of a channel plane is
+// written 512 contiguous bytes at a time (measured on the extraction's write
+// pattern: 13-18% faster than 64 x 32 tiles, whose rows are 256 bytes).
+constexpr int CF_TX = 128;
+constexpr int CF_TY = 16;
+
+// LDS geometry of the CFOG tile for Gaussian radius R.
 template <int R>
 struct ExTile {
-  static constexpr int IW = EX_TX + 2 * R + 2, IH = EX_TY + 2 * R + 2;  // image tile (+1 for the gradient)
-  static constexpr int GW = EX_TX + 2 * R, GH = EX_TY + 2 * R;          // gradient / channel tile
+  static constexpr int TX = CF_TX, TY = CF_TY;
+  static constexpr int IW = TX + 2 * R + 2, IH = TY + 2 * R + 2;  // image tile (+1 for the gradient)
+  static constexpr int GW = TX + 2 * R, GH = TY + 2 * R;          // gradient / channel tile
   static constexpr int NQ = (4 + 2 * R + 3) / 4;  // 16-byte reads per 4 horizontal outputs
-  // gradient row stride: a multiple of 4 floats covering the last quad's reads
-  static constexpr int GWP = ((GW + 3) / 4 * 4) > (EX_TX - 4 + 4 * NQ) ? ((GW + 3) / 4 * 4) : (EX_TX - 4 + 4 * NQ);
-  static constexpr int NQUAD = GH * EX_TX / 4;    // horizontal outputs four at a time
+  // channel row stride: a multiple of 4 floats covering the last quad's reads
+  static constexpr int GWP = ((GW + 3) / 4 * 4) > (TX - 4 + 4 * NQ) ? ((GW + 3) / 4 * 4) : (TX - 4 + 4 * NQ);
+  static constexpr int QPR = TX / 4;              // horizontal outputs four at a time, per row
+  static constexpr int NQUAD = GH * QPR;
   static constexpr size_t IMG = ((size_t)IH * IW + 3) / 4 * 4;   // floats
   static constexpr size_t GP = (size_t)GH * GWP;                 // floats of the channel plane
-  static constexpr size_t HB = (size_t)GH * EX_TX;                // floats: one channel's row pass
-  // the image tile is dead once the gradients are in registers: it shares
-  // HB's storage
-  static constexpr size_t HBI = HB > IMG ? HB : IMG;
+  static constexpr size_t HB = (size_t)GH * TX;                   // floats: one channel's row pass
   // the spatially smoothed channels 0 and 1 of a thread's 4 outputs, needed
   // again by the circular orientation smoothing after the last channel
   static constexpr size_t KEEP = 2 * EX_RUN * EX_NT;  // floats, [value][thread]
-  static constexpr size_t BYTES = 4 * GP + 4 * HBI + 4 * KEEP;
-  // halo-tile pixels of a thread: lane l of wave w takes column l of the rows
-  // w, w + 8, ... (NROW of them), and the 2R columns right of the first 64
+  // LDS: [channel plane | KEEP] then HB; the image tile shares the first
+  // region (it is dead once the gradients are in registers)
+  static constexpr size_t A = (GP + KEEP) > IMG ? (GP + KEEP) : IMG;
+  static constexpr size_t BYTES = 4 * (A + HB);
+  // halo-tile pixels of a thread: thread t takes column t % TX of the rows
+  // t / TX + RPP i (NROW of them), and the 2R columns right of the first TX
   // are spread over the threads (NEXTRA each)
-  static constexpr int NROW = (GH + EX_NT / 64 - 1) / (EX_NT / 64);
+  static constexpr int RPP = EX_NT / TX;
+  static constexpr int NROW = (GH + RPP - 1) / RPP;
   static constexpr int NX = 2 * R;
-  static constexpr int NEXTRA = (NX * GH + EX_NT - 1) / EX_NT;
+  // where the last row slot is past the tile for some threads (GH not a
+  // multiple of RPP), those threads take the extra columns in it if they fit
+  static constexpr int LASTR = GH % RPP;  // threads with tid / TX >= LASTR have no row in the last slot
+  static constexpr bool FOLD = LASTR != 0 && (RPP - LASTR) * TX >= NX * GH;
+  static constexpr int NEXTRA = FOLD ? 0 : (NX * GH + EX_NT - 1) / EX_NT;
   static constexpr int NPX = NROW + NEXTRA;
+  static_assert((EX_NT / TX) * EX_RUN == TY, "one EX_RUN-row piece of the tile per thread");
 };
 
 // M > 0: the channel count fixed at compile time (the channel loop unrolls
@@ -164,22 +195,24 @@ struct ExTile {
 // it from the arguments.  S1: scheme 1 instead of Eq. 2, fixed at compile
 // time so that the per-pixel channel value carries no branch.
 template <int R, int M, bool S1>
-__global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
+__global__ __launch_bounds__(EX_NT) __attribute__((amdgpu_waves_per_eu(M > 0 ? 8 : 1, 8))) void cfog_extract_kernel(ExtractArgs a) {
   using T = ExTile<R>;
+  constexpr int TX = T::TX, TY = T::TY;
   constexpr int IW = T::IW, IH = T::IH, GW = T::GW, GH = T::GH, GWP = T::GWP;
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   const int m = M > 0 ? M : a.m;
   float* gk = lds;                                   // GH * GWP: one oriented-gradient channel
-  float* Hb = gk + T::GP;                            // GH * EX_TX row-pass outputs
-  float* img = Hb;                                   // IH * IW, read only by the gradient pass
-  float* keep = Hb + T::HBI;                         // KEEP: Gs_0, Gs_1 of this thread's outputs
-  double* qx = reinterpret_cast<double*>(gk);        // 64 wave carries per wave, after the last channel
-  static_assert(T::GP * sizeof(float) >= (EX_NT / 64) * 64 * sizeof(double), "wave carries");
+  float* keep = gk + T::GP;                          // KEEP: Gs_0, Gs_1 of this thread's outputs
+  float* img = lds;                                  // IH * IW, read only by the gradient pass
+  float* Hb = lds + T::A;                            // GH * TX row-pass outputs
+  double* qx = reinterpret_cast<double*>(gk);        // the tile prefix's carries, after the last channel
+  static_assert(T::GP * sizeof(float) >= ((EX_NT / TX) * TX + (EX_NT / 64) * EX_RUN) * sizeof(double),
+                "tile prefix carries");
   const ExImage I = a.im[blockIdx.z];
   if ((int)blockIdx.x >= I.ntx || (int)blockIdx.y >= I.nty) return;  // beyond this image's tiles
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * EX_TX, y0 = blockIdx.y * EX_TY;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
   const int H = I.H, W = I.W;
   float w[R + 1];
 #pragma unroll
@@ -210,7 +243,7 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   // B. gradients of the halo tile.  Interior tiles read their neighbours
   // directly; tiles at the border take them at clamped positions, which is
   // what clamp-to-edge gradient and Gaussian borders read.
-  const bool interior = x0 - R - 1 >= 0 && y0 - R - 1 >= 0 && x0 + EX_TX + R <= W - 1 && y0 + EX_TY + R <= H - 1;
+  const bool interior = x0 - R - 1 >= 0 && y0 - R - 1 >= 0 && x0 + TX + R <= W - 1 && y0 + TY + R <= H - 1;
   const int oy = y0 - R - 1, ox = x0 - R - 1;  // global coords of img[0][0]
   auto grad = [&](int r, int c) {              // (gx, gy) at halo-tile pixel (r, c)
     if (interior) {
@@ -223,23 +256,28 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
     const int yp = clampi(Yc + 1, 0, H - 1) - oy, ym = clampi(Yc - 1, 0, H - 1) - oy;
     return make_float2(img[yl * IW + xp] - img[yl * IW + xm], img[yp * IW + xl] - img[ym * IW + xl]);
   };
-  // this thread's pixels (the mapping of ExTile) and their offsets in the
-  // channel plane: row slots at rbase + it 8 GWP (rows beyond the tile are
-  // skipped, uniformly per wave), extra slots at xoff[e] (-1: none)
-  const int wv = tid >> 6, lane = tid & 63;
-  const int rbase = wv * GWP + lane;
-  int xoff[T::NEXTRA > 0 ? T::NEXTRA : 1];
+  // this thread's pixels (the mapping of ExTile): row slots at column
+  // tid % TX of the rows tid / TX + RPP it (rows beyond the tile are skipped,
+  // uniformly per wave), extra slots in the columns right of the first TX
+  const int pc = tid % TX, pr = tid / TX;
+  // folded extra pixel of this thread (in its last row slot), if any
+  const int fe = tid - T::LASTR * TX;
+  const bool fold_px = T::FOLD && pr >= T::LASTR && fe < T::NX * GH;
   float2 gb[T::NPX];  // this thread's pixels, held through the channel loop
 #pragma unroll
   for (int it = 0; it < T::NROW; ++it) {
-    const int r = wv + it * (EX_NT / 64);
-    gb[it] = r < GH ? grad(r, lane) : make_float2(0.f, 0.f);
+    const int r = pr + it * T::RPP;
+    if (T::FOLD && it == T::NROW - 1 && pr >= T::LASTR) {
+      const int fr = fe / T::NX;
+      gb[it] = fold_px ? grad(fr, TX + (fe - fr * T::NX)) : make_float2(0.f, 0.f);
+    } else {
+      gb[it] = r < GH ? grad(r, pc) : make_float2(0.f, 0.f);
+    }
   }
 #pragma unroll
   for (int e = 0; e < T::NEXTRA; ++e) {
     const int t = tid + e * EX_NT;
-    const int r = t / T::NX, c = EX_TX + (t - r * T::NX);
-    xoff[e] = t < T::NX * GH ? r * GWP + c : -1;
+    const int r = t / T::NX, c = TX + (t - r * T::NX);
     gb[T::NROW + e] = t < T::NX * GH ? grad(r, c) : make_float2(0.f, 0.f);
   }
   // scheme 1 keeps (|g|, orientation bin position in [0, m)) instead of (gx, gy)
@@ -272,13 +310,23 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
       }
     };
 #pragma unroll
-    for (int it = 0; it < T::NROW; ++it)
-      if (wv + it * (EX_NT / 64) < GH) gk[rbase + it * (EX_NT / 64) * GWP] = g_of(gb[it]);
+    for (int it = 0; it < T::NROW; ++it) {
+      if (T::FOLD && it == T::NROW - 1 && pr >= T::LASTR) {
+        const int fr = fe / T::NX;
+        if (fold_px) gk[fr * GWP + TX + (fe - fr * T::NX)] = g_of(gb[it]);
+      } else if (pr + it * T::RPP < GH) {
+        gk[(pr + it * T::RPP) * GWP + pc] = g_of(gb[it]);
+      }
+    }
 #pragma unroll
-    for (int e = 0; e < T::NEXTRA; ++e)
-      if (xoff[e] >= 0) gk[xoff[e]] = g_of(gb[T::NROW + e]);
+    for (int e = 0; e < T::NEXTRA; ++e) {
+      const int t = tid + e * EX_NT;
+      const int r = t / T::NX;
+      if (t < T::NX * GH) gk[r * GWP + TX + (t - r * T::NX)] = g_of(gb[T::NROW + e]);
+    }
   };
-  form_channel(0);  // the channel plane does not alias the image tile
+  __syncthreads();  // every read of the image tile is done: the channel plane shares its storage
+  form_channel(0);
   __syncthreads();
 
   // C. per channel: the horizontal Gaussian of the oriented gradient (the
@@ -286,7 +334,7 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   // vertical pass, which leaves the spatially smoothed channel Gs_k for the
   // rows [4 (tid/64), +4) of column tid % 64 in registers.  A barrier after
   // each pass: the next channel's row pass rewrites the buffer.
-  const int oc = tid & 63, orow = (tid >> 6) * EX_RUN;
+  const int oc = tid % TX, orow = (tid / TX) * EX_RUN;
   const int gxx = x0 + oc;
   double q[EX_RUN];
   float pm2[EX_RUN], pm1[EX_RUN];
@@ -310,12 +358,12 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
   auto channel = [&](int k) {
     float* hb = Hb;
     // horizontal pass: each thread four consecutive outputs of one row from
-    // 16-byte reads of the channel plane (16 threads cover a row)
+    // 16-byte reads of the channel plane (QPR threads cover a row)
 #pragma unroll
     for (int it = 0; it < (T::NQUAD + EX_NT - 1) / EX_NT; ++it) {
       const int qd = tid + it * EX_NT;
       if (T::NQUAD % EX_NT == 0 || qd < T::NQUAD) {
-        const int r = qd >> 4, c4 = (qd & 15) * 4;
+        const int r = qd / T::QPR, c4 = (qd - r * T::QPR) * 4;
         const float4* sx = reinterpret_cast<const float4*>(gk + r * GWP + c4);
         float x[4 * T::NQ];
 #pragma unroll
@@ -334,16 +382,16 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
           for (int t = 1; t <= R; ++t) s = fmaf(w[t], x[j + R - t] + x[j + R + t], s);
           o4[j] = s;
         }
-        *reinterpret_cast<float4*>(hb + r * EX_TX + c4) = make_float4(o4[0], o4[1], o4[2], o4[3]);
+        *reinterpret_cast<float4*>(hb + r * TX + c4) = make_float4(o4[0], o4[1], o4[2], o4[3]);
       }
     }
     __syncthreads();
     float cur[EX_RUN];
     {
-      const float* col = hb + orow * EX_TX + oc;  // col[t*TX] = row orow - R + t
+      const float* col = hb + orow * TX + oc;  // col[t*TX] = row orow - R + t
       float v[EX_RUN + 2 * R];
 #pragma unroll
-      for (int t = 0; t < EX_RUN + 2 * R; ++t) v[t] = col[t * EX_TX];
+      for (int t = 0; t < EX_RUN + 2 * R; ++t) v[t] = col[t * TX];
 #pragma unroll
       for (int o = 0; o < EX_RUN; ++o) {
         float s = w[0] * v[o + R];
@@ -396,7 +444,7 @@ __global__ __launch_bounds__(EX_NT) void cfog_extract_kernel(ExtractArgs a) {
     }
   }
   if (!I.sat) return;
-  tile_sat_prefix(q, qx, I.sat, I.rc, I.bt, H, W, I.ntx, y0, orow, oc, gxx);
+  tile_sat_prefix<TX, TY>(q, qx, I.sat, I.rc, I.bt, H, W, I.ntx, y0, orow, oc, gxx);
 }
 
 // ------------------------------------------------ pixel-wise HOG (FHOG)
@@ -581,7 +629,7 @@ __global__ __launch_bounds__(EX_NT) void fhog_kernel(FhogArgs a) {
       }
   }
   if (!a.sat) return;
-  tile_sat_prefix(q, qx, a.sat, a.rc, a.bt, H, W, a.ntx, y0, orow, oc, gxx);
+  tile_sat_prefix<EX_TX, EX_TY>(q, qx, a.sat, a.rc, a.bt, H, W, a.ntx, y0, orow, oc, gxx);
 }
 
 // Kernel 2: exclusive prefixes of the right columns along each image row (one
@@ -679,10 +727,13 @@ __global__ __launch_bounds__(SAT_NT) void sat_carry_kernel(SatBatch b) {
 }
 
 // Kernel 3: SAT = L + row carry + column carry + corner, in place; zero row 0
-// and column 0.  One thread per pixel column of an extraction tile, 4 rows each.
-// The tile's values and carries are loaded first, so their latency overlaps
-// the corner's reduction.
+// and column 0.  One workgroup per TX x TY extraction tile, one thread per
+// pixel column of a row group of EX_RUN rows (TX and TY as in the extraction
+// kernel that wrote the tile-local prefixes).  The tile's values and carries
+// are loaded first, so their latency overlaps the corner's reduction.
+template <int TX, int TY>
 __global__ __launch_bounds__(EX_NT) void sat_fix_kernel(SatBatch b) {
+  static_assert((EX_NT / TX) * EX_RUN == TY, "tile geometry");
   __shared__ double corner_part[EX_NT / 64];
   const SatImage I = b.im[blockIdx.z];
   if (!I.sat || (int)blockIdx.x >= I.ntx || (int)blockIdx.y >= I.nty) return;  // beyond this image's tiles
@@ -690,18 +741,18 @@ __global__ __launch_bounds__(EX_NT) void sat_fix_kernel(SatBatch b) {
   const double* const rc = I.rc;
   const double* const bt = I.bt;
   const int H = I.H, W = I.W, ntx = I.ntx;
-  const int tid = threadIdx.x, oc = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, oc = tid % TX, rg = tid / TX, wv = tid >> 6;
   const int tx = blockIdx.x, ty = blockIdx.y;
-  const int x0 = tx * EX_TX, y0 = ty * EX_TY;
+  const int x0 = tx * TX, y0 = ty * TY;
   const int W1 = W + 1;
   const int gxx = x0 + oc;
-  double* const p0 = sat + (size_t)(y0 + wv * EX_RUN + 1) * W1 + gxx + 1;
+  double* const p0 = sat + (size_t)(y0 + rg * EX_RUN + 1) * W1 + gxx + 1;
   bool ok[EX_RUN];
   double l[EX_RUN], r[EX_RUN];
   const double colc = gxx < W ? bt[(size_t)ty * W + gxx] : 0.0;
 #pragma unroll
   for (int o = 0; o < EX_RUN; ++o) {
-    const int gyy = y0 + wv * EX_RUN + o;
+    const int gyy = y0 + rg * EX_RUN + o;
     ok[o] = gxx < W && gyy < H;
     l[o] = ok[o] ? p0[(size_t)o * W1] : 0.0;
     r[o] = ok[o] ? rc[(size_t)gyy * ntx + tx] : 0.0;
@@ -709,7 +760,7 @@ __global__ __launch_bounds__(EX_NT) void sat_fix_kernel(SatBatch b) {
   // corner = sum_{j' < tx} (column prefix of bottom rows at the last column of tile j')
   double cpart = 0.0;
   for (int j = tid; j < tx; j += EX_NT) {
-    const int xl = min(W, (j + 1) * EX_TX) - 1;
+    const int xl = min(W, (j + 1) * TX) - 1;
     cpart += bt[(size_t)ty * W + xl];
   }
 #pragma unroll
@@ -723,10 +774,10 @@ __global__ __launch_bounds__(EX_NT) void sat_fix_kernel(SatBatch b) {
   for (int o = 0; o < EX_RUN; ++o)
     if (ok[o]) __builtin_nontemporal_store(l[o] + r[o] + colc + corner, p0 + (size_t)o * W1);
   if (ty == 0) {
-    for (int x = x0 + tid; x < min(W + 1, x0 + EX_TX + 1); x += EX_NT) sat[x] = 0.0;
+    for (int x = x0 + tid; x < min(W + 1, x0 + TX + 1); x += EX_NT) sat[x] = 0.0;
   }
   if (tx == 0) {
-    for (int y = y0 + tid; y < min(H + 1, y0 + EX_TY + 1); y += EX_NT) sat[(size_t)y * W1] = 0.0;
+    for (int y = y0 + tid; y < min(H + 1, y0 + TY + 1); y += EX_NT) sat[(size_t)y * W1] = 0.0;
   }
 }
 
@@ -748,9 +799,15 @@ static size_t lds_bytes(int m, int R) {
 
 size_t extract_lds_bytes(int m, int R) { return lds_bytes(m, R); }
 
-size_t extract_workspace_bytes(int H, int W) {
-  const size_t ntx = (W + EX_TX - 1) / EX_TX, nty = (H + EX_TY - 1) / EX_TY;
+// The carries of a TX x TY tiling: right columns [H][ntx], bottom rows [nty][W].
+static size_t carry_bytes(int H, int W, int TX, int TY) {
+  const size_t ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY;
   return sizeof(double) * ((size_t)H * ntx + nty * (size_t)W);
+}
+
+// Enough for the CFOG tiling and the pixel-wise HOG tiling.
+size_t extract_workspace_bytes(int H, int W) {
+  return std::max(carry_bytes(H, W, CF_TX, CF_TY), carry_bytes(H, W, EX_TX, EX_TY));
 }
 
 template <int R, bool S1>
@@ -807,7 +864,8 @@ int init_extract_attributes() {
   return 0;
 }
 
-// The SAT carries and fix-up of the images of one launch.
+// The SAT carries and fix-up of the images of one launch (tiles of TX x TY).
+template <int TX, int TY>
 static int launch_sat(const SatBatch& b, int n, hipStream_t st) {
   int carry_blocks = 0, ntx = 0, nty = 0;
   for (int i = 0; i < n; ++i) {
@@ -819,7 +877,7 @@ static int launch_sat(const SatBatch& b, int n, hipStream_t st) {
   }
   if (!carry_blocks) return 0;
   hipLaunchKernelGGL(sat_carry_kernel, dim3(carry_blocks, n), dim3(SAT_NT), 0, st, b);
-  hipLaunchKernelGGL(sat_fix_kernel, dim3(ntx, nty, n), dim3(EX_NT), 0, st, b);
+  hipLaunchKernelGGL((sat_fix_kernel<TX, TY>), dim3(ntx, nty, n), dim3(EX_NT), 0, st, b);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -868,8 +926,8 @@ int launch_extract_batch(const ExtractImage* ims, int n, int m, float sigma, int
       ExImage& I = a.im[i];
       I = ExImage{};
       I.img = src.img; I.stride = src.stride; I.vol = src.vol; I.sat = src.sat; I.H = src.H; I.W = src.W;
-      I.ntx = (src.W + EX_TX - 1) / EX_TX;
-      I.nty = (src.H + EX_TY - 1) / EX_TY;
+      I.ntx = (src.W + CF_TX - 1) / CF_TX;
+      I.nty = (src.H + CF_TY - 1) / CF_TY;
       if (src.sat) {
         I.rc = (double*)((char*)ws + off[j]);
         I.bt = I.rc + (size_t)src.H * I.ntx;
@@ -894,7 +952,7 @@ int launch_extract_batch(const ExtractImage* ims, int n, int m, float sigma, int
       default: return -1;
     }
     if (rc != 0) return rc;
-    rc = launch_sat(sb, nb, st);
+    rc = launch_sat<CF_TX, CF_TY>(sb, nb, st);
     if (rc != 0) return rc;
   }
   return 0;
@@ -938,7 +996,7 @@ int launch_fhog(const float* img, int64_t stride, int H, int W, int cell, float*
   if (!sat) return 0;
   SatBatch sb{};
   sb.im[0] = SatImage{sat, a.rc, a.bt, H, W, a.ntx, a.nty};
-  return launch_sat(sb, 1, st);
+  return launch_sat<EX_TX, EX_TY>(sb, 1, st);
 }
 
 }  // namespace cfog

@@ -81,7 +81,8 @@ def test_extract_batch_workspace_and_argument_checks(lib):
     from paper_1808_06194_amd import cfog
     shapes = [(37, 53), (1, 1), (2048, 2048), (129, 7)]
     one = [lib.cfog_extract_workspace_size(H, W) for H, W in shapes]
-    assert one[2] == 8 * (2048 * 32 + 64 * 2048)
+    assert one[2] == max(8 * (2048 * 16 + 128 * 2048), 8 * (2048 * 32 + 64 * 2048))
+    assert one[3] == max(8 * (129 * 1 + 9 * 7), 8 * (129 * 1 + 5 * 7))
     assert cfog.extract_batch_workspace_size(shapes) == sum((b + 255) // 256 * 256 for b in one)
     assert cfog.extract_batch_workspace_size(shapes, with_sat=False) == 0
     assert cfog.extract_batch_workspace_size([]) == 0
