@@ -94,6 +94,12 @@ struct FftCfg {
   static constexpr int T_ROWS = FUSE ? XT_ROWS : P;  // template rows the plan takes
   static constexpr size_t LDS = BASE + sizeof(float2) * (size_t)XT_ROWS * PH;
   static constexpr size_t TG_BYTES = TG ? sizeof(float2) * (size_t)P * PH : 0;
+  // The separated row spectra are 2 A and 2 B (the exact factor 4 of their
+  // product goes into the inverse's normalisation), except at P = 192, whose
+  // spills the register allocator places better with the halving done in
+  // the separation (measured: 11% faster; at P = 160 it was 18% slower).
+  // Both give the same values: scaling by a power of two is exact.
+  static constexpr bool SEP_HALF = P == 192;
 };
 
 // Lane identity within the FFT group layout.
@@ -190,12 +196,10 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const XRows (&S)[NS]
       v[a] = make_float2(re, im);
     }
   };
-  // the large plans (one workgroup per CU) fetch the next pair while
-  // transforming this one (measured: 3% at P = 144, 1-2% at P = 120 and 192;
-  // the 768-thread P = 100 plan loses by it)
-  constexpr bool PF = P >= 120;
-  float2 vn[R1];
-  if (PF && L.g < total && L.li < R2) load(L.g, vn);
+  // each pair is loaded just before its transform: the plans that use this
+  // pass (P <= 108 and the global-layout sizes) lost by fetching the next
+  // pair ahead (P = 100 at 768 threads; P = 160 and 192, whose registers
+  // spill, by 1%), unlike the fused pass of the larger plans
   for (int i = L.g; i < total; i += C::NG) {
     int s, q;
     which(i, s, q);
@@ -204,13 +208,7 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const XRows (&S)[NS]
     if (L.li < R2) {
       const int j = L.li;
       float2 v[R1];
-      if constexpr (PF) {
-#pragma unroll
-        for (int a = 0; a < R1; ++a) v[a] = vn[a];
-        if (i + C::NG < total) load(i + C::NG, vn);
-      } else {
-        load(i, v);
-      }
+      load(i, v);
       dft<R1, -1>(v);
 #pragma unroll
       for (int k = 0; k < R1; ++k) base[s1_pos<C>(j, k)] = v[k];
@@ -249,8 +247,9 @@ __device__ __forceinline__ void xpass_stage2(const Lane<C>& L, float2* base, int
       const int k = k1 + R1 * k2;
       if (L.li < R1 && k <= P / 2) {
         const float2 z = v[k2];
-        base[k] = make_float2(z.x + zm.x, z.y - zm.y);
-        base[PH + k] = odd_pad ? make_float2(0.f, 0.f) : make_float2(z.y + zm.y, zm.x - z.x);
+        constexpr float h = C::SEP_HALF ? 0.5f : 1.0f;
+        base[k] = make_float2(h * (z.x + zm.x), h * (z.y - zm.y));
+        base[PH + k] = odd_pad ? make_float2(0.f, 0.f) : make_float2(h * (z.y + zm.y), h * (zm.x - z.x));
       }
     });
     wave_sync();
@@ -560,7 +559,7 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   const int npair = (K + 1) >> 1;
   float* Cs = reinterpret_cast<float*>(X + 2 * npair * PH);
   // 1/P^2 of the inverse 2-D DFT and 1/4 for the doubled row spectra of T and S
-  const float inv = 0.25f / ((float)P * (float)P);
+  const float inv = (C::SEP_HALF ? 1.0f : 0.25f) / ((float)P * (float)P);
   for (int p = L.g; p < npair; p += C::NG) {
     float2* sc = X + 2 * opaque(p) * PH;
     float2 v[R1];
