@@ -81,7 +81,14 @@ struct FftCfg {
   static constexpr int GPW = 64 / G;           // groups per wave
   static constexpr int NW = NT / 64;
   static constexpr int NG = NW * GPW;          // groups per workgroup
-  static constexpr int KF = (PH + NG - 1) / NG;  // column rounds per group
+  // The DC and Nyquist columns of the x-pass half-spectra are real.  Where
+  // P/2 is a multiple of NG, the P/2 + 1 columns would take a whole round
+  // more than P/2 columns, so those two go through one complex column FFT as
+  // its real and imaginary parts (the packed job, column index 0): P/2 column
+  // jobs, a round and its accumulators fewer (P = 120 and 192).
+  static constexpr bool PACK = (P / 2) % NG == 0;
+  static constexpr int NCOL = PACK ? P / 2 : PH;   // column jobs of a y-pass
+  static constexpr int KF = (NCOL + NG - 1) / NG;  // column rounds per group
   static constexpr size_t BASE = sizeof(float2) * ((size_t)P * PH + P) + NW * 16;
   // Fused layout (plans with one workgroup per CU): the row spectra of the
   // template (XT, up to XT_ROWS rows) and of the window (X, P rows) side by
@@ -336,6 +343,51 @@ __device__ __forceinline__ void xpass_fused_preload(const Lane<C>& L, const XRow
   }
 }
 
+// Row `row` of a y-pass input column: col[row PH], or for the packed job
+// (col = X, the DC column) the DC value plus i times the Nyquist value.
+template <class C>
+__device__ __forceinline__ float2 col_in(const float2* col, int row, bool pk) {
+  const float2 v = col[row * C::PH];
+  return pk ? make_float2(v.x, col[row * C::PH + C::P / 2].x) : v;
+}
+
+// The packed job's share of the spectral product, for lane k1 holding
+// ky = k1 + R1 k2.  zs and zt are the column FFTs of (DC + i Nyquist) of the
+// window and the template; with F(-ky) = F((P - ky) mod P),
+//   T0 = (zt + conj zt(-ky)) / 2,  TN = (zt - conj zt(-ky)) / 2i  (S likewise),
+// both Hermitian in ky, and acc += conj(T0) S0 + i conj(TN) SN, whose inverse
+// column FFT is the DC column's correlation plus i times the Nyquist one's:
+//   conj(T0) S0 + i conj(TN) SN = (u s + i v t) / 4,
+//   u, v = conj zt +- zt(-ky),  s, t = zs +- conj zs(-ky).
+// The values at -ky come through LDS: column 0 takes zs, column P/2 zt.
+template <class C>
+__device__ __forceinline__ void packed_mac(float2* col, int k1, const float2 (&zs)[C::R2], const float2 (&zt)[C::R2],
+                                           float2 (&acc)[C::R2]) {
+  constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH;
+  wave_sync();  // the stage-2 reads of the column are done
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    const int ky = k1 + R1 * k2;
+    col[ky * PH] = zs[k2];
+    col[ky * PH + P / 2] = zt[k2];
+  }
+  wave_sync();
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    const int ky = k1 + R1 * k2;
+    const int km = ky == 0 ? 0 : P - ky;
+    const float2 sm = col[km * PH], tm = col[km * PH + P / 2];
+    const float2 ta = zt[k2], sc = zs[k2];
+    const float2 u = make_float2(ta.x + tm.x, tm.y - ta.y);
+    const float2 v = make_float2(ta.x - tm.x, -ta.y - tm.y);
+    const float2 sp = make_float2(sc.x + sm.x, sc.y - sm.y);
+    const float2 sq = make_float2(sc.x - sm.x, sc.y + sm.y);
+    const float2 us = cmul(u, sp), vt = cmul(v, sq);
+    acc[k2].x = fmaf(0.25f, us.x - vt.y, acc[k2].x);
+    acc[k2].y = fmaf(0.25f, us.y + vt.x, acc[k2].y);
+  }
+}
+
 // y-pass of the fused layout.  For each column kx of the group: the window's
 // column FFT in place in X (all P rows), then the template's, whose first
 // stage reads XT (rows < nT, zero beyond) and writes its intermediate into the
@@ -348,7 +400,8 @@ __device__ __forceinline__ void ypass_fused(const Lane<C>& L, const float2* XT, 
   static_for<0, C::KF>([&](auto rndI) {
     constexpr int rnd = decltype(rndI)::value;
     const int kx = L.g + rnd * C::NG;
-    if (kx < PH) {
+    if (kx < C::NCOL) {
+      const bool pk = C::PACK && rnd == 0 && kx == 0;
       float2* col = X + opaque(kx);
       const float2* colT = XT + kx;
       float2 sh[R2];
@@ -357,7 +410,7 @@ __device__ __forceinline__ void ypass_fused(const Lane<C>& L, const float2* XT, 
         const int j = L.li;
         float2 v[R1];
 #pragma unroll
-        for (int a = 0; a < R1; ++a) v[a] = col[(j + R2 * a) * PH];
+        for (int a = 0; a < R1; ++a) v[a] = col_in<C>(col, j + R2 * a, pk);
         dft<R1, -1>(v);
 #pragma unroll
         for (int k = 0; k < R1; ++k) col[s1c<C>(j, k) * PH] = v[k];
@@ -376,7 +429,7 @@ __device__ __forceinline__ void ypass_fused(const Lane<C>& L, const float2* XT, 
 #pragma unroll
         for (int a = 0; a < R1; ++a) {
           const int row = j + R2 * a;
-          v[a] = row < nT ? colT[row * PH] : make_float2(0.f, 0.f);
+          v[a] = row < nT ? col_in<C>(colT, row, pk) : make_float2(0.f, 0.f);
         }
         dft<R1, -1>(v);
 #pragma unroll
@@ -388,8 +441,12 @@ __device__ __forceinline__ void ypass_fused(const Lane<C>& L, const float2* XT, 
         float2 w[R2];
         stage2_inputs<C, false>(w, tw, k1, [&](int b) { return col[s1c<C>(b, k1) * PH]; });
         dft<R2, -1>(w);
+        if (pk) {
+          packed_mac<C>(col, k1, sh, w, acc[rnd]);
+        } else {
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) acc[rnd][k2] = cmac_conj(acc[rnd][k2], w[k2], sh[k2]);
+          for (int k2 = 0; k2 < R2; ++k2) acc[rnd][k2] = cmac_conj(acc[rnd][k2], w[k2], sh[k2]);
+        }
       }
     }
   });
@@ -398,20 +455,22 @@ __device__ __forceinline__ void ypass_fused(const Lane<C>& L, const float2* XT, 
 // y-pass: forward column FFTs of the half-spectrum (rows >= nrows were zeroed
 // by the x-pass).
 // Column kx = g + rnd * NG; lane k1 < R1 of its group ends up with
-// ky = k1 + R1 k2 and hands each value to sink(rnd, k2, kx, value).
-template <class C, class Sink>
-__device__ __forceinline__ void ypass_fwd(const Lane<C>& L, float2* X, const float2* tw, Sink&& sink) {
+// ky = k1 + R1 k2 and hands each value to sink(rnd, k2, kx, value), or for
+// the packed job all of them to psink(rnd, k1, values, column).
+template <class C, class Sink, class PSink>
+__device__ __forceinline__ void ypass_fwd(const Lane<C>& L, float2* X, const float2* tw, Sink&& sink, PSink&& psink) {
   constexpr int R1 = C::R1, R2 = C::R2, PH = C::PH;
   static_for<0, C::KF>([&](auto rndI) {
     constexpr int rnd = decltype(rndI)::value;
     const int kx = L.g + rnd * C::NG;
-    if (kx < PH) {
+    if (kx < C::NCOL) {
+      const bool pk = C::PACK && rnd == 0 && kx == 0;
       float2* col = X + opaque(kx);
       if (L.li < R2) {
         const int j = L.li;
         float2 v[R1];
 #pragma unroll
-        for (int a = 0; a < R1; ++a) v[a] = col[(j + R2 * a) * PH];
+        for (int a = 0; a < R1; ++a) v[a] = col_in<C>(col, j + R2 * a, pk);
         dft<R1, -1>(v);
 #pragma unroll
         for (int k = 0; k < R1; ++k) col[s1c<C>(j, k) * PH] = v[k];
@@ -422,10 +481,14 @@ __device__ __forceinline__ void ypass_fwd(const Lane<C>& L, float2* X, const flo
         float2 w[R2];
         stage2_inputs<C, false>(w, tw, k1, [&](int b) { return col[s1c<C>(b, k1) * PH]; });
         dft<R2, -1>(w);
-        static_for<0, R2>([&](auto k2I) {
-          constexpr int k2 = decltype(k2I)::value;
-          sink(rndI, k2I, kx, w[k2]);
-        });
+        if (pk) {
+          psink(rndI, k1, w, col);
+        } else {
+          static_for<0, R2>([&](auto k2I) {
+            constexpr int k2 = decltype(k2I)::value;
+            sink(rndI, k2I, kx, w[k2]);
+          });
+        }
       }
     }
   });
@@ -494,21 +557,31 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
       const XRows rt[1] = {{tA + c * planeA, jd.wA, N, N, X, true}};
       xpass_fwd<C, 1>(L, rt, tw);
       __syncthreads();
-      ypass_fwd<C>(L, X, tw, [&](auto rndI, auto k2I, int kx, float2 v) {
+      auto park = [&](auto rndI, auto k2I, int kx, float2 v) {
         constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
         if constexpr (C::TG) tg[(size_t)kx * P + L.li + R1 * k2] = v;
         else th[rnd][k2] = v;
+      };
+      ypass_fwd<C>(L, X, tw, park, [&](auto rndI, int, const float2 (&w)[R2], float2*) {
+        static_for<0, R2>([&](auto k2I) { park(rndI, k2I, 0, w[decltype(k2I)::value]); });
       });
       __syncthreads();
       const XRows rs[1] = {{sB + c * planeB, jd.wB, Ws, Ws, X, true}};
       xpass_fwd<C, 1>(L, rs, tw);
       __syncthreads();
+      auto parked = [&](auto rndI, auto k2I, int kx) {
+        constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
+        if constexpr (C::TG) return tg[(size_t)kx * P + L.li + R1 * k2];
+        else return th[rnd][k2];
+      };
       ypass_fwd<C>(L, X, tw, [&](auto rndI, auto k2I, int kx, float2 v) {
         constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
-        float2 t;
-        if constexpr (C::TG) t = tg[(size_t)kx * P + L.li + R1 * k2];
-        else t = th[rnd][k2];
-        acc[rnd][k2] = cmac_conj(acc[rnd][k2], t, v);
+        acc[rnd][k2] = cmac_conj(acc[rnd][k2], parked(rndI, k2I, kx), v);
+      }, [&](auto rndI, int k1, const float2 (&w)[R2], float2* col) {
+        constexpr int rnd = decltype(rndI)::value;
+        float2 zt[R2];
+        static_for<0, R2>([&](auto k2I) { zt[decltype(k2I)::value] = parked(rndI, k2I, 0); });
+        packed_mac<C>(col, k1, w, zt, acc[rnd]);
       });
     }
   };
@@ -520,7 +593,9 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
 #pragma unroll
   for (int rnd = 0; rnd < KF; ++rnd) {
     const int kx = L.g + rnd * C::NG;
-    if (kx < PH) {
+    if (kx < C::NCOL) {
+      // the packed job's outputs: real part the DC column, imaginary the Nyquist
+      const bool pk = C::PACK && rnd == 0 && kx == 0;
       float2* col = X + opaque(kx);
       if (L.li < R1) {
 #pragma unroll
@@ -545,7 +620,14 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) {
           const int uy = k1 + R1 * k2;
-          if (uy < K) col[uy * PH] = w[k2];
+          if (uy < K) {
+            if (pk) {
+              col[uy * PH] = make_float2(w[k2].x, 0.f);
+              col[uy * PH + P / 2] = make_float2(w[k2].y, 0.f);
+            } else {
+              col[uy * PH] = w[k2];
+            }
+          }
         }
       }
     }
