@@ -372,15 +372,28 @@ def matcher_digest() -> str:
     return h.hexdigest()
 
 
-def traffic_record(kernel_key: str):
-    """HBM bytes per matching call measured by counters (profiles/traffic.json),
-    if recorded for the current matcher sources; None otherwise."""
+EXTRACT_SOURCES = ("cfog_extract.hip", "kernels.hpp", "abi.hip")
+
+
+def extract_digest() -> str:
+    """sha256 over the sources the extraction launches are built from."""
+    h = hashlib.sha256()
+    for f in EXTRACT_SOURCES:
+        with open(os.path.join(ROOT, "paper_1808_06194_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record(kernel_key: str, digest=None):
+    """HBM bytes per call measured by counters (profiles/traffic.json), if
+    recorded for the current sources (matcher sources unless `digest` names
+    others); None otherwise."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
         e = rec.get(kernel_key)
-        if e and e.get("sources_sha256") == matcher_digest():
+        if e and e.get("sources_sha256") == (digest or matcher_digest()):
             return e["bytes_per_launch"]
     except (OSError, ValueError):
         pass
@@ -603,9 +616,10 @@ def main():
     # the extraction call (every image of the step) against the HBM roofline
     ext_bytes = sum(i[0].numel() for i in imgs) * extract_bytes_per_px(m)
     egbs = ext_bytes / t_ext / 1e9
+    ext_traffic = traffic_record(f"{args.workload}:extract", extract_digest()) if desc == "cfog" else None
     out["roofline_extract"] = dict(bound="hbm", achieved=round(egbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                                    frac=round(egbs / HBM_PEAK_GBS, 4), bytes_per_launch=ext_bytes,
-                                   launch_ms=round(t_ext * 1e3, 4),
+                                   traffic=ext_traffic, launch_ms=round(t_ext * 1e3, 4),
                                    kernel="cfog_extract_kernel + sat_carry_kernel + sat_fix_kernel, one "
                                           "cfog_extract_batch call" if desc != "fhog" else "fhog_kernel + SAT")
 
