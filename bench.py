@@ -179,11 +179,17 @@ def _oracle_tile_task(args):
 
 def sample_points(name: str, pairs, n_sample: int):
     """Seeded sample of (pair, cp) indices: every control point of small
-    workloads, one per pair for batch_64 (so every FFT-size bucket is in it),
-    else n_sample points of the single pair."""
+    workloads; for several pairs, n_sample / (pairs) distinct points of every
+    pair (at least one, so every FFT-size bucket is in it); else n_sample
+    points of the single pair."""
     rng = np.random.default_rng(np.random.SeedSequence([8, 1808]))
     if len(pairs) > 1:
-        return [(j, int(rng.integers(0, len(p["cps"])))) for j, p in enumerate(pairs)]
+        per = max(1, n_sample // len(pairs))
+        out = []
+        for j, p in enumerate(pairs):
+            n = len(p["cps"])
+            out += [(j, int(k)) for k in np.sort(rng.choice(n, min(per, n), replace=False))]
+        return out
     n = len(pairs[0]["cps"])
     if n <= n_sample:
         return [(0, k) for k in range(n)]
@@ -234,7 +240,7 @@ def cpu_leg(name: str, pairs, m: int, desc: str, pool, n_workers: int, n_sample:
     t_fft = cf_ * sum(len(p["cps"]) * wf(p["N"], p["r"]) for p in pairs)
     t_sat = px_total * 8.0 / 1e9                       # two cumulative sums: negligible, counted at 8 ns/px
     busy = sum(o["t_cfog"] + o["t_direct"] + o["t_fft"] + o["t_sat"] for o in outs) + sum(t for _, t in tile_res)
-    smp = (f"{len(sample)} sampled control points (seeded; {'one per pair' if len(pairs) > 1 else 'of the pair'}) "
+    smp = (f"{len(sample)} sampled control points (seeded; {'spread evenly over the pairs' if len(pairs) > 1 else 'of the pair'}) "
            f"through the oracle on {n_workers} worker processes: CFOG of their crops, direct SSD and FFT form, "
            f"plus CFOG of {len(tiles)} image tiles of up to 512^2; per-point costs fitted as m N^2 (2r+1)^2 "
            f"(direct) and m Ws^2 log2 Ws^2 (FFT form) and extrapolated to all {n_cps} points and "
@@ -425,7 +431,8 @@ def main():
                     help="shape of B's Gamma speckle (4: the workload recipe; larger is milder)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (then no cpu_baseline and no parity block)")
-    ap.add_argument("--cpu-sample", type=int, default=64, help="control points the oracle leg runs")
+    ap.add_argument("--cpu-sample", type=int, default=256,
+                    help="control points the oracle leg runs (and the parity block compares)")
     ap.add_argument("--gen-workers", type=int, default=-1,
                     help="processes generating batch_64 (-1: the host cores, 0: this process only)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
