@@ -420,8 +420,8 @@ def bf16_tol(N: int, r: int, m: int = 9) -> float:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="batch_64",
                     choices=["batch_64", "plain_2048", "plain_256", "precision_4096", "serve", "harris_8192",
                              "reject_3000"])
