@@ -152,8 +152,8 @@ cfog::SplitArgs plan_split(const cfog::FftPlan* p, int n, int S, int m, int Nmax
   return cfog::SplitArgs{c.n_whole, c.G, c.slot, nullptr};
 }
 
-// Workspace layout of a plain-path launch of job j: the template-spectrum
-// region of a TG plan, then the split partials (when split_ok).
+// Workspace layout of a plain-path launch of job j: the split partials (when
+// split_ok), one workgroup per work item.
 struct PlainLayout {
   const cfog::FftPlan* p = nullptr;
   cfog::SplitArgs sp{0, 1, 0, nullptr};
@@ -170,16 +170,15 @@ PlainLayout plain_layout(cfog_ctx* ctx, const cfog_job& j, int m, bool split_ok)
   L.sp = split_ok ? plan_split(L.p, j.n_cps, S, m, j.N, j.N + 2 * j.r, 2 * j.r + 1, &sb)
                   : cfog::SplitArgs{j.n_cps, 1, 0, nullptr};
   const int items = cfog::split_items(j.n_cps, L.sp);
-  L.blocks = L.p->tg_bytes ? std::min(items, S) : items;
-  L.split_off = align_up((size_t)L.blocks * L.p->tg_bytes, 256);
-  L.total = L.split_off + sb;
+  L.blocks = items;
+  L.split_off = 0;
+  L.total = sb;
   return L;
 }
 
 struct Bucket {
   const cfog::FftPlan* plan;
   int begin, count, blocks;
-  size_t tg_off;  // this bucket's template-spectrum region in the workspace
   cfog::SplitArgs sp;
   size_t split_off;  // its split partials (sp.G > 1)
 };
@@ -206,10 +205,9 @@ int build_batch(cfog_ctx* ctx, const cfog_job* jobs, int n_jobs, int m, int obj,
   for (int i = 0; i < n_jobs; ++i) B.jobs[i] = to_device_job(jobs[i], m, obj);
   int nplans = 0;
   const cfog::FftPlan* all = cfog::fft_plans(&nplans);
-  size_t tg = 0;
   std::vector<size_t> split_bytes;
   for (int p = 0; p < nplans; ++p) {
-    Bucket b{&all[p], (int)B.tasks.size(), 0, 0, 0, cfog::SplitArgs{0, 1, 0, nullptr}, 0};
+    Bucket b{&all[p], (int)B.tasks.size(), 0, 0, cfog::SplitArgs{0, 1, 0, nullptr}, 0};
     int Nmax = 0, Wmax = 0, Kmax = 0;
     for (int i = 0; i < n_jobs; ++i)
       if (plans[i] == &all[p] && jobs[i].n_cps > 0) {
@@ -230,11 +228,9 @@ int build_batch(cfog_ctx* ctx, const cfog_job* jobs, int n_jobs, int m, int obj,
     split_budget -= sb;
     split_bytes.push_back(sb);
     b.blocks = std::min(cfog::split_items(b.count, b.sp), S);
-    b.tg_off = tg;
-    tg += align_up((size_t)b.blocks * b.plan->tg_bytes, 256);  // buckets run concurrently
     B.buckets.push_back(b);
   }
-  B.jobs_off = tg;
+  B.jobs_off = 0;
   B.tasks_off = align_up(B.jobs_off + sizeof(cfog::MatchJob) * (size_t)n_jobs, 256);
   size_t end = align_up(B.tasks_off + sizeof(int2) * B.tasks.size(), 256);
   B.table_bytes = B.tasks_off + sizeof(int2) * B.tasks.size() - B.jobs_off;
@@ -262,8 +258,8 @@ int enqueue_batch(cfog_ctx* ctx, const BatchPlan& B, char* ws, const void* host,
   auto launch_bucket = [&](const Bucket& b, hipStream_t s) {
     cfog::SplitArgs sp = b.sp;
     sp.part = sp.G > 1 ? (float*)(ws + b.split_off) : nullptr;
-    return cfog::launch_match_fft(b.plan, cfog::MatchJob{}, d_jobs, d_tasks + b.begin, b.count, b.blocks,
-                                  ws + b.tg_off, sp, s) == 0 &&
+    return cfog::launch_match_fft(b.plan, cfog::MatchJob{}, d_jobs, d_tasks + b.begin, b.count, b.blocks, sp,
+                                  s) == 0 &&
            cfog::launch_split_reduce(cfog::MatchJob{}, d_jobs, d_tasks + b.begin, b.count, sp, s) == 0;
   };
   if (B.buckets.size() == 1) {
@@ -335,8 +331,8 @@ void save_plan_cache(cfog_ctx* ctx) {
 // Time the candidate FFT sizes for (N, r) on up to 2 x #CU control points of
 // job j and keep the fastest.  The trial launches write into the job's own
 // result buffer; the real launch that follows on the same stream overwrites
-// them.  tg_ws/tg_bytes: scratch for the template spectra of the large sizes.
-int autotune(cfog_ctx* ctx, const cfog_job& j, int m, hipStream_t st, void* tg_ws, size_t tg_bytes) {
+// them.
+int autotune(cfog_ctx* ctx, const cfog_job& j, int m, hipStream_t st) {
   const long key = nrm_key(j.N, j.r, m);
   if (ctx->pinned.count(nr_key(j.N, j.r)) || ctx->tuned.count(key) || j.n_cps == 0) return CFOG_OK;
   int nplans = 0;
@@ -363,14 +359,13 @@ int autotune(cfog_ctx* ctx, const cfog_job& j, int m, hipStream_t st, void* tg_w
   float best = 1e30f;
   int bestP = first->P;
   for (const cfog::FftPlan* p : cands) {
-    const int blocks = p->tg_bytes ? std::min(dj.n_cps, cfog::plan_slots(p, ctx->num_cus)) : dj.n_cps;
-    if (p->tg_bytes && (!tg_ws || (size_t)blocks * p->tg_bytes > tg_bytes)) continue;
+    const int blocks = dj.n_cps;
     float ms = 0.f;
     bool ok = true;
     for (int rep = 0; rep < 2 && ok; ++rep) {  // the first launch warms up
       ok = hipEventRecord(e0, st) == hipSuccess &&
-           cfog::launch_match_fft(p, dj, nullptr, nullptr, dj.n_cps, blocks, tg_ws,
-                                  cfog::SplitArgs{dj.n_cps, 1, 0, nullptr}, st) == 0 &&
+           cfog::launch_match_fft(p, dj, nullptr, nullptr, dj.n_cps, blocks, cfog::SplitArgs{dj.n_cps, 1, 0, nullptr},
+                                  st) == 0 &&
            hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
            hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
     }
@@ -618,11 +613,6 @@ static size_t ws_need(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32
   for (int i = 0; i < n_jobs; ++i)
     if (validate_job(jobs[i], m) != CFOG_OK) return (size_t)-1;
   if (path == CFOG_PATH_MFMA_BF16) return cfog::direct_workspace_bytes(jobs, n_jobs, m, ctx->num_cus);
-  // the autotuner may try sizes above the default: reserve for the largest
-  size_t tune = 0;
-  if (flags & CFOG_AUTOTUNE)
-    for (int i = 0; i < n_jobs; ++i)
-      tune = std::max(tune, cfog::max_tg_bytes(jobs[i].N, jobs[i].r) * (size_t)std::min(jobs[i].n_cps, 2 * ctx->num_cus));
   if (path == CFOG_PATH_PLAIN_FFT) {
     size_t need = 0;  // the jobs run one after another on one stream
     for (int i = 0; i < n_jobs; ++i) {
@@ -631,11 +621,11 @@ static size_t ws_need(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32
       if (!L.p) return 0;  // match_batch reports CFOG_EUNSUPPORTED
       need = std::max(need, L.total);
     }
-    return align_up(std::max(need, tune), 256);
+    return align_up(need, 256);
   }
   BatchPlan B;
   if (build_batch(ctx, jobs, n_jobs, m, 0, B, split ? SIZE_MAX : 0) != CFOG_OK) return 0;
-  return std::max(B.total, align_up(tune, 256));
+  return B.total;
 }
 
 size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m,
@@ -675,13 +665,12 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
   const size_t need = ws_need(ctx, jobs, n_jobs, m, flags, false);  // the minimum
   if (need > 0 && (!d_ws || ws_bytes < need)) return CFOG_ENOMEM;
   if (flags & CFOG_AUTOTUNE) {
-    // tune each distinct (N, r) on its first job, with the workspace's front as
-    // template-spectrum scratch (stream-ordered before its real use below)
+    // tune each distinct (N, r) on its first job
     std::map<long, int> seen;
     for (int i = 0; i < n_jobs; ++i) {
       if (seen.count(nr_key(jobs[i].N, jobs[i].r)) || jobs[i].n_cps == 0) continue;
       seen[nr_key(jobs[i].N, jobs[i].r)] = 1;
-      int rc = autotune(ctx, jobs[i], m, st, ws, ws_bytes);
+      int rc = autotune(ctx, jobs[i], m, st);
       if (rc != CFOG_OK) return rc;
     }
   }
@@ -696,7 +685,7 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
       cfog::SplitArgs sp = L.sp;
       sp.part = sp.G > 1 ? (float*)(ws + L.split_off) : nullptr;
       const cfog::MatchJob dj = to_device_job(jobs[i], m, obj);
-      if (cfog::launch_match_fft(L.p, dj, nullptr, nullptr, jobs[i].n_cps, L.blocks, ws, sp, st) != 0 ||
+      if (cfog::launch_match_fft(L.p, dj, nullptr, nullptr, jobs[i].n_cps, L.blocks, sp, st) != 0 ||
           cfog::launch_split_reduce(dj, nullptr, nullptr, jobs[i].n_cps, sp, st) != 0)
         return record(ctx, hipGetLastError());
     }

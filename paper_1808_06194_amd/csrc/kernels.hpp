@@ -58,19 +58,15 @@ int launch_fhog(const float* img, int64_t stride, int H, int W, int cell, float*
 size_t extract_lds_bytes(int m, int R);
 size_t extract_workspace_bytes(int H, int W);
 
-// FFT matcher plans: FFT side P = R1 * R2, NT threads per workgroup; plans
-// with tg_bytes > 0 park the template spectrum of the current channel in a
-// per-workgroup global workspace of that size.
-struct FftPlan { int P, R1, R2, NT; size_t lds; size_t tg_bytes; int t_rows; /* template rows it takes */ };
+// FFT matcher plans: FFT side P = R1 * R2, NT threads per workgroup, lds
+// bytes of dynamic LDS, templates of up to t_rows rows.
+struct FftPlan { int P, R1, R2, NT; size_t lds; int t_rows; };
 const FftPlan* fft_plans(int* count);
 // Smallest supported plan with P >= Ws whose LDS scratch also fits the
 // inverse row pass for K = 2r + 1; nullptr if none.
 const FftPlan* choose_fft_plan(int N, int r);
 // Whether plan p can match template side N with radius r.
 bool plan_fits(const FftPlan* p, int N, int r);
-// Largest per-workgroup template-spectrum workspace among the sizes the
-// autotuner considers for (N, r).
-size_t max_tg_bytes(int N, int r);
 // Set the dynamic-LDS limits of every kernel of the library on the current
 // device (once per device, from context creation, before any stream capture;
 // safe to call from several host threads).  0 on success.
@@ -82,7 +78,6 @@ int init_outlier_attributes();
 int plan_slots(const FftPlan* p, int num_cus);
 // Launch the FFT matcher.  d_jobs == nullptr: n_tasks control points of job0
 // (plain path).  Otherwise n_tasks (job, cp) pairs from d_tasks over d_jobs.
-// tg_ws: n_blocks * tg_bytes bytes when tg_bytes > 0.
 // Channel split of a launch's last tasks: tasks [0, n_whole) run whole; every
 // later task runs as G work items, item g taking the channels
 // [g m / G, (g+1) m / G) and writing its correlation surface (K*K floats) to
@@ -98,7 +93,7 @@ struct SplitArgs {
 
 // n_blocks: workgroups (a grid-stride loop covers the remaining items).
 int launch_match_fft(const FftPlan* plan, const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks,
-                     int n_tasks, int n_blocks, void* tg_ws, const SplitArgs& sp, hipStream_t st);
+                     int n_tasks, int n_blocks, const SplitArgs& sp, hipStream_t st);
 // Finishes the split tasks [sp.n_whole, n_tasks) (no-op for G = 1).
 int launch_split_reduce(const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks, int n_tasks,
                         const SplitArgs& sp, hipStream_t st);

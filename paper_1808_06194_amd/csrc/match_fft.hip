@@ -66,14 +66,13 @@ __device__ __forceinline__ int opaque(int v) {
 }
 
 // Channel layouts of a plan: T^ parked in registers between the template's
-// and the window's passes (LAY_REG), both row spectra side by side in LDS
-// (LAY_FUSED), or T^ parked in a global workspace (LAY_GLOBAL).
-enum : int { LAY_REG = 0, LAY_FUSED = 1, LAY_GLOBAL = 2 };
+// and the window's passes (LAY_REG), or both row spectra side by side in LDS
+// (LAY_FUSED).
+enum : int { LAY_REG = 0, LAY_FUSED = 1 };
 
 template <int P_, int R1_, int R2_, int NT_, int LAY_>
 struct FftCfg {
   static constexpr int P = P_, R1 = R1_, R2 = R2_, NT = NT_;
-  static constexpr bool TG = LAY_ == LAY_GLOBAL;  // T^ parked in a global workspace
   static_assert(P == R1 * R2, "P must equal R1 * R2");
   static_assert(NT % 64 == 0 && NT <= 1024, "bad workgroup size");
   static constexpr int PH = P / 2 + 1;
@@ -100,7 +99,6 @@ struct FftCfg {
   static constexpr int XT_ROWS = FUSE ? (int)(XT_FIT < (size_t)P ? XT_FIT : (size_t)P) : 0;
   static constexpr int T_ROWS = FUSE ? XT_ROWS : P;  // template rows the plan takes
   static constexpr size_t LDS = BASE + sizeof(float2) * (size_t)XT_ROWS * PH;
-  static constexpr size_t TG_BYTES = TG ? sizeof(float2) * (size_t)P * PH : 0;
   // The separated row spectra are 2 A and 2 B (the exact factor 4 of their
   // product goes into the inverse's normalisation), except at P = 192, whose
   // spills the register allocator places better with the halving done in
@@ -500,8 +498,7 @@ __device__ __forceinline__ void ypass_fwd(const Lane<C>& L, float2* X, const flo
 // out-of-bounds point).
 template <class C>
 __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, int cpi, float2* X, const float2* tw,
-                          ArgminState* red, float2* __restrict__ tg, int c0, int c1,
-                          float* __restrict__ part, int g) {
+                          ArgminState* red, int c0, int c1, float* __restrict__ part, int g) {
   constexpr int P = C::P, R1 = C::R1, R2 = C::R2, PH = C::PH, NT = C::NT, KF = C::KF;
   const int4 cp = jd.cps[cpi];
   const int N = jd.N, r = jd.r, K = 2 * r + 1, Ws = N + 2 * r;
@@ -552,15 +549,14 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   // template's and the window's passes; four barriers per channel
   auto split_channels = [&]() {
     for (int c = c0; c < c1; ++c) {
-      float2 th[C::TG ? 1 : KF][R2];
+      float2 th[KF][R2];
       __syncthreads();  // previous readers of X are done
       const XRows rt[1] = {{tA + c * planeA, jd.wA, N, N, X, true}};
       xpass_fwd<C, 1>(L, rt, tw);
       __syncthreads();
-      auto park = [&](auto rndI, auto k2I, int kx, float2 v) {
+      auto park = [&](auto rndI, auto k2I, int, float2 v) {
         constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
-        if constexpr (C::TG) tg[(size_t)kx * P + L.li + R1 * k2] = v;
-        else th[rnd][k2] = v;
+        th[rnd][k2] = v;
       };
       ypass_fwd<C>(L, X, tw, park, [&](auto rndI, int, const float2 (&w)[R2], float2*) {
         static_for<0, R2>([&](auto k2I) { park(rndI, k2I, 0, w[decltype(k2I)::value]); });
@@ -569,10 +565,9 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
       const XRows rs[1] = {{sB + c * planeB, jd.wB, Ws, Ws, X, true}};
       xpass_fwd<C, 1>(L, rs, tw);
       __syncthreads();
-      auto parked = [&](auto rndI, auto k2I, int kx) {
+      auto parked = [&](auto rndI, auto k2I, int) {
         constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
-        if constexpr (C::TG) return tg[(size_t)kx * P + L.li + R1 * k2];
-        else return th[rnd][k2];
+        return th[rnd][k2];
       };
       ypass_fwd<C>(L, X, tw, [&](auto rndI, auto k2I, int kx, float2 v) {
         constexpr int rnd = decltype(rndI)::value, k2 = decltype(k2I)::value;
@@ -693,11 +688,11 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
 // One kernel for both paths: with jobs == nullptr every task t is control
 // point t of job0 (plain path); otherwise task t = tasks[t] = (job, cp) over the
 // device job table (batched path).  Workgroups loop over tasks with a grid
-// stride; tg_ws holds one T^ buffer per workgroup for the TG plans.
+// stride.
 template <class C>
 __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const MatchJob* __restrict__ jobs,
                                                           const int2* __restrict__ tasks, int n_tasks,
-                                                          float2* __restrict__ tg_ws, SplitArgs sp) {
+                                                          SplitArgs sp) {
   extern __shared__ float2 smem[];
   float2* X = smem;
   float2* tw = X + C::P * C::PH;
@@ -711,7 +706,6 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
     tw[i] = make_float2((float)c, (float)-s);
   }
   const Lane<C> L;
-  float2* tg = C::TG ? tg_ws + (size_t)blockIdx.x * C::P * C::PH : nullptr;
   const int n_items = split_items(n_tasks, sp);
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     __syncthreads();  // twiddles ready / previous task's reduction done
@@ -730,7 +724,7 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
       cpi = tk.y;
     }
     float* part = G > 1 ? sp.part + (size_t)(it - sp.n_whole) * sp.slot : nullptr;
-    match_one<C>(L, jd, cpi, X, tw, red, tg, g * jd.m / G, (g + 1) * jd.m / G, part, g);
+    match_one<C>(L, jd, cpi, X, tw, red, g * jd.m / G, (g + 1) * jd.m / G, part, g);
   }
 }
 
@@ -739,15 +733,17 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
 //  small).  NT is set per size from measurement: as many waves as the
 //  registers allow without starving the column rounds (P = 96..108 at 768
 //  threads take every column in one round; P = 144 at 512 threads beats
-//  256-384 threads; P = 120 and the global-layout sizes P >= 160 gain 3-5%
-//  from 768 threads over 512 despite their register spilling).  The layout
-//  too: the fused one was 6-18% faster than parking T^ in registers for
-//  P = 80..144; the largest sizes park T^ in global memory.  Sizes that
-//  lost to the next larger one on every measured (N, r) are left out: P = 128
-//  (T^ in registers, 256 VGPRs and spills: 25-35% slower than P = 144) and
-//  P = 180 (15 x 12, several hundred spilled registers at any workgroup
-//  size: twice the time of P = 192).  P = 150 (fused, 512 threads) is 4-5%
-//  faster than P = 160 where both fit.
+//  256-384 threads; P = 120 gains 3% from 768 threads over 512 despite its
+//  register spilling).  The layout too: the fused one was 6-18% faster than
+//  parking T^ in registers for P = 80..144.  P = 160 and 192 park T^ in
+//  registers at 512 threads, where P = 192's DC/Nyquist packing leaves three
+//  whole column rounds: 10% and 18% faster than parking it in a global
+//  workspace at 768 threads, whose round trip was most of their HBM traffic.
+//  Sizes that lost to the next larger one on every measured (N, r) are left
+//  out: P = 128 (T^ in registers, 256 VGPRs and spills: 25-35% slower than
+//  P = 144) and P = 180 (15 x 12, several hundred spilled registers at any
+//  workgroup size: twice the time of P = 192).  P = 150 (fused, 512 threads)
+//  is 4-5% faster than P = 160 where both fit.
 #define CFOG_PLANS(X)                  \
   X(16, 4, 4, 64, LAY_REG)             \
   X(24, 6, 4, 128, LAY_REG)            \
@@ -765,15 +761,14 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
   X(120, 12, 10, 768, LAY_FUSED)       \
   X(144, 12, 12, 512, LAY_FUSED)       \
   X(150, 15, 10, 512, LAY_FUSED)       \
-  X(160, 16, 10, 768, LAY_GLOBAL)      \
-  X(192, 16, 12, 768, LAY_GLOBAL)
+  X(160, 16, 10, 512, LAY_REG)         \
+  X(192, 16, 12, 512, LAY_REG)
 
-#define CFOG_CFG(P_, R1_, R2_, NT_, TG_) FftCfg<P_, R1_, R2_, NT_, TG_>
+#define CFOG_CFG(P_, R1_, R2_, NT_, L_) FftCfg<P_, R1_, R2_, NT_, L_>
 
 static const FftPlan kPlans[] = {
-#define CFOG_PLAN_ENTRY(P_, R1_, R2_, NT_, TG_)                                                  \
-  {P_, R1_, R2_, NT_, CFOG_CFG(P_, R1_, R2_, NT_, TG_)::LDS, CFOG_CFG(P_, R1_, R2_, NT_, TG_)::TG_BYTES, \
-   CFOG_CFG(P_, R1_, R2_, NT_, TG_)::T_ROWS},
+#define CFOG_PLAN_ENTRY(P_, R1_, R2_, NT_, L_) \
+  {P_, R1_, R2_, NT_, CFOG_CFG(P_, R1_, R2_, NT_, L_)::LDS, CFOG_CFG(P_, R1_, R2_, NT_, L_)::T_ROWS},
     CFOG_PLANS(CFOG_PLAN_ENTRY)
 #undef CFOG_PLAN_ENTRY
 };
@@ -798,17 +793,6 @@ const FftPlan* choose_fft_plan(int N, int r) {
   return nullptr;
 }
 
-size_t max_tg_bytes(int N, int r) {
-  size_t m = 0;
-  int taken = 0;
-  for (const FftPlan& p : kPlans)
-    if (plan_fits(&p, N, r) && taken < 3) {
-      m = std::max(m, p.tg_bytes);
-      ++taken;
-    }
-  return m;
-}
-
 // Workgroups of each plan resident per CU, from the runtime's occupancy
 // calculator (registers, LDS and waves); filled by init_match_fft_attributes.
 static int g_plan_occupancy[64];
@@ -822,10 +806,8 @@ int plan_slots(const FftPlan* p, int num_cus) {
 
 template <class C>
 static int launch_t(const MatchJob& job0, const MatchJob* jobs, const int2* tasks, int n_tasks, int n_blocks,
-                    void* tg_ws, const SplitArgs& sp, hipStream_t st) {
-  if (C::TG && !tg_ws) return -1;
-  hipLaunchKernelGGL(match_fft_kernel<C>, dim3(n_blocks), dim3(C::NT), C::LDS, st, job0, jobs, tasks, n_tasks,
-                     (float2*)tg_ws, sp);
+                    const SplitArgs& sp, hipStream_t st) {
+  hipLaunchKernelGGL(match_fft_kernel<C>, dim3(n_blocks), dim3(C::NT), C::LDS, st, job0, jobs, tasks, n_tasks, sp);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -871,9 +853,9 @@ int launch_split_reduce(const MatchJob& job0, const MatchJob* d_jobs, const int2
 
 int init_match_fft_attributes() {
   int idx = 0;
-#define CFOG_PLAN_ATTR(P_, R1_, R2_, NT_, TG_)                                                               \
+#define CFOG_PLAN_ATTR(P_, R1_, R2_, NT_, L_)                                                               \
   {                                                                                                          \
-    using Cfg = CFOG_CFG(P_, R1_, R2_, NT_, TG_);                                                            \
+    using Cfg = CFOG_CFG(P_, R1_, R2_, NT_, L_);                                                             \
     if (hipFuncSetAttribute((const void*)match_fft_kernel<Cfg>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
                             (int)Cfg::LDS) != hipSuccess)                                                    \
       return -2;                                                                                             \
@@ -908,11 +890,11 @@ int init_kernel_attributes() {
 }
 
 int launch_match_fft(const FftPlan* plan, const MatchJob& job0, const MatchJob* d_jobs, const int2* d_tasks,
-                     int n_tasks, int n_blocks, void* tg_ws, const SplitArgs& sp, hipStream_t st) {
+                     int n_tasks, int n_blocks, const SplitArgs& sp, hipStream_t st) {
   if (n_tasks <= 0) return 0;
-#define CFOG_PLAN_CASE(P_, R1_, R2_, NT_, TG_) \
-  if (plan->P == P_)                           \
-    return launch_t<CFOG_CFG(P_, R1_, R2_, NT_, TG_)>(job0, d_jobs, d_tasks, n_tasks, n_blocks, tg_ws, sp, st);
+#define CFOG_PLAN_CASE(P_, R1_, R2_, NT_, L_) \
+  if (plan->P == P_)                          \
+    return launch_t<CFOG_CFG(P_, R1_, R2_, NT_, L_)>(job0, d_jobs, d_tasks, n_tasks, n_blocks, sp, st);
   CFOG_PLANS(CFOG_PLAN_CASE)
 #undef CFOG_PLAN_CASE
   return -1;

@@ -81,17 +81,12 @@ struct Slot {
 };
 
 // Upper bound of match_batch's workspace for one batch of at most max_cps
-// control points in max_jobs jobs: every template-spectrum bucket at its
-// largest, the job table and the task table.
+// control points in max_jobs jobs: the job table and the task table (the
+// server runs without channel splits).
 size_t match_ws_bound(int path, int num_cus, int max_cps, int max_jobs) {
+  (void)num_cus;
   if (path == CFOG_PATH_MFMA_BF16) return 0;
-  int n = 0;
-  const cfog::FftPlan* all = cfog::fft_plans(&n);
-  size_t tg = 0;
-  for (int i = 0; i < n; ++i)
-    if (all[i].tg_bytes)
-      tg += round_up((size_t)std::min(max_cps, cfog::plan_slots(&all[i], num_cus)) * all[i].tg_bytes, 256);
-  return tg + round_up(sizeof(cfog::MatchJob) * (size_t)max_jobs, 256) + sizeof(int2) * (size_t)max_cps + 256;
+  return round_up(sizeof(cfog::MatchJob) * (size_t)max_jobs, 256) + sizeof(int2) * (size_t)max_cps + 256;
 }
 
 bool supported(int path, int N, int r) {

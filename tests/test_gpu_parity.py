@@ -336,8 +336,8 @@ def test_channel_split_matches_unsplit(cf, N, r, H, n, seed):
     points by channel groups over several workgroups (the recommended
     workspace holds the partial surfaces); with no workspace the same points
     run whole.  Both agree with the FP64 oracle, and with each other up to
-    FP32 rounding of the channel sum.  (128, 32) takes a plan that parks the
-    template spectrum in global memory."""
+    FP32 rounding of the channel sum.  (128, 32) takes the P = 192 plan, whose
+    DC and Nyquist columns share one column job."""
     _say("channel split vs whole", N, r, H, n, seed)
     spec = synth.PairSpec(H, H, max(6, H // 6), (2.0, 12.0), 6, 3)
     A, B, _ = synth.make_pair(spec, (310, seed))

@@ -2,8 +2,8 @@
 nothing (its workspace is the library's static device array): on two calls
 in a row, the second with a smaller input, its results equal match_batch's on
 the same inputs bit for bit (plain FFT path with channel splits, a plain
-call whose FFT size parks the template spectrum in the workspace, and the
-MFMA path), and a sample of points agrees with the FP64 oracle.  Every case
+call at the largest FFT size, and the MFMA path), and a sample of points
+agrees with the FP64 oracle.  Every case
 prints its name before touching the GPU."""
 import numpy as np
 import pytest
@@ -49,7 +49,7 @@ def test_noalloc_equals_match_batch_on_two_calls(cf):
     assert cf.load().cfog_noalloc_scratch_bytes() == 48 << 20
     # first call: 300 points, N = 100, r = 20 (P = 144, split last round);
     # second call, smaller: 24 points, N = 48, r = 10 (P = 72); then a call
-    # with N = 128, r = 32 (P = 192: template spectra in the workspace) and
+    # with N = 128, r = 32 (P = 192, the largest FFT size) and
     # one on the MFMA path
     cases = [("plain", 512, 100, 20, 300, 1, cf.PATH_PLAIN_FFT), ("plain", 256, 48, 10, 24, 2, cf.PATH_PLAIN_FFT),
              ("plain", 320, 128, 32, 40, 3, cf.PATH_PLAIN_FFT), ("mfma", 256, 48, 10, 16, 4, cf.PATH_MFMA_BF16)]
