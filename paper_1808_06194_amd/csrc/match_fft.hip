@@ -741,9 +741,10 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
 //  workspace at 768 threads, whose round trip was most of their HBM traffic.
 //  Sizes that lost to the next larger one on every measured (N, r) are left
 //  out: P = 128 (T^ in registers, 256 VGPRs and spills: 25-35% slower than
-//  P = 144) and P = 180 (15 x 12, several hundred spilled registers at any
-//  workgroup size: twice the time of P = 192).  P = 150 (fused, 512 threads)
-//  is 4-5% faster than P = 160 where both fit.
+//  P = 144), P = 150 (15 x 10, fused, 512 threads, spills: 1-11% slower than
+//  P = 160 on the same windows since P = 160 keeps T^ in registers; its
+//  registers layout spills 161 VGPRs) and P = 180 (15 x 12, several hundred
+//  spilled registers at any workgroup size: twice the time of P = 192).
 #define CFOG_PLANS(X)                  \
   X(16, 4, 4, 64, LAY_REG)             \
   X(24, 6, 4, 128, LAY_REG)            \
@@ -760,7 +761,6 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
   X(108, 12, 9, 768, LAY_FUSED)        \
   X(120, 12, 10, 768, LAY_FUSED)       \
   X(144, 12, 12, 512, LAY_FUSED)       \
-  X(150, 15, 10, 512, LAY_FUSED)       \
   X(160, 16, 10, 512, LAY_REG)         \
   X(192, 16, 12, 512, LAY_REG)
 
