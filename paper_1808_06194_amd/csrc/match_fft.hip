@@ -21,8 +21,9 @@
 //   ACC(ky, kx) += conj(T^_c) * S^_c  in registers.  Per plan layout: the
 //           row spectra of T_c and S_c side by side in LDS, both x-passes in
 //           one phase and each y-pass column transforming S then T (fused);
-//           or T^_c parked in registers (or, for the largest P, in a global
-//           workspace) between the T and S passes of the channel;
+//           or T^_c parked in registers between the T and S passes of the
+//           channel (the DC and Nyquist columns, both real, as one complex
+//           column job where that saves a round);
 // then one inverse: column IFFTs (kept rows u_y < K) and a C2R row IFFT with
 // two output rows packed per complex FFT (kept columns u_x < K), the SSD
 // assembly in FP64, and a lexicographic argmin + second-best over (SSD, index).
@@ -545,8 +546,8 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
       }
     }
   };
-  // two-phase layout: T^ parked in registers (or global memory) between the
-  // template's and the window's passes; four barriers per channel
+  // two-phase layout: T^ parked in registers between the template's and the
+  // window's passes; four barriers per channel
   auto split_channels = [&]() {
     for (int c = c0; c < c1; ++c) {
       float2 th[KF][R2];
