@@ -850,3 +850,48 @@ def test_match_on_scheme1_volumes(cf):
         E1, E2 = O.energies(D1, D2, cp, N, r)
         parity.check_point(k, res, ora["surfaces"][k], E1, E2, r, surf_gpu=surf[k].cpu().numpy(), stats=stats)
     _say("scheme-1 parity", stats)
+
+
+@pytest.mark.parametrize("P,N,r", [(120, 80, 20), (144, 100, 20), (192, 128, 32)])
+def test_match_volumes_with_nyquist_content(cf, P, N, r):
+    """The x-pass half-spectra's DC and Nyquist columns are real; the P = 120
+    and 192 plans transform them as one complex column and separate the two
+    products (a third plan is the unpacked control).  Volumes given directly
+    to the matcher with a strong DC offset and +-1 patterns along x, y and
+    both (their energy sits at and next to the Nyquist bins), against the
+    FP64 oracle's direct SSD of Eq. 3 on the same volumes.  On these volumes
+    a surface that lost the Nyquist column's share would be off by about
+    0.17 (E1 + E2), the DC column's 0.8: three orders of magnitude past the
+    tolerance (computed with numpy's FFT on the host)."""
+    _say("match volumes with Nyquist content", P, N, r)
+    rng = np.random.default_rng(P)
+    H = W = N + 2 * r + 48
+    m = 9
+    yy, xx = np.mgrid[0:H, 0:W]
+    alt_x, alt_y, alt_xy = (-1.0) ** xx, (-1.0) ** yy, (-1.0) ** (xx + yy)
+    D = np.empty((m, H, W))
+    for c in range(m):
+        a = rng.uniform(0.2, 0.6, 3)
+        D[c] = 1.0 + a[0] * alt_x + a[1] * alt_y + a[2] * alt_xy + 0.3 * rng.random((H, W))
+    DA = D.astype(np.float32)
+    DB = (np.roll(D, (2, -3), (1, 2)) + 0.05 * rng.random((m, H, W))).astype(np.float32)
+    satA = O.sat(np.sum(DA.astype(np.float64) ** 2, axis=0))
+    satB = O.sat(np.sum(DB.astype(np.float64) ** 2, axis=0))
+    cps = synth.random_cps(rng, H, W, N, r, 3)
+    cf.set_plan(N, r, P)
+    try:
+        assert cf.plan_for(N, r) == P
+        K = 2 * r + 1
+        surf = torch.full((len(cps), K, K), float("nan"), device="cuda")
+        job = cf.Job(_dev(DA), _dev(satA), _dev(DB), _dev(satB), _dev(cps.astype(np.int32)), N, r, surfaces=surf)
+        cf.match_batch([job], m=m)
+        torch.cuda.synchronize()
+        res = {k: v.cpu().numpy() for k, v in cf.results(job.out).items()}
+        surf_np = surf.cpu().numpy()
+    finally:
+        cf.set_plan(N, r, 0)
+    D1, D2 = DA.astype(np.float64), DB.astype(np.float64)
+    for k, cp in enumerate(cps):
+        S = O.ssd_surface_direct(D1, D2, tuple(int(v) for v in cp), N, r)
+        E1, E2 = O.energies(D1, D2, tuple(int(v) for v in cp), N, r)
+        parity.check_point(k, res, S, E1, E2, r, surf_np[k])
