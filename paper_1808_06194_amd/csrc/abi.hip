@@ -17,6 +17,7 @@
 #include "cfog.h"
 #include "kernels.hpp"
 #include "split_plan.hpp"
+#include "trace.hpp"
 
 namespace {
 
@@ -522,6 +523,7 @@ static int context_extract_ws(cfog_ctx* ctx, size_t need, void** ws) {
 int cfog_extract_scheme(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride, int32_t m,
                         float sigma, int32_t gauss_radius, int32_t scheme, float* d_vol, double* d_sat, void* d_ws,
                         size_t ws_bytes, void* stream) {
+  cfog::TraceRange trace("cfog_extract");
   if (!ctx || !d_img || !d_vol || (scheme != 1 && scheme != 2)) return CFOG_EINVAL;
   if (H < 1 || W < 1 || row_stride < W || m < 1 || m > cfog::kMaxOrient) return CFOG_EINVAL;
   if (!(sigma > 0.f) || !isfinite(sigma)) return CFOG_EINVAL;
@@ -567,6 +569,7 @@ size_t cfog_extract_batch_workspace_size(const cfog_image* imgs, int32_t n) {
 
 int cfog_extract_batch(cfog_ctx* ctx, const cfog_image* imgs, int32_t n, int32_t m, float sigma,
                        int32_t gauss_radius, int32_t scheme, void* d_ws, size_t ws_bytes, void* stream) {
+  cfog::TraceRange trace("cfog_extract_batch");
   if (!ctx || n < 0 || (n > 0 && !imgs) || (scheme != 1 && scheme != 2)) return CFOG_EINVAL;
   if (m < 1 || m > cfog::kMaxOrient || !(sigma > 0.f) || !isfinite(sigma)) return CFOG_EINVAL;
   if (n == 0) return CFOG_OK;
@@ -594,6 +597,7 @@ int cfog_extract_batch(cfog_ctx* ctx, const cfog_image* imgs, int32_t n, int32_t
 
 int cfog_extract_fhog(cfog_ctx* ctx, const float* d_img, int32_t H, int32_t W, int64_t row_stride, int32_t cell,
                       float* d_vol, double* d_sat, void* d_ws, size_t ws_bytes, void* stream) {
+  cfog::TraceRange trace("cfog_extract_fhog");
   if (!ctx || !d_img || !d_vol || H < 1 || W < 1 || row_stride < W || cell < 1) return CFOG_EINVAL;
   if (cell > 8) return CFOG_EUNSUPPORTED;
   if (!aligned(d_sat, 8) || !aligned(d_ws, 8)) return CFOG_EINVAL;
@@ -637,8 +641,10 @@ size_t match_batch_workspace_size(cfog_ctx* ctx, const cfog_job* jobs, int32_t n
   return ws_need(ctx, jobs, n_jobs, m, flags, !(flags & CFOG_NO_SPLIT));
 }
 
-int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags, void* d_ws,
-                size_t ws_bytes, void* stream) {
+// match_batch without its trace range (match_batch_noalloc calls it too, and
+// calls nothing that may allocate)
+static int match_batch_run(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags,
+                           void* d_ws, size_t ws_bytes, void* stream) {
   if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return CFOG_EINVAL;
   const int path = flags & CFOG_PATH_MASK;
   if (flags & ~(CFOG_PATH_MASK | CFOG_AUTOTUNE | CFOG_USE_GRAPH | CFOG_OBJ_CORR | CFOG_NO_SPLIT)) return CFOG_EINVAL;
@@ -758,6 +764,12 @@ int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, 
   return CFOG_OK;
 }
 
+int match_batch(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags, void* d_ws,
+                size_t ws_bytes, void* stream) {
+  cfog::TraceRange trace("match_batch");
+  return match_batch_run(ctx, jobs, n_jobs, m, flags, d_ws, ws_bytes, stream);
+}
+
 size_t cfog_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
 
 int match_batch_noalloc(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int32_t m, int32_t flags,
@@ -774,7 +786,7 @@ int match_batch_noalloc(cfog_ctx* ctx, const cfog_job* jobs, int32_t n_jobs, int
   if (need > kNoallocScratchBytes) return CFOG_ENOMEM;
   // the channel splits are taken where their partials also fit, exactly as
   // match_batch does with a workspace of this size
-  return match_batch(ctx, jobs, n_jobs, m, flags, ctx->scratch, kNoallocScratchBytes, stream);
+  return match_batch_run(ctx, jobs, n_jobs, m, flags, ctx->scratch, kNoallocScratchBytes, stream);
 }
 
 }  // extern "C"

@@ -30,6 +30,7 @@
 #include "cfog.h"
 #include "kernels.hpp"
 #include "sched.hpp"
+#include "trace.hpp"
 #include "window.hpp"
 
 namespace {
@@ -434,6 +435,7 @@ int cfog_server_destroy(cfog_server* s) {
 
 int cfog_server_add_pair(cfog_server* s, const float* d_imgA, int32_t hA, int32_t wA, int64_t strideA,
                          const float* d_imgB, int32_t hB, int32_t wB, int64_t strideB, int32_t* pair_id) {
+  cfog::TraceRange trace("cfog_server_add_pair");
   if (!s || !d_imgA || !d_imgB || !pair_id || hA < 1 || wA < 1 || hB < 1 || wB < 1 || strideA < wA ||
       strideB < wB)
     return CFOG_EINVAL;
@@ -468,6 +470,7 @@ int cfog_server_add_pair(cfog_server* s, const float* d_imgA, int32_t hA, int32_
 
 int cfog_server_submit(cfog_server* s, int32_t pair_id, const cfog_cp* h_cps, int32_t n_cps, int32_t N, int32_t r,
                        cfog_result* h_out, float* h_surfaces, int64_t* req_id) {
+  cfog::TraceRange trace("cfog_server_submit");
   if (!s || !req_id || n_cps < 1 || !h_cps || !h_out || N < 1 || r < 0) return CFOG_EINVAL;
   if (!supported(s->cfg.flags & CFOG_PATH_MASK, N, r)) return CFOG_EUNSUPPORTED;
   const size_t K = 2 * (size_t)r + 1;
