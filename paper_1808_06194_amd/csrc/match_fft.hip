@@ -245,10 +245,23 @@ __device__ __forceinline__ void xpass_stage2(const Lane<C>& L, float2* base, int
     // lane R1-k1 of the group (k1 > 0), or this lane's register (R2-k2) mod R2 (k1 = 0).
     const int lane = threadIdx.x & 63;
     const int msrc = lane - L.li + (k1 == 0 ? 0 : R1 - k1);
+    // the value of lane R1 - k1 of the group: where the group is a DPP row
+    // (R1 = 16) or half row (R1 = 8), a mirror within it and a shift by one
+    // lane (lane i then holds lane R1 - i's value; lane 0's is not used), on
+    // the vector units; otherwise an LDS permute
+    auto from_mirror = [&](float x) -> float {
+      if constexpr (C::G == R1 && (R1 == 16 || R1 == 8)) {
+        constexpr int MIRROR = R1 == 16 ? 0x140 : 0x141;  // row_mirror, row_half_mirror
+        const int t = __builtin_amdgcn_update_dpp(0, __float_as_int(x), MIRROR, 0xf, 0xf, false);
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, t, 0x111, 0xf, 0xf, false));  // row_shr:1
+      } else {
+        return __shfl(x, msrc, 64);
+      }
+    };
     const bool odd_pad = (2 * q + 1) >= nrows;  // second row of the pair is padding
     static_for<0, R2>([&](auto k2I) {
       constexpr int k2 = decltype(k2I)::value;
-      const float2 far = make_float2(__shfl(v[R2 - 1 - k2].x, msrc, 64), __shfl(v[R2 - 1 - k2].y, msrc, 64));
+      const float2 far = make_float2(from_mirror(v[R2 - 1 - k2].x), from_mirror(v[R2 - 1 - k2].y));
       const float2 zm = (k1 == 0) ? v[(R2 - k2) % R2] : far;
       const int k = k1 + R1 * k2;
       if (L.li < R1 && k <= P / 2) {
