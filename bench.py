@@ -670,6 +670,18 @@ def main():
                                                           for a, b in zip(res_s, res_o)))
         out["parity"] = blocks
 
+    if not args.calib_copy_mib:  # (a counter run keeps its one calibration copy)
+        # the counter-measured traffic of each call against the peak and
+        # against what a plain copy reaches on this GPU
+        probe = hbm_probe(dev)
+        out["hbm_probe"] = probe
+        for key, t_call in (("roofline", t_match), ("roofline_extract", t_ext)):
+            tr = out[key].get("traffic")
+            if tr:
+                g = tr / t_call / 1e9
+                out[key].update(traffic_gbs=round(g, 1), traffic_frac_peak=round(g / HBM_PEAK_GBS, 4),
+                                traffic_frac_copy_probe=round(g / probe["copy_gbs"], 4))
+
     if args.calib_copy_mib:
         # source written first, then 1 GiB of other writes so that the copy's
         # reads come from HBM rather than the last-level cache
@@ -684,6 +696,36 @@ def main():
         out["calib_copy_bytes"] = nb
         del junk
     print(json.dumps(out), flush=True)
+
+
+def hbm_probe(dev, mib: int = 1024, reps: int = 10) -> dict:
+    """Achievable HBM bandwidth on this GPU, as context for the counter-measured
+    traffic: a plain device-to-device copy (bytes read + written) and a fill
+    (bytes written) of a `mib` MiB buffer, four times the last-level cache,
+    timed with HIP events after the timed steps.  Measurement only: nothing
+    on the path uses it."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev[1].record()
+    for _ in range(reps):
+        dst.fill_(1.0)
+    ev[2].record()
+    torch.cuda.synchronize()
+    t_copy = ev[0].elapsed_time(ev[1]) / reps * 1e-3
+    t_fill = ev[1].elapsed_time(ev[2]) / reps * 1e-3
+    nb = n * 4
+    del src, dst
+    return dict(copy_gbs=round(2 * nb / t_copy / 1e9, 1), fill_gbs=round(nb / t_fill / 1e9, 1), bytes=nb,
+                kernel=f"torch copy_ and fill_ of a {mib} MiB fp32 buffer (the copy counts bytes read + written)")
 
 
 def harris_flops_per_px(R: int = 4) -> int:
