@@ -96,15 +96,17 @@ def extract_bytes_per_px(m: int = 9) -> int:
 #
 # The oracle (FP64, test infrastructure) is timed on the host cores on a
 # bounded sample of the workload's control points, in forked worker processes
-# started before anything touches the GPU.  The same oracle outputs then judge
-# the GPU's results for those points (the parity block of the JSON line).
+# started before anything touches the GPU.  The same oracle outputs are then
+# the reference for the GPU's results on those points (the parity block of the
+# JSON line).
 
 CFOG_R = 3  # Gaussian radius at sigma = 0.8: int(4 sigma + 0.5)
 PAPER_CFOG_MPX_S = 512 * 512 / 0.210 / 1e6  # Table III: 0.210 s per 512^2 image on an i7-4710MQ
 
 
 def cpu_workers() -> int:
-    """Host cores this process may use (the GPU machine grants 16 per GPU)."""
+    """Host cores this process may use: its CPU affinity, at most 16 (one
+    GPU's share of the host)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -307,7 +309,7 @@ def parity_block(sample, outs, results, surfaces, pairs, tol: float, plan_of=Non
                mismatch_rate=round(mismatched / max(1, n), 4),
                max_norm_ssd_err=float(f"{worst:.3e}"), max_rel_ssd_err=float(f"{rel_max:.3e}"),
                tol_norm=float(f"{tol:.4e}"), oracle_fft_vs_direct=float(f"{fft_vs_direct:.2e}"),
-               judge="oracle direct SSD (Eq. 3) in FP64 on the sampled points; normalised error "
+               reference="oracle direct SSD (Eq. 3) in FP64 on the sampled points; normalised error "
                      "|S_gpu - S_ora| / (E1 + E2(d))")
     if buckets:
         out["points_per_fft_size"] = {str(k): v for k, v in sorted(buckets.items())}
