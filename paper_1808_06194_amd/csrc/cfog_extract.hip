@@ -219,7 +219,9 @@ __global__ __launch_bounds__(EX_NT) __attribute__((amdgpu_waves_per_eu(M > 0 ? 8
   for (int j = 0; j <= R; ++j) w[j] = a.w[j];
 
   // A. image tile, rows y0-R-1 .. y0+TY+R, clamped; all loads issued before
-  // the LDS stores so their latencies overlap
+  // the LDS stores so their latencies overlap.  Ordinary (cached) loads: the
+  // tile below is dispatched to the same XCD whenever the tile grid is a
+  // multiple of 8 tiles wide, and reads these halo rows again from its L2.
   {
     constexpr int NIT = (IH * IW + EX_NT - 1) / EX_NT;
     float v[NIT];
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(EX_NT) __attribute__((amdgpu_waves_per_eu(M > 0 ? 8
       if (i < IH * IW) {
         const int r = i / IW, c = i - r * IW;
         const int gy = clampi(y0 - R - 1 + r, 0, H - 1), gx = clampi(x0 - R - 1 + c, 0, W - 1);
-        v[it] = __builtin_nontemporal_load(I.img + (int64_t)gy * I.stride + gx);
+        v[it] = I.img[(int64_t)gy * I.stride + gx];
       }
     }
 #pragma unroll
