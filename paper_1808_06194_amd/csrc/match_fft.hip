@@ -202,10 +202,9 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const XRows (&S)[NS]
       v[a] = make_float2(re, im);
     }
   };
-  // each pair is loaded just before its transform: the plans that use this
-  // pass (P <= 108 and the global-layout sizes) lost by fetching the next
-  // pair ahead (P = 100 at 768 threads; P = 160 and 192, whose registers
-  // spill, by 1%), unlike the fused pass of the larger plans
+  // each pair is loaded just before its transform: fetching the next pair
+  // ahead lost on the plans that use this pass (P = 160 and 192, whose
+  // registers spill, by 1%), unlike the fused pass of P = 80-144
   for (int i = L.g; i < total; i += C::NG) {
     int s, q;
     which(i, s, q);
