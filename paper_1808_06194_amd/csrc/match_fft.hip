@@ -203,8 +203,9 @@ __device__ __forceinline__ void xpass_fwd(const Lane<C>& L, const XRows (&S)[NS]
     }
   };
   // each pair is loaded just before its transform: fetching the next pair
-  // ahead lost on the plans that use this pass (P = 160 and 192, whose
-  // registers spill, by 1%), unlike the fused pass of P = 80-144
+  // ahead lost on the plans that use this pass (P = 100 at 768 threads;
+  // P = 160 and 192, whose registers spill, by 1%), unlike the prefetching
+  // fused pass of P = 144
   for (int i = L.g; i < total; i += C::NG) {
     int s, q;
     which(i, s, q);
@@ -535,9 +536,11 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   // rows into X), then one y-pass phase; two barriers per channel
   auto fused_channels = [&]() {
     float2* XT = reinterpret_cast<float2*>(reinterpret_cast<char*>(X) + C::BASE);
-    if constexpr (C::P >= 120) {
-      // the large plans load the next channel's first template pair during
-      // this channel's y-pass (measured: 1.4% at P = 144, 3.6% at P = 120)
+    if constexpr (C::P >= 144) {
+      // P = 144 loads the next channel's first template pair during this
+      // channel's y-pass (measured: 1.4%).  At P = 120 (768 threads, 168
+      // VGPRs) the pair held through the y-pass raised the spills from 6 to
+      // 26 VGPRs and made the plan 7% slower.
       float2 vn[R1];
       xpass_fused_preload<C>(L, XRows{tA + c0 * planeA, jd.wA, N, N, XT, false}, vn);
       for (int c = c0; c < c1; ++c) {
