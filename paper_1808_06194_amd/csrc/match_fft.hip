@@ -747,14 +747,17 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
 // ------------------------------------------------------------------ plans
 //  P, R1, R2, NT, layout  (R1 >= R2 keeps the per-lane outputs of stage 2
 //  small).  NT is set per size from measurement: as many waves as the
-//  registers allow without starving the column rounds (P = 96..108 at 768
-//  threads take every column in one round; P = 144 at 512 threads beats
-//  256-384 threads; P = 120 gains 3% from 768 threads over 512 despite its
-//  register spilling).  The layout too: the fused one was 6-18% faster than
-//  parking T^ in registers for P = 80..144.  P = 160 and 192 park T^ in
-//  registers at 512 threads, where P = 192's DC/Nyquist packing leaves three
-//  whole column rounds: 10% and 18% faster than parking it in a global
-//  workspace at 768 threads, whose round trip was most of their HBM traffic.
+//  registers allow, in workgroups that fill a CU's wave slots (P = 60 and
+//  64 at 512 threads: 16 waves per CU where 384 and 320 threads left 12
+//  and 15, 10% and 15% faster; P = 80-120 at 768 threads, three waves per
+//  SIMD: P = 80 and 90 6% and 5% faster than at 448 and 512, P = 96..108
+//  take every column in one round, P = 120 is 19% faster than at 512;
+//  P = 144 at 512 threads beats 256-384 and 768).  The layout too: the
+//  fused one was 6-18% faster than parking T^ in registers for P = 80..144.
+//  P = 160 and 192 park T^ in registers at 512 threads, where P = 192's
+//  DC/Nyquist packing leaves three whole column rounds: 10% and 18% faster
+//  than parking it in a global workspace at 768 threads, whose round trip
+//  was most of their HBM traffic.
 //  Sizes that lost to the next larger one on every measured (N, r) are left
 //  out: P = 128 (T^ in registers, 256 VGPRs and spills: 25-35% slower than
 //  P = 144), P = 150 (15 x 10, fused, 512 threads, spills: 1-11% slower than
@@ -767,11 +770,11 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
   X(32, 8, 4, 192, LAY_REG)            \
   X(40, 8, 5, 192, LAY_REG)            \
   X(48, 8, 6, 256, LAY_REG)            \
-  X(60, 10, 6, 384, LAY_REG)           \
-  X(64, 8, 8, 320, LAY_REG)            \
+  X(60, 10, 6, 512, LAY_REG)           \
+  X(64, 8, 8, 512, LAY_REG)            \
   X(72, 9, 8, 384, LAY_REG)            \
-  X(80, 10, 8, 448, LAY_FUSED)         \
-  X(90, 10, 9, 512, LAY_FUSED)         \
+  X(80, 10, 8, 768, LAY_FUSED)         \
+  X(90, 10, 9, 768, LAY_FUSED)         \
   X(96, 12, 8, 768, LAY_FUSED)         \
   X(100, 10, 10, 768, LAY_FUSED)       \
   X(108, 12, 9, 768, LAY_FUSED)        \
