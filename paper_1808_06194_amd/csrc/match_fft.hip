@@ -100,12 +100,6 @@ struct FftCfg {
   static constexpr int XT_ROWS = FUSE ? (int)(XT_FIT < (size_t)P ? XT_FIT : (size_t)P) : 0;
   static constexpr int T_ROWS = FUSE ? XT_ROWS : P;  // template rows the plan takes
   static constexpr size_t LDS = BASE + sizeof(float2) * (size_t)XT_ROWS * PH;
-  // The separated row spectra are 2 A and 2 B (the exact factor 4 of their
-  // product goes into the inverse's normalisation), except at P = 192, whose
-  // spills the register allocator places better with the halving done in
-  // the separation (measured: 11% faster; at P = 160 it was 18% slower).
-  // Both give the same values: scaling by a power of two is exact.
-  static constexpr bool SEP_HALF = P == 192;
 };
 
 // Lane identity within the FFT group layout.
@@ -266,9 +260,8 @@ __device__ __forceinline__ void xpass_stage2(const Lane<C>& L, float2* base, int
       const int k = k1 + R1 * k2;
       if (L.li < R1 && k <= P / 2) {
         const float2 z = v[k2];
-        constexpr float h = C::SEP_HALF ? 0.5f : 1.0f;
-        base[k] = make_float2(h * (z.x + zm.x), h * (z.y - zm.y));
-        base[PH + k] = odd_pad ? make_float2(0.f, 0.f) : make_float2(h * (z.y + zm.y), h * (zm.x - z.x));
+        base[k] = make_float2(z.x + zm.x, z.y - zm.y);
+        base[PH + k] = odd_pad ? make_float2(0.f, 0.f) : make_float2(z.y + zm.y, zm.x - z.x);
       }
     });
     wave_sync();
@@ -652,7 +645,7 @@ __device__ __forceinline__ void match_one(const Lane<C>& L, const MatchJob& jd, 
   const int npair = (K + 1) >> 1;
   float* Cs = reinterpret_cast<float*>(X + 2 * npair * PH);
   // 1/P^2 of the inverse 2-D DFT and 1/4 for the doubled row spectra of T and S
-  const float inv = (C::SEP_HALF ? 1.0f : 0.25f) / ((float)P * (float)P);
+  const float inv = 0.25f / ((float)P * (float)P);
   for (int p = L.g; p < npair; p += C::NG) {
     float2* sc = X + 2 * opaque(p) * PH;
     float2 v[R1];
