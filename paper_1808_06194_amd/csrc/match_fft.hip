@@ -740,9 +740,10 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
 // ------------------------------------------------------------------ plans
 //  P, R1, R2, NT, layout  (R1 >= R2 keeps the per-lane outputs of stage 2
 //  small).  NT is set per size from measurement: as many waves as the
-//  registers allow, in workgroups that fill a CU's wave slots (P = 60 and
-//  64 at 512 threads: 16 waves per CU where 384 and 320 threads left 12
-//  and 15, 10% and 15% faster; P = 80-120 at 768 threads, three waves per
+//  registers allow, in workgroups that fill a CU's wave slots (P = 32 and
+//  40 at 256 threads instead of 192, 2% faster; P = 60 and 64 at 512
+//  threads: 16 waves per CU where 384 and 320 threads left 12 and 15, 10%
+//  and 15% faster; P = 80-120 at 768 threads, three waves per
 //  SIMD: P = 80 and 90 6% and 5% faster than at 448 and 512, P = 96..108
 //  take every column in one round, P = 120 is 19% faster than at 512;
 //  P = 144 at 512 threads beats 256-384 and 768).  The layout too: the
@@ -760,8 +761,8 @@ __global__ __launch_bounds__(C::NT) void match_fft_kernel(MatchJob job0, const M
 #define CFOG_PLANS(X)                  \
   X(16, 4, 4, 64, LAY_REG)             \
   X(24, 6, 4, 128, LAY_REG)            \
-  X(32, 8, 4, 192, LAY_REG)            \
-  X(40, 8, 5, 192, LAY_REG)            \
+  X(32, 8, 4, 256, LAY_REG)            \
+  X(40, 8, 5, 256, LAY_REG)            \
   X(48, 8, 6, 256, LAY_REG)            \
   X(60, 10, 6, 512, LAY_REG)           \
   X(64, 8, 8, 512, LAY_REG)            \
